@@ -1,0 +1,985 @@
+/* FP64 CPU oracle for the hybrid surface-volumetric marcher.
+ *
+ * TEST INFRASTRUCTURE ONLY -- see oracle.h.  Plain loops in double precision,
+ * brute force over every triangle, one sample at a time.
+ *
+ * Paper: "Dynamic Mesh-Aware Radiance Fields" (Qiao, Gao et al., ICCV 2023).
+ *   Sec. 3.1 "Surface Rendering Equation", Eq. 1-4: surface transport, the
+ *       ray-casting function t(p, w) and the path throughput recursion.
+ *   Sec. 3.1 "Volumetric Rendering Equation", Eq. 8-9: emission-absorption
+ *       volume rendering with transmittance T(t) = exp(-int sigma).
+ *   Sec. 3.1 "Unifying color space": the field emits linear HDR radiance.
+ *   Sec. 3.1 "Shadow rays" and "Hybrid Rendering Algorithm", Eq. 10-13 and
+ *       Algorithm 1: per-segment march, then BSDF sampling at the surface hit,
+ *       termination on escape / low throughput / bounce limit.
+ * The radiance field itself is an Instant-NGP hash grid + small MLPs (Sec. 3.3);
+ * its definition follows Mueller et al. 2022 (multiresolution hash encoding).
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11). */
+/* The paper only says rays are "randomly cast" (Sec. 3.1, surface LTE); the  */
+/* generator is keyed by the seed and counted by (ray id, segment, purpose). */
+/* ------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static double u01(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
+
+enum { RNG_GLASS = 0, RNG_DIFFUSE = 1, RNG_RR = 2 };
+
+static void draw(uint32_t seed, int64_t ray, int seg, int purpose, double u[4]) {
+  uint32_t ctr[4] = {(uint32_t)ray, (uint32_t)seg, (uint32_t)purpose, 0u};
+  uint32_t key[2] = {seed, 0u};
+  uint32_t o[4];
+  orc_philox4x32_10(ctr, key, o);
+  for (int i = 0; i < 4; ++i) u[i] = u01(o[i]);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Multiresolution hash encoding (Instant-NGP field of Sec. 3.3).            */
+/* Level l has grid resolution N_l; a vertex v in {0..N_l}^3 is stored at    */
+/* the dense index vx + vy(N+1) + vz(N+1)^2 when (N+1)^3 <= T, otherwise at  */
+/* the spatial hash (vx*1 ^ vy*2654435761 ^ vz*805459861) mod T (uint32).     */
+/* ------------------------------------------------------------------------- */
+int orc_hash_index(int32_t res, int32_t log2_table, const int64_t v[3], uint32_t* idx) {
+  int64_t T = (int64_t)1 << log2_table;
+  int64_t n1 = (int64_t)res + 1;
+  if (n1 * n1 * n1 <= T) {
+    *idx = (uint32_t)(v[0] + v[1] * n1 + v[2] * n1 * n1);
+    return 1;
+  }
+  uint32_t h = (uint32_t)v[0] ^ ((uint32_t)v[1] * 2654435761u) ^ ((uint32_t)v[2] * 805459861u);
+  *idx = h & (uint32_t)(T - 1);
+  return 0;
+}
+
+/* xhat in [0,1]^3 (clamped); features level-major, trilinear over 8 corners. */
+void orc_hash_encode(const orc_field* f, const double xhat_in[3], double* feat) {
+  int64_t T = (int64_t)1 << f->log2_table;
+  double xhat[3];
+  for (int k = 0; k < 3; ++k) xhat[k] = fmin(fmax(xhat_in[k], 0.0), 1.0);
+  for (int l = 0; l < f->n_levels; ++l) {
+    int32_t N = f->res[l];
+    int64_t v0[3];
+    double w[3];
+    for (int k = 0; k < 3; ++k) {
+      double xl = xhat[k] * (double)N;
+      double fl = floor(xl);
+      if (fl > (double)(N - 1)) fl = (double)(N - 1);
+      v0[k] = (int64_t)fl;
+      w[k] = xl - fl;
+    }
+    for (int c = 0; c < f->feats; ++c) feat[l * f->feats + c] = 0.0;
+    for (int corner = 0; corner < 8; ++corner) {
+      int64_t v[3];
+      double wt = 1.0;
+      for (int k = 0; k < 3; ++k) {
+        int bit = (corner >> k) & 1;
+        v[k] = v0[k] + bit;
+        wt *= bit ? w[k] : (1.0 - w[k]);
+      }
+      uint32_t idx;
+      orc_hash_index(N, f->log2_table, v, &idx);
+      const float* e = f->table + ((int64_t)l * T + idx) * f->feats;
+      for (int c = 0; c < f->feats; ++c) feat[l * f->feats + c] += wt * (double)e[c];
+    }
+  }
+}
+
+/* Real spherical harmonics, orthonormal, degrees l <= 3 (n = 1, 4, 9 or 16
+ * components), in Sloan's "Efficient Spherical Harmonic Evaluation" ordering. */
+void orc_sh(int32_t n, const double d[3], double* o) {
+  double x = d[0], y = d[1], z = d[2];
+  double xx = x * x, yy = y * y, zz = z * z;
+  o[0] = 0.28209479177387814;
+  if (n <= 1) return;
+  o[1] = -0.48860251190291987 * y;
+  o[2] = 0.48860251190291987 * z;
+  o[3] = -0.48860251190291987 * x;
+  if (n <= 4) return;
+  o[4] = 1.0925484305920792 * x * y;
+  o[5] = -1.0925484305920792 * y * z;
+  o[6] = 0.31539156525252005 * (3.0 * zz - 1.0);
+  o[7] = -1.0925484305920792 * x * z;
+  o[8] = 0.54627421529603959 * (xx - yy);
+  if (n <= 9) return;
+  o[9] = -0.59004358992664352 * y * (3.0 * xx - yy);
+  o[10] = 2.8906114426405538 * x * y * z;
+  o[11] = -0.45704579946446572 * y * (5.0 * zz - 1.0);
+  o[12] = 0.3731763325901154 * z * (5.0 * zz - 3.0);
+  o[13] = -0.45704579946446572 * x * (5.0 * zz - 1.0);
+  o[14] = 1.4453057213202769 * z * (xx - yy);
+  o[15] = -0.59004358992664352 * x * (xx - 3.0 * yy);
+}
+
+static double softplus(double x) { return fmax(x, 0.0) + log1p(exp(-fabs(x))); }
+
+/* y[out] = W[out][in] x[in] */
+static void matvec(const float* W, int out, int in, const double* x, double* y) {
+  for (int i = 0; i < out; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < in; ++j) s += (double)W[(int64_t)i * in + j] * x[j];
+    y[i] = s;
+  }
+}
+
+static void relu(double* x, int n) {
+  for (int i = 0; i < n; ++i) x[i] = x[i] > 0.0 ? x[i] : 0.0;
+}
+
+#define MAXW 256
+
+/* The radiance field: density sigma = softplus(raw0 + offset) from the density
+ * MLP on the hash features; colour = exp(colour MLP(raw ++ SH(d))), linear HDR
+ * radiance (Sec. 3.1 "Unifying color space"). */
+void orc_field_eval(const orc_field* f, const double p[3], const double d[3], double* sigma,
+                    double rgb[3], double* raw_out) {
+  double xhat[3], feat[MAXW], h[MAXW], raw[MAXW] = {0}, cin[MAXW], h2[MAXW], out[4];
+  for (int k = 0; k < 3; ++k) xhat[k] = (p[k] - f->aabb_min[k]) / (f->aabb_max[k] - f->aabb_min[k]);
+  int nfeat = f->n_levels * f->feats;
+  for (int i = 0; i < f->d_in; ++i) feat[i] = 0.0;
+  orc_hash_encode(f, xhat, feat);
+  (void)nfeat;
+  const float* w = f->mlp;
+  matvec(w, f->d_hidden, f->d_in, feat, h);
+  w += (int64_t)f->d_hidden * f->d_in;
+  relu(h, f->d_hidden);
+  matvec(w, f->d_out, f->d_hidden, h, raw);
+  w += (int64_t)f->d_out * f->d_hidden;
+  *sigma = softplus(raw[0] + f->density_offset);
+  if (raw_out)
+    for (int i = 0; i < f->d_out; ++i) raw_out[i] = raw[i];
+  if (f->c_layers <= 0 || !rgb) return;
+  for (int i = 0; i < f->c_in; ++i) cin[i] = 0.0;
+  for (int i = 0; i < f->d_out; ++i) cin[i] = raw[i];
+  orc_sh(f->sh, d, cin + f->d_out);
+  matvec(w, f->c_hidden, f->c_in, cin, h);
+  w += (int64_t)f->c_hidden * f->c_in;
+  relu(h, f->c_hidden);
+  for (int layer = 1; layer < f->c_layers; ++layer) {
+    matvec(w, f->c_hidden, f->c_hidden, h, h2);
+    w += (int64_t)f->c_hidden * f->c_hidden;
+    relu(h2, f->c_hidden);
+    memcpy(h, h2, sizeof(double) * f->c_hidden);
+  }
+  matvec(w, 3, f->c_hidden, h, out);
+  for (int c = 0; c < 3; ++c) rgb[c] = exp(out[c]);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Ray casting t(p, w) (Eq. 3): watertight ray-triangle test of Woop, Benthin */
+/* and Wald (JCGT 2013), here in double precision, no back-face culling.     */
+/* Returns 1 on a hit with t > 0; bary = (U, V, W)/det (weights of v0,v1,v2). */
+/* ------------------------------------------------------------------------- */
+static void sub3(const double a[3], const double b[3], double r[3]) {
+  r[0] = a[0] - b[0]; r[1] = a[1] - b[1]; r[2] = a[2] - b[2];
+}
+static double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+static void cross3(const double a[3], const double b[3], double r[3]) {
+  r[0] = a[1] * b[2] - a[2] * b[1];
+  r[1] = a[2] * b[0] - a[0] * b[2];
+  r[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+typedef struct { int kx, ky, kz; double Sx, Sy, Sz; } shear_t;
+
+static shear_t make_shear(const double d[3]) {
+  shear_t s;
+  double ax = fabs(d[0]), ay = fabs(d[1]), az = fabs(d[2]);
+  s.kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+  s.kx = (s.kz + 1) % 3;
+  s.ky = (s.kx + 1) % 3;
+  if (d[s.kz] < 0.0) { int t = s.kx; s.kx = s.ky; s.ky = t; }
+  s.Sx = d[s.kx] / d[s.kz];
+  s.Sy = d[s.ky] / d[s.kz];
+  s.Sz = 1.0 / d[s.kz];
+  return s;
+}
+
+/* Edge functions of the sheared triangle; returns det, fills U,V,W and t. */
+static double tri_edges(const shear_t* s, const double o[3], const double v0[3],
+                        const double v1[3], const double v2[3], double uvw[3], double* t) {
+  double A[3], B[3], C[3];
+  sub3(v0, o, A); sub3(v1, o, B); sub3(v2, o, C);
+  double Ax = A[s->kx] - s->Sx * A[s->kz], Ay = A[s->ky] - s->Sy * A[s->kz];
+  double Bx = B[s->kx] - s->Sx * B[s->kz], By = B[s->ky] - s->Sy * B[s->kz];
+  double Cx = C[s->kx] - s->Sx * C[s->kz], Cy = C[s->ky] - s->Sy * C[s->kz];
+  double U = Cx * By - Cy * Bx;
+  double V = Ax * Cy - Ay * Cx;
+  double W = Bx * Ay - By * Ax;
+  double det = U + V + W;
+  uvw[0] = U; uvw[1] = V; uvw[2] = W;
+  if (det != 0.0) {
+    double T = U * (s->Sz * A[s->kz]) + V * (s->Sz * B[s->kz]) + W * (s->Sz * C[s->kz]);
+    *t = T / det;
+  } else {
+    *t = INFINITY;
+  }
+  return det;
+}
+
+int orc_intersect(const double o[3], const double d[3], const double v0[3], const double v1[3],
+                  const double v2[3], double* t, double bary[3]) {
+  shear_t s = make_shear(d);
+  double uvw[3];
+  double det = tri_edges(&s, o, v0, v1, v2, uvw, t);
+  if ((uvw[0] < 0 || uvw[1] < 0 || uvw[2] < 0) && (uvw[0] > 0 || uvw[1] > 0 || uvw[2] > 0))
+    return 0;
+  if (det == 0.0) return 0;
+  if (!(*t > 0.0)) return 0;
+  for (int k = 0; k < 3; ++k) bary[k] = uvw[k] / det;
+  return 1;
+}
+
+static void tri_verts(const orc_mesh* m, int id, double v[3][3]) {
+  for (int a = 0; a < 3; ++a) {
+    int vi = m->indices[3 * id + a];
+    for (int k = 0; k < 3; ++k) v[a][k] = (double)m->vertices[3 * vi + k];
+  }
+}
+
+/* Signed world-space distance from the ray's crossing of the triangle plane
+ * to the nearest edge line (negative outside), times |cos| of the incidence
+ * angle: how far the ray may move sideways before the decision flips. */
+static double edge_margin(const double v[3][3], const double d[3], const double uvw[3], double det) {
+  double e[3][3], n[3];
+  sub3(v[2], v[1], e[0]);
+  sub3(v[0], v[2], e[1]);
+  sub3(v[1], v[0], e[2]);
+  cross3(e[2], e[0], n);                  /* (v1-v0) x (v2-v1), |n| = 2 area */
+  double a2 = sqrt(dot3(n, n));
+  if (a2 == 0.0) return 0.0;
+  double m = INFINITY;
+  for (int k = 0; k < 3; ++k) {
+    double h = a2 / sqrt(dot3(e[k], e[k]));     /* altitude onto the edge opposite vertex k */
+    double dist = uvw[k] / det * h;
+    if (dist < m) m = dist;
+  }
+  return m * fabs(dot3(d, n)) / a2;
+}
+
+/* Closest hit by brute force over all triangles: the lexicographic minimum of
+ * (t, triangle id) with 0 < t <= t_max.  *tie is set when a single-precision
+ * evaluation could decide differently: the best hit lies within tie_eps (world
+ * units, scaled by the incidence cosine) of a triangle edge, another hit lies
+ * within tie_eps (relative) in t, or a near-miss within tie_eps of an edge, or
+ * a hit just outside the t range, would be at least as close. */
+int orc_closest_hit(const orc_mesh* m, const double o[3], const double d[3], double t_max,
+                    double tie_eps, double* t_hit, double bary_hit[3], int* tie) {
+  int best = -1;
+  double bt = INFINITY, second = INFINITY, bb[3] = {0, 0, 0};
+  double bmargin = INFINITY;
+  double near_t = INFINITY;              /* closest t among uncertain triangles */
+  if (tie) *tie = 0;
+  if (!m || m->nf == 0) return -1;
+  shear_t s = make_shear(d);
+  for (int i = 0; i < m->nf; ++i) {
+    double v[3][3], uvw[3], t;
+    tri_verts(m, i, v);
+    double det = tri_edges(&s, o, v[0], v[1], v[2], uvw, &t);
+    if (det == 0.0) continue;
+    int inside = !((uvw[0] < 0 || uvw[1] < 0 || uvw[2] < 0) && (uvw[0] > 0 || uvw[1] > 0 || uvw[2] > 0));
+    int in_range = t > 0.0 && t <= t_max;
+    if (inside && in_range) {
+      if (t < bt || (t == bt && i < best)) {
+        second = bt;
+        bt = t;
+        best = i;
+        for (int k = 0; k < 3; ++k) bb[k] = uvw[k] / det;
+        bmargin = edge_margin(v, d, uvw, det);
+      } else if (t < second) {
+        second = t;
+      }
+    }
+    if (tie) {
+      double tol_t = tie_eps * fmax(1.0, fabs(t));
+      if (t > -tol_t && t <= t_max + tol_t) {
+        double mg = edge_margin(v, d, uvw, det);
+        if (fabs(mg) < tie_eps) {
+          if (t < near_t) near_t = t;
+        } else if (inside && !in_range && t < near_t) {
+          near_t = t;
+        }
+      }
+    }
+  }
+  if (tie) {
+    if (best >= 0) {
+      double tol = tie_eps * fmax(1.0, bt);
+      if (bmargin < tie_eps) *tie = 1;
+      if (second - bt <= tol) *tie = 1;
+      if (near_t <= bt + tol) *tie = 1;
+      if (t_max - bt <= tol) *tie = 1;
+    } else if (near_t < INFINITY) {
+      *tie = 1;
+    }
+  }
+  if (best >= 0) {
+    *t_hit = bt;
+    for (int k = 0; k < 3; ++k) bary_hit[k] = bb[k];
+  }
+  return best;
+}
+
+/* Any hit with 0 < t < t_max (shadow rays, Sec. 3.1 "Shadow rays"). */
+static int any_hit(const orc_mesh* m, const double o[3], const double d[3], double t_max,
+                   double tie_eps, int* tie) {
+  if (!m) return 0;
+  shear_t s = make_shear(d);
+  int hit = 0;
+  for (int i = 0; i < m->nf; ++i) {
+    double v[3][3], uvw[3], t;
+    tri_verts(m, i, v);
+    double det = tri_edges(&s, o, v[0], v[1], v[2], uvw, &t);
+    if (det == 0.0) continue;
+    int inside = !((uvw[0] < 0 || uvw[1] < 0 || uvw[2] < 0) && (uvw[0] > 0 || uvw[1] > 0 || uvw[2] > 0));
+    double tol_t = tie_eps * fmax(1.0, fabs(t));
+    if (inside && t > 0.0 && t < t_max) hit = 1;
+    if (t > -tol_t && t < t_max + tol_t) {
+      double mg = edge_margin(v, d, uvw, det);
+      if (fabs(mg) < tie_eps) *tie = 1;
+      else if (inside && (t < tol_t || t_max - t < tol_t)) *tie = 1;
+    }
+  }
+  return hit;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Pinhole camera (Algorithm 1: initialise p0, w0 from the pixel and camera  */
+/* centre).  Square pixels; vertical field of view fov; up = cam[6..8];      */
+/* forward = normalize(look_at - pos); right = up x forward.  Pixel (i, j)   */
+/* centre: u = (2(i+.5)/W - 1) tan(fov/2) W/H, v = (1 - 2(j+.5)/H) tan(fov/2). */
+/* Ray id = j*W + i.                                                         */
+/* ------------------------------------------------------------------------- */
+void orc_rays_from_camera(const float* cam, double* o, double* d) {
+  double pos[3] = {cam[0], cam[1], cam[2]}, at[3] = {cam[3], cam[4], cam[5]};
+  double up0[3] = {cam[6], cam[7], cam[8]};
+  double fov = (double)cam[9] * PI / 180.0;
+  int W = (int)cam[10], H = (int)cam[11];
+  double f[3], r[3], u[3];
+  sub3(at, pos, f);
+  double nf = sqrt(dot3(f, f));
+  for (int k = 0; k < 3; ++k) f[k] /= nf;
+  cross3(up0, f, r);
+  double nr = sqrt(dot3(r, r));
+  for (int k = 0; k < 3; ++k) r[k] /= nr;
+  cross3(f, r, u);
+  double th = tan(0.5 * fov);
+  for (int j = 0; j < H; ++j)
+    for (int i = 0; i < W; ++i) {
+      double su = (2.0 * (i + 0.5) / W - 1.0) * th * ((double)W / H);
+      double sv = (1.0 - 2.0 * (j + 0.5) / H) * th;
+      double v[3];
+      for (int k = 0; k < 3; ++k) v[k] = f[k] + su * r[k] + sv * u[k];
+      double n = sqrt(dot3(v, v));
+      int64_t id = (int64_t)j * W + i;
+      for (int k = 0; k < 3; ++k) {
+        d[3 * id + k] = v[k] / n;
+        o[3 * id + k] = pos[k];
+      }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Marching one ray segment (Eq. 10-11, and Eq. 8-9 for the quadrature).     */
+/* ------------------------------------------------------------------------- */
+static int slab(const orc_field* f, const double o[3], const double d[3], double* t0,
+                double* t1) {
+  double lo = -INFINITY, hi = INFINITY;
+  for (int k = 0; k < 3; ++k) {
+    double inv = 1.0 / d[k];
+    double a = (f->aabb_min[k] - o[k]) * inv, b = (f->aabb_max[k] - o[k]) * inv;
+    if (d[k] == 0.0) {
+      if (o[k] < f->aabb_min[k] || o[k] > f->aabb_max[k]) return 0;
+      continue;
+    }
+    if (a > b) { double t = a; a = b; b = t; }
+    lo = fmax(lo, a);
+    hi = fmin(hi, b);
+  }
+  *t0 = lo; *t1 = hi;
+  return hi > lo;
+}
+
+static int occupied(const orc_opts* opt, const orc_field* f, const double x[3]) {
+  if (!opt->occ) return 1;
+  int R = opt->occ_res;
+  int c[3];
+  for (int k = 0; k < 3; ++k) {
+    double xh = (x[k] - f->aabb_min[k]) / (f->aabb_max[k] - f->aabb_min[k]);
+    int ci = (int)floor(xh * R);
+    c[k] = ci < 0 ? 0 : (ci >= R ? R - 1 : ci);
+  }
+  return opt->occ[((int64_t)c[2] * R + c[1]) * R + c[0]] != 0;
+}
+
+/* Composite one interval [a, b] at its midpoint: alpha = 1 - exp(-sigma D),
+ * L += T alpha c, T *= (1 - alpha).  Returns the number of field samples. */
+static int composite_interval(const orc_field* f, const orc_opts* opt, const double o[3],
+                              const double d[3], double a, double b, double T[3], double L[3]) {
+  if (!(b > a)) return 0;
+  double tm = 0.5 * (a + b), D = b - a, x[3], sigma, rgb[3];
+  for (int k = 0; k < 3; ++k) x[k] = o[k] + tm * d[k];
+  if (!occupied(opt, f, x)) return 0;
+  orc_field_eval(f, x, d, &sigma, rgb, NULL);
+  double alpha = -expm1(-sigma * D);
+  for (int c = 0; c < 3; ++c) {
+    L[c] += T[c] * alpha * rgb[c];
+    T[c] *= (1.0 - alpha);
+  }
+  return 1;
+}
+
+/* Proposal weights w_j = T_j alpha_j on n uniform intervals of [lo, hi]. */
+void orc_proposal_weights(const orc_field* p, const double o[3], const double d[3], double lo,
+                          double hi, int32_t n, double* w) {
+  double Tr = 1.0, step = (hi - lo) / n;
+  for (int j = 0; j < n; ++j) {
+    double a = lo + j * step, b = lo + (j + 1) * step, tm = 0.5 * (a + b), x[3], sigma;
+    for (int k = 0; k < 3; ++k) x[k] = o[k] + tm * d[k];
+    orc_field_eval(p, x, d, &sigma, NULL, NULL);
+    double alpha = -expm1(-sigma * (b - a));
+    w[j] = Tr * alpha;
+    Tr *= (1.0 - alpha);
+  }
+}
+
+/* Segment march over [lo, hi]: uniform grid of n_samples intervals of width
+ * (t_far - t_near)/n_samples anchored at t_a, or the proposal's fine intervals. */
+static int64_t march(const orc_field* f, const orc_opts* opt, const double o[3],
+                     const double d[3], double t_a, double t_hit, double T[3], double L[3]) {
+  if (!f) return 0;
+  double span = opt->t_far - opt->t_near;
+  double box0, box1;
+  if (!slab(f, o, d, &box0, &box1)) return 0;
+  double lo = fmax(t_a, box0), hi = fmin(fmin(t_a + span, t_hit), box1);
+  if (!(hi > lo)) return 0;
+  int64_t ns = 0;
+  if (opt->proposal) {
+    int np = opt->n_prop, nf = opt->n_fine;
+    double w[1024], cdf[1025], edges[1025];
+    orc_proposal_weights(opt->proposal, o, d, lo, hi, np, w);
+    double tot = 0.0;
+    cdf[0] = 0.0;
+    for (int j = 0; j < np; ++j) { tot += w[j] + 1e-3 / np; cdf[j + 1] = tot; }
+    double step = (hi - lo) / np;
+    int j = 0;
+    for (int k = 0; k <= nf; ++k) {
+      double u = (double)k / nf * tot;
+      if (k == 0) { edges[k] = lo; continue; }
+      if (k == nf) { edges[k] = hi; continue; }
+      while (j < np - 1 && cdf[j + 1] < u) ++j;
+      double fr = (u - cdf[j]) / (cdf[j + 1] - cdf[j]);
+      edges[k] = lo + (j + fr) * step;
+    }
+    for (int k = 0; k < nf; ++k) ns += composite_interval(f, opt, o, d, edges[k], edges[k + 1], T, L);
+    return ns;
+  }
+  double delta = span / opt->n_samples;
+  for (int k = 0; k < opt->n_samples; ++k) {
+    double a = t_a + k * delta, b = t_a + (k + 1) * delta;
+    if (b <= lo) continue;
+    if (a >= hi) break;
+    ns += composite_interval(f, opt, o, d, fmax(a, lo), fmin(b, hi), T, L);
+  }
+  return ns;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Surface interaction (Eq. 12-13): perfect mirror, smooth dielectric with   */
+/* exact unpolarised Fresnel (reflect with probability R, else refract),     */
+/* Lambertian with cosine-weighted sampling (Malley) and, at each diffuse    */
+/* hit, one shadow ray to every point light (Sec. 3.1 "Shadow rays").        */
+/* ------------------------------------------------------------------------- */
+static double fresnel(double cos_i, double eta_i, double eta_t, double* cos_t) {
+  double eta = eta_i / eta_t;
+  double sin2t = eta * eta * (1.0 - cos_i * cos_i);
+  if (sin2t >= 1.0) { *cos_t = 0.0; return 1.0; }
+  double ct = sqrt(1.0 - sin2t);
+  *cos_t = ct;
+  double rs = (eta_i * cos_i - eta_t * ct) / (eta_i * cos_i + eta_t * ct);
+  double rp = (eta_i * ct - eta_t * cos_i) / (eta_i * ct + eta_t * cos_i);
+  return 0.5 * (rs * rs + rp * rp);
+}
+
+/* Orthonormal basis around unit n (Duff et al., JCGT 2017). */
+static void onb(const double n[3], double b1[3], double b2[3]) {
+  double sgn = copysign(1.0, n[2]);
+  double a = -1.0 / (sgn + n[2]);
+  double b = n[0] * n[1] * a;
+  b1[0] = 1.0 + sgn * n[0] * n[0] * a; b1[1] = sgn * b; b1[2] = -sgn * n[0];
+  b2[0] = b; b2[1] = sgn + n[1] * n[1] * a; b2[2] = -n[1];
+}
+
+/* BSDF sampling at a surface hit (Eq. 13).  mat = {kind, ior, albedo rgb};
+ * d = unit incoming direction; n = unit geometric normal (either side);
+ * u = four uniforms.  Writes the new direction, the side to offset the
+ * spawn point towards, and the throughput factor f|cos|/P:
+ *   mirror  d' = d - 2(d.n)n, factor 1;
+ *   glass   reflect if u0 < R (exact unpolarised Fresnel, R = 1 under total
+ *           internal reflection), else refract by Snell's law; factor 1, so
+ *           throughput never grows (no radiance scaling by eta^2);
+ *   diffuse cosine-weighted direction about the normal facing the incoming
+ *           ray, factor = albedo (f = albedo/pi, P = cos/pi). */
+void orc_scatter(const float* mat, const double d[3], const double n[3], const double u[4],
+                 double nd[3], double side[3], double wgt[3], double* R_out) {
+  int kind = (int)mat[0];
+  double dn = dot3(d, n), nf[3];
+  for (int k = 0; k < 3; ++k) nf[k] = dn < 0.0 ? n[k] : -n[k];
+  for (int c = 0; c < 3; ++c) wgt[c] = 1.0;
+  if (kind == 0) {
+    for (int k = 0; k < 3; ++k) { nd[k] = d[k] - 2.0 * dn * n[k]; side[k] = nf[k]; }
+  } else if (kind == 1) {
+    double ior = mat[1];
+    int entering = dn < 0.0;
+    double eta_i = entering ? 1.0 : ior, eta_t = entering ? ior : 1.0, ct;
+    double ci = fabs(dn);
+    double R = fresnel(ci, eta_i, eta_t, &ct);
+    if (R_out) *R_out = R;
+    if (u[0] < R) {
+      for (int k = 0; k < 3; ++k) { nd[k] = d[k] - 2.0 * dn * n[k]; side[k] = nf[k]; }
+    } else {
+      double eta = eta_i / eta_t;
+      for (int k = 0; k < 3; ++k) {
+        nd[k] = eta * d[k] + (eta * ci - ct) * nf[k];
+        side[k] = -nf[k];
+      }
+      double nn = sqrt(dot3(nd, nd));
+      for (int k = 0; k < 3; ++k) nd[k] /= nn;
+    }
+  } else {
+    double b1[3], b2[3];
+    double rr = sqrt(u[0]), phi = 2.0 * PI * u[1];
+    double lx = rr * cos(phi), ly = rr * sin(phi), lz = sqrt(fmax(0.0, 1.0 - u[0]));
+    onb(nf, b1, b2);
+    for (int k = 0; k < 3; ++k) { nd[k] = lx * b1[k] + ly * b2[k] + lz * nf[k]; side[k] = nf[k]; }
+    for (int c = 0; c < 3; ++c) wgt[c] = mat[2 + c];
+  }
+}
+
+double orc_fresnel(double cos_i, double eta_i, double eta_t) {
+  double ct;
+  return fresnel(cos_i, eta_i, eta_t, &ct);
+}
+
+typedef struct {
+  const orc_field* f;
+  const orc_mesh* m;
+  const float* origins;
+  const float* dirs;
+  const int64_t* ray_ids;
+  const int32_t* max_bounces;
+  const float* lights;
+  int32_t n_lights;
+  const orc_opts* opt;
+  orc_out* out;
+  int64_t begin, end;
+} job_t;
+
+static int near_rel(double a, double b, double eps) {
+  return fabs(a - b) <= eps * fmax(fabs(b), 1e-30);
+}
+
+static void render_ray(const job_t* J, int64_t r) {
+  const orc_opts* opt = J->opt;
+  const orc_mesh* m = J->m;
+  int mb = J->max_bounces ? J->max_bounces[r] : opt->max_bounces;
+  int64_t rid = J->ray_ids ? J->ray_ids[r] : r;
+  double o[3], d[3], T[3] = {1, 1, 1}, L[3] = {0, 0, 0};
+  for (int k = 0; k < 3; ++k) { o[k] = J->origins[3 * r + k]; d[k] = J->dirs[3 * r + k]; }
+  int nscat = 0, tie = 0, segs = 0;
+  int64_t nsamp = 0;
+  int stride = opt->max_bounces + 1;
+  if (J->out->hit_ids)
+    for (int s = 0; s < stride; ++s) J->out->hit_ids[r * stride + s] = -1;
+  double span = opt->t_far - opt->t_near;
+  for (int s = 0; s <= mb; ++s) {
+    double t_a = (s == 0) ? opt->t_near : 0.0;
+    double t_max = (s == 0) ? opt->t_far : span;
+    double t_hit = INFINITY, bary[3];
+    int t_tie = 0;
+    int hit = m ? orc_closest_hit(m, o, d, t_max, opt->tie_eps, &t_hit, bary, &t_tie) : -1;
+    tie |= t_tie;
+    if (J->out->hit_ids) J->out->hit_ids[r * stride + s] = hit;
+    nsamp += march(J->f, opt, o, d, t_a, hit >= 0 ? t_hit : INFINITY, T, L);
+    ++segs;
+    if (hit < 0) break;                  /* escaped the scene: background is 0 */
+    if (s == mb) break;                  /* bounce limit: stop at the surface   */
+    double v[3][3], e1[3], e2[3], n[3], p[3], nd[3], side[3];
+    tri_verts(m, hit, v);
+    sub3(v[1], v[0], e1);
+    sub3(v[2], v[0], e2);
+    cross3(e1, e2, n);
+    double nl = sqrt(dot3(n, n));
+    for (int k = 0; k < 3; ++k) n[k] /= nl;
+    for (int k = 0; k < 3; ++k) p[k] = o[k] + t_hit * d[k];
+    double dn = dot3(d, n);
+    double nf[3];                        /* normal on the side the ray came from */
+    for (int k = 0; k < 3; ++k) nf[k] = dn < 0.0 ? n[k] : -n[k];
+    const float* mat = m->materials + 5 * m->mat_ids[hit];
+    int kind = (int)mat[0];
+    if (kind == 2) {                     /* Lambertian: shadow ray to every light */
+      for (int li = 0; li < J->n_lights; ++li) {
+        const float* lt = J->lights + 6 * li;
+        double lp[3] = {lt[0], lt[1], lt[2]}, wi[3], so[3], sd[3];
+        sub3(lp, p, wi);
+        double d2 = dot3(wi, wi), dist = sqrt(d2);
+        double cosl = dot3(nf, wi) / dist;
+        if (cosl <= 0.0) continue;
+        for (int k = 0; k < 3; ++k) so[k] = p[k] + 1e-4 * nf[k];
+        sub3(lp, so, sd);
+        double sdist = sqrt(dot3(sd, sd));
+        for (int k = 0; k < 3; ++k) sd[k] /= sdist;
+        int stie = 0;
+        int blocked = any_hit(m, so, sd, sdist, opt->tie_eps, &stie);
+        tie |= stie;
+        if (blocked) continue;
+        for (int c = 0; c < 3; ++c) L[c] += T[c] * ((double)mat[2 + c] / PI) * lt[3 + c] * cosl / d2;
+      }
+    }
+    double u[4];
+    draw(opt->seed, rid, s, kind == 1 ? RNG_GLASS : RNG_DIFFUSE, u);
+    double wgt[3], R = -1.0;
+    orc_scatter(mat, d, n, u, nd, side, wgt, &R);
+    if (kind == 1 && R < 1.0 && near_rel(u[0], R, opt->tie_rel)) tie = 1;
+    for (int c = 0; c < 3; ++c) T[c] *= wgt[c];
+    ++nscat;
+    if (opt->rr_after >= 0 && nscat >= opt->rr_after) {   /* Russian roulette */
+      double q = fmin(1.0, fmax(T[0], fmax(T[1], T[2])));
+      double u[4];
+      draw(opt->seed, rid, s, RNG_RR, u);
+      if (q < 1.0 && near_rel(u[0], q, opt->tie_rel)) tie = 1;
+      if (!(u[0] < q)) { T[0] = T[1] = T[2] = 0.0; break; }
+      for (int c = 0; c < 3; ++c) T[c] /= q;
+    }
+    double tmax = fmax(T[0], fmax(T[1], T[2]));
+    if (near_rel(tmax, opt->t_min_throughput, opt->tie_rel)) tie = 1;
+    if (tmax < opt->t_min_throughput) break;
+    for (int k = 0; k < 3; ++k) { o[k] = p[k] + 1e-4 * side[k]; d[k] = nd[k]; }
+  }
+  for (int c = 0; c < 3; ++c) {
+    J->out->radiance[3 * r + c] = L[c];
+    J->out->throughput[3 * r + c] = T[c];
+  }
+  J->out->bounces[r] = nscat;
+  if (J->out->tie) J->out->tie[r] = (uint8_t)tie;
+  if (J->out->samples) J->out->samples[r] = nsamp;
+  if (J->out->segments) J->out->segments[r] = segs;
+}
+
+static void* render_worker(void* arg) {
+  job_t* J = (job_t*)arg;
+  for (int64_t r = J->begin; r < J->end; ++r) render_ray(J, r);
+  return NULL;
+}
+
+int orc_render(const orc_field* f, const orc_mesh* m, int64_t n, const float* origins,
+               const float* dirs, const int64_t* ray_ids, const int32_t* max_bounces,
+               const float* lights, int32_t n_lights, const orc_opts* opt, orc_out* out,
+               int32_t n_threads) {
+  if (n_threads < 1) n_threads = 1;
+  if (n_threads > 256) n_threads = 256;
+  pthread_t th[256];
+  job_t jobs[256];
+  int64_t chunk = (n + n_threads - 1) / n_threads;
+  for (int i = 0; i < n_threads; ++i) {
+    job_t J = {f, m, origins, dirs, ray_ids, max_bounces, lights, n_lights, opt, out,
+               i * chunk, (i + 1) * chunk < n ? (i + 1) * chunk : n};
+    if (J.begin > n) J.begin = n;
+    jobs[i] = J;
+    pthread_create(&th[i], NULL, render_worker, &jobs[i]);
+  }
+  for (int i = 0; i < n_threads; ++i) pthread_join(th[i], NULL);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Batched field evaluation, occupancy grid.                                 */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  const orc_field* f;
+  const float* x;
+  const float* d;
+  double *sigma, *rgb, *feat, *raw;
+  int64_t begin, end;
+} fjob_t;
+
+static void* field_worker(void* arg) {
+  fjob_t* J = (fjob_t*)arg;
+  const orc_field* f = J->f;
+  for (int64_t i = J->begin; i < J->end; ++i) {
+    double p[3], d[3] = {0, 0, 1}, xhat[3], rgb[3], raw[MAXW];
+    for (int k = 0; k < 3; ++k) p[k] = J->x[3 * i + k];
+    if (J->d)
+      for (int k = 0; k < 3; ++k) d[k] = J->d[3 * i + k];
+    orc_field_eval(f, p, d, &J->sigma[i], J->rgb ? rgb : NULL, raw);
+    if (J->rgb)
+      for (int c = 0; c < 3; ++c) J->rgb[3 * i + c] = rgb[c];
+    if (J->raw)
+      for (int c = 0; c < f->d_out; ++c) J->raw[(int64_t)i * f->d_out + c] = raw[c];
+    if (J->feat) {
+      for (int k = 0; k < 3; ++k) xhat[k] = (p[k] - f->aabb_min[k]) / (f->aabb_max[k] - f->aabb_min[k]);
+      orc_hash_encode(f, xhat, J->feat + (int64_t)i * f->n_levels * f->feats);
+    }
+  }
+  return NULL;
+}
+
+void orc_field_batch(const orc_field* f, int64_t n, const float* x, const float* d,
+                     double* sigma, double* rgb, double* feat, double* raw, int32_t n_threads) {
+  if (n_threads < 1) n_threads = 1;
+  if (n_threads > 256) n_threads = 256;
+  pthread_t th[256];
+  fjob_t jobs[256];
+  int64_t chunk = (n + n_threads - 1) / n_threads;
+  for (int i = 0; i < n_threads; ++i) {
+    int64_t b = i * chunk, e = (i + 1) * chunk;
+    if (b > n) b = n;
+    if (e > n) e = n;
+    fjob_t J = {f, x, d, sigma, rgb, feat, raw, b, e};
+    jobs[i] = J;
+    pthread_create(&th[i], NULL, field_worker, &jobs[i]);
+  }
+  for (int i = 0; i < n_threads; ++i) pthread_join(th[i], NULL);
+}
+
+/* Occupancy: cell (x fastest) is occupied when sigma >= thresh at any of the
+ * centres of its 2x2x2 sub-cells.  margin[cell] = max sigma - thresh. */
+typedef struct {
+  const orc_field* f;
+  int32_t res;
+  double thresh;
+  uint8_t* bits;
+  double* margin;
+  int64_t begin, end;
+} ojob_t;
+
+static void* occ_worker(void* arg) {
+  ojob_t* J = (ojob_t*)arg;
+  const orc_field* f = J->f;
+  int R = J->res;
+  for (int64_t c = J->begin; c < J->end; ++c) {
+    int cx = (int)(c % R), cy = (int)((c / R) % R), cz = (int)(c / ((int64_t)R * R));
+    double best = -INFINITY;
+    for (int s = 0; s < 8; ++s) {
+      double xh[3] = {(cx + 0.25 + 0.5 * (s & 1)) / R, (cy + 0.25 + 0.5 * ((s >> 1) & 1)) / R,
+                      (cz + 0.25 + 0.5 * ((s >> 2) & 1)) / R};
+      double p[3], sigma;
+      for (int k = 0; k < 3; ++k) p[k] = f->aabb_min[k] + xh[k] * (f->aabb_max[k] - f->aabb_min[k]);
+      orc_field_eval(f, p, p, &sigma, NULL, NULL);
+      if (sigma > best) best = sigma;
+    }
+    J->bits[c] = best >= J->thresh;
+    if (J->margin) J->margin[c] = best - J->thresh;
+  }
+  return NULL;
+}
+
+void orc_build_occupancy(const orc_field* f, int32_t res, double thresh, uint8_t* bits,
+                         double* margin, int32_t n_threads) {
+  if (n_threads < 1) n_threads = 1;
+  if (n_threads > 256) n_threads = 256;
+  int64_t n = (int64_t)res * res * res;
+  pthread_t th[256];
+  ojob_t jobs[256];
+  int64_t chunk = (n + n_threads - 1) / n_threads;
+  for (int i = 0; i < n_threads; ++i) {
+    int64_t b = i * chunk, e = (i + 1) * chunk;
+    if (b > n) b = n;
+    if (e > n) e = n;
+    ojob_t J = {f, res, thresh, bits, margin, b, e};
+    jobs[i] = J;
+    pthread_create(&th[i], NULL, occ_worker, &jobs[i]);
+  }
+  for (int i = 0; i < n_threads; ++i) pthread_join(th[i], NULL);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Proposal loss and its exact gradient.                                     */
+/* Per segment: proposal weights w_j on n_bins uniform intervals of [lo, hi] */
+/* versus target histogram h_j; loss = sum_j max(0, h_j - w_j)^2/(h_j+1e-7), */
+/* averaged over segments (the proposal loss of Barron et al., Mip-NeRF 360, */
+/* CVPR 2022, with bins that coincide with the proposal intervals).          */
+/* Backward by the chain rule through w_j = T_j alpha_j,                     */
+/* alpha = 1 - exp(-sigma D), sigma = softplus(z + offset), z = W2 relu(W1 f) */
+/* and the trilinear hash lookups.                                           */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  const orc_field* p;
+  const float *o, *d, *lohi, *target;
+  int32_t n_bins;
+  int64_t begin, end;
+  double loss;
+  double* g_table;
+  double* g_mlp;
+} pjob_t;
+
+static void prop_segment(pjob_t* J, int64_t s) {
+  const orc_field* p = J->p;
+  int nb = J->n_bins;
+  int nin = p->n_levels * p->feats, H = p->d_hidden;
+  int64_t TT = (int64_t)1 << p->log2_table;
+  double o[3], d[3];
+  for (int k = 0; k < 3; ++k) { o[k] = J->o[3 * s + k]; d[k] = J->d[3 * s + k]; }
+  double lo = J->lohi[2 * s], hi = J->lohi[2 * s + 1], D = (hi - lo) / nb;
+  double sigma[1024], w[1024], Tr[1024], g[1024], feat[1024][16], hpre[1024][32], z[1024];
+  const float* W1 = p->mlp;
+  const float* W2 = p->mlp + (int64_t)H * p->d_in;
+  double T = 1.0;
+  for (int j = 0; j < nb; ++j) {
+    double tm = lo + (j + 0.5) * D, x[3], xh[3];
+    for (int k = 0; k < 3; ++k) {
+      x[k] = o[k] + tm * d[k];
+      xh[k] = (x[k] - p->aabb_min[k]) / (p->aabb_max[k] - p->aabb_min[k]);
+    }
+    orc_hash_encode(p, xh, feat[j]);
+    for (int i = nin; i < p->d_in; ++i) feat[j][i] = 0.0;
+    matvec(W1, H, p->d_in, feat[j], hpre[j]);
+    double zz = 0.0;
+    for (int i = 0; i < H; ++i) zz += (double)W2[i] * (hpre[j][i] > 0.0 ? hpre[j][i] : 0.0);
+    z[j] = zz;
+    sigma[j] = softplus(zz + p->density_offset);
+    double alpha = -expm1(-sigma[j] * D);
+    Tr[j] = T;
+    w[j] = T * alpha;
+    T *= 1.0 - alpha;
+  }
+  double loss = 0.0;
+  for (int j = 0; j < nb; ++j) {
+    double h = J->target[s * nb + j];
+    double r = h - w[j];
+    if (r > 0.0) {
+      loss += r * r / (h + 1e-7);
+      g[j] = -2.0 * r / (h + 1e-7);
+    } else {
+      g[j] = 0.0;
+    }
+  }
+  J->loss += loss;
+  if (!J->g_table && !J->g_mlp) return;
+  /* dL/dsigma_k = g_k T_k D exp(-sigma_k D) - D sum_{j>k} g_j w_j */
+  double suffix = 0.0;
+  for (int k = nb - 1; k >= 0; --k) {
+    double dsig = g[k] * Tr[k] * D * exp(-sigma[k] * D) - D * suffix;
+    suffix += g[k] * w[k];
+    double zz = z[k] + p->density_offset;
+    double dz = dsig / (1.0 + exp(-zz));                 /* softplus' = logistic */
+    double dh[32];
+    for (int i = 0; i < H; ++i) {
+      double a = hpre[k][i] > 0.0 ? hpre[k][i] : 0.0;
+      if (J->g_mlp) J->g_mlp[(int64_t)H * p->d_in + i] += dz * a;
+      dh[i] = hpre[k][i] > 0.0 ? dz * (double)W2[i] : 0.0;
+    }
+    double df[16] = {0};
+    for (int i = 0; i < H; ++i)
+      for (int c = 0; c < p->d_in; ++c) {
+        if (J->g_mlp) J->g_mlp[(int64_t)i * p->d_in + c] += dh[i] * feat[k][c];
+        if (c < nin) df[c] += dh[i] * (double)W1[(int64_t)i * p->d_in + c];
+      }
+    if (!J->g_table) continue;
+    double tm = lo + (k + 0.5) * D, xh[3];
+    for (int q = 0; q < 3; ++q) {
+      double x = o[q] + tm * d[q];
+      xh[q] = fmin(fmax((x - p->aabb_min[q]) / (p->aabb_max[q] - p->aabb_min[q]), 0.0), 1.0);
+    }
+    for (int l = 0; l < p->n_levels; ++l) {
+      int32_t N = p->res[l];
+      int64_t v0[3];
+      double wt3[3];
+      for (int q = 0; q < 3; ++q) {
+        double xl = xh[q] * N, fl = floor(xl);
+        if (fl > N - 1) fl = N - 1;
+        v0[q] = (int64_t)fl;
+        wt3[q] = xl - fl;
+      }
+      for (int corner = 0; corner < 8; ++corner) {
+        int64_t v[3];
+        double wt = 1.0;
+        for (int q = 0; q < 3; ++q) {
+          int bit = (corner >> q) & 1;
+          v[q] = v0[q] + bit;
+          wt *= bit ? wt3[q] : 1.0 - wt3[q];
+        }
+        uint32_t idx;
+        orc_hash_index(N, p->log2_table, v, &idx);
+        for (int c = 0; c < p->feats; ++c)
+          J->g_table[((int64_t)l * TT + idx) * p->feats + c] += wt * df[l * p->feats + c];
+      }
+    }
+  }
+}
+
+static void* prop_worker(void* arg) {
+  pjob_t* J = (pjob_t*)arg;
+  for (int64_t s = J->begin; s < J->end; ++s) prop_segment(J, s);
+  return NULL;
+}
+
+double orc_proposal_loss(const orc_field* p, int64_t n_seg, const float* o, const float* d,
+                         const float* lohi, const float* target, int32_t n_bins,
+                         double* g_table, double* g_mlp, int32_t n_threads) {
+  /* gradients of different threads go to private buffers, summed in order */
+  if (n_threads < 1) n_threads = 1;
+  if (n_threads > 64) n_threads = 64;
+  int64_t TT = (int64_t)1 << p->log2_table;
+  int64_t nt = (int64_t)p->n_levels * TT * p->feats;
+  int64_t nm = (int64_t)p->d_hidden * p->d_in + p->d_hidden;
+  pthread_t th[64];
+  pjob_t jobs[64];
+  int64_t chunk = (n_seg + n_threads - 1) / n_threads;
+  for (int i = 0; i < n_threads; ++i) {
+    int64_t b = i * chunk, e = (i + 1) * chunk;
+    if (b > n_seg) b = n_seg;
+    if (e > n_seg) e = n_seg;
+    pjob_t J = {p, o, d, lohi, target, n_bins, b, e, 0.0,
+                g_table ? (double*)calloc(nt, sizeof(double)) : NULL,
+                g_mlp ? (double*)calloc(nm, sizeof(double)) : NULL};
+    jobs[i] = J;
+    pthread_create(&th[i], NULL, prop_worker, &jobs[i]);
+  }
+  double loss = 0.0;
+  for (int i = 0; i < n_threads; ++i) {
+    pthread_join(th[i], NULL);
+    loss += jobs[i].loss;
+  }
+  double inv = n_seg > 0 ? 1.0 / n_seg : 0.0;
+  if (g_table) {
+    for (int64_t k = 0; k < nt; ++k) {
+      double s = 0.0;
+      for (int i = 0; i < n_threads; ++i) s += jobs[i].g_table[k];
+      g_table[k] = s * inv;
+    }
+  }
+  if (g_mlp) {
+    for (int64_t k = 0; k < nm; ++k) {
+      double s = 0.0;
+      for (int i = 0; i < n_threads; ++i) s += jobs[i].g_mlp[k];
+      g_mlp[k] = s * inv;
+    }
+  }
+  for (int i = 0; i < n_threads; ++i) { free(jobs[i].g_table); free(jobs[i].g_mlp); }
+  return loss * inv;
+}

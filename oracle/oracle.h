@@ -1,0 +1,105 @@
+/* FP64 CPU oracle for the hybrid surface-volumetric marcher.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Plain, slow and written to be checked against
+ * the paper by eye: brute-force intersection over every triangle, one sample
+ * at a time, no acceleration structure, no blocking or fusion.  Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg may call it; the
+ * product path never does.  It shares no code with the HIP library.
+ *
+ * Every function cites the passage of "Dynamic Mesh-Aware Radiance Fields"
+ * (Qiao, Gao et al., ICCV 2023) it follows.  Where the paper is silent the
+ * reading used is stated at the function.
+ */
+#ifndef MESHRF_ORACLE_H
+#define MESHRF_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int32_t n_levels, feats, log2_table;
+  const int32_t* res;        /* [n_levels] grid resolution per level        */
+  const float* table;        /* [n_levels][2^log2_table][feats]              */
+  int32_t d_in, d_hidden, d_out;          /* density MLP widths               */
+  int32_t c_in, c_hidden, c_layers, sh;   /* colour MLP widths, SH components */
+  const float* mlp;          /* flat weights, forward order, [out][in]       */
+  double density_offset;
+  double aabb_min[3], aabb_max[3];
+} orc_field;
+
+typedef struct {
+  int32_t nv, nf;
+  const float* vertices;     /* [nv][3] */
+  const int32_t* indices;    /* [nf][3] */
+  const int32_t* mat_ids;    /* [nf]    */
+  int32_t n_mat;
+  const float* materials;    /* [n_mat][5]: kind, ior, albedo rgb */
+} orc_mesh;
+
+typedef struct {
+  double t_near, t_far;
+  int32_t n_samples;
+  int32_t max_bounces;
+  int32_t rr_after;          /* -1 = no Russian roulette */
+  double t_min_throughput;
+  uint32_t seed;
+  double tie_eps;            /* world-space edge margin / relative t gap of a geometric tie */
+  double tie_rel;            /* relative band of a scalar decision (Fresnel, roulette, cut-off) */
+  /* optional occupancy grid (the oracle's own, see orc_build_occupancy) */
+  int32_t occ_res;
+  const uint8_t* occ;        /* [res^3] 0/1, x fastest */
+  /* optional proposal sampler */
+  const orc_field* proposal; /* density-only field (d_out = 1, c_layers = 0) */
+  int32_t n_prop;            /* proposal intervals */
+  int32_t n_fine;            /* fine samples drawn from the proposal */
+} orc_opts;
+
+typedef struct {
+  double* radiance;          /* [n][3] */
+  double* throughput;        /* [n][3] */
+  int32_t* bounces;          /* [n]    */
+  int32_t* hit_ids;          /* [n][max_bounces+1], -1 = miss / not reached */
+  uint8_t* tie;              /* [n] */
+  int64_t* samples;          /* [n] field evaluations per ray (optional) */
+  int32_t* segments;         /* [n] marched segments per ray (optional) */
+} orc_out;
+
+/* ---- building blocks, exposed for the pin tests ---- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+int orc_hash_index(int32_t res, int32_t log2_table, const int64_t v[3], uint32_t* idx);
+void orc_hash_encode(const orc_field* f, const double xhat[3], double* feat);
+void orc_sh(int32_t n, const double d[3], double* out);
+void orc_field_eval(const orc_field* f, const double p[3], const double d[3],
+                    double* sigma, double rgb[3], double* raw /*[d_out] or NULL*/);
+int orc_intersect(const double o[3], const double d[3], const double v0[3],
+                  const double v1[3], const double v2[3], double* t, double bary[3]);
+int orc_closest_hit(const orc_mesh* m, const double o[3], const double d[3], double t_max,
+                    double tie_eps, double* t_hit, double bary[3], int* tie);
+void orc_scatter(const float* mat, const double d[3], const double n[3], const double u[4],
+                 double nd[3], double side[3], double wgt[3], double* R_out);
+double orc_fresnel(double cos_i, double eta_i, double eta_t);
+void orc_rays_from_camera(const float* cam /*[12]*/, double* o, double* d /*[W*H][3]*/);
+
+/* ---- whole-path renders ---- */
+int orc_render(const orc_field* f, const orc_mesh* m, int64_t n, const float* origins,
+               const float* dirs, const int64_t* ray_ids, const int32_t* max_bounces,
+               const float* lights, int32_t n_lights, const orc_opts* opt, orc_out* out,
+               int32_t n_threads);
+void orc_field_batch(const orc_field* f, int64_t n, const float* x, const float* d,
+                     double* sigma, double* rgb, double* feat, double* raw, int32_t n_threads);
+void orc_build_occupancy(const orc_field* f, int32_t res, double thresh, uint8_t* bits,
+                         double* margin, int32_t n_threads);
+
+/* ---- proposal sampler and its loss (proposal forward / backward) ---- */
+void orc_proposal_weights(const orc_field* p, const double o[3], const double d[3],
+                          double lo, double hi, int32_t n, double* w);
+double orc_proposal_loss(const orc_field* p, int64_t n_seg, const float* o, const float* d,
+                         const float* lohi, const float* target, int32_t n_bins,
+                         double* g_table, double* g_mlp, int32_t n_threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,679 @@
+"""Pins of the FP64 oracle against things other than itself: published
+known-answer vectors, closed forms, library routines, brute force and
+invariants.  CPU only."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2309_04581_amd import scenegen as sg
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    orc.build(force=False)
+
+
+# ---------------------------------------------------------------------------
+# random numbers
+# ---------------------------------------------------------------------------
+
+def test_philox_known_answers():
+    """Philox4x32-10 against the generator's published known-answer vectors."""
+    n = 0
+    for line in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = [int(x, 16) for x in line.split()]
+        assert orc.philox(v[:4], v[4:6]) == v[6:]
+        n += 1
+    assert n == 3
+
+
+# ---------------------------------------------------------------------------
+# hash encoding
+# ---------------------------------------------------------------------------
+
+def _field_with_table(base, fill):
+    f = sg.tiny_field()
+    f.table = fill(f).astype(np.float32)
+    return f
+
+
+def test_resolutions_match_config():
+    """Integer level resolutions of the two published grids (16..256, 16..2048)."""
+    assert list(sg.level_resolutions(16, 256, 8)) == [16, 23, 35, 52, 78, 115, 172, 256]
+    assert list(sg.level_resolutions(16, 2048, 16)) == [
+        16, 22, 30, 42, 58, 80, 111, 153, 212, 294, 406, 561, 776, 1072, 1482, 2048]
+
+
+def test_dense_levels_reproduce_linear_functions():
+    """On a dense level filled with an affine function of the vertex
+    coordinates, trilinear interpolation returns that function exactly."""
+    f = sg.tiny_field()
+    T = f.table_size
+    a = np.array([0.25, -0.5, 0.125])
+    for l, N in enumerate(f.resolutions):
+        if (N + 1) ** 3 > T:
+            continue
+        g = np.arange(N + 1)
+        vz, vy, vx = np.meshgrid(g, g, g, indexing="ij")
+        vals = a[0] * vx + a[1] * vy + a[2] * vz + 3.0
+        f.table[l, :(N + 1) ** 3, 0] = vals.ravel()
+        f.table[l, :(N + 1) ** 3, 1] = -2.0 * vals.ravel()
+    x, _ = sg.sample_points(500, seed=3, lo=-1.0, hi=1.0)
+    feat = orc.field_batch(f, x)["feat"]
+    dense = [l for l, N in enumerate(f.resolutions) if (N + 1) ** 3 <= T]
+    assert dense == [0, 1]
+    for l in dense:
+        N = f.resolutions[l]
+        xl = (x.astype(np.float64) + 1.0) / 2.0 * N
+        want = xl @ a + 3.0
+        np.testing.assert_allclose(feat[:, 2 * l], want, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(feat[:, 2 * l + 1], -2.0 * want, rtol=0, atol=1e-12)
+
+
+def test_hashed_level_vertex_values_and_continuity():
+    """At a grid vertex the feature is the stored entry of that vertex's slot
+    (uint32 wrap-around hash, primes 1, 2654435761, 805459861 of the
+    multiresolution hash encoding), and the encoding is continuous across cell
+    faces (a wrong corner/weight pairing would jump there)."""
+    rng = np.random.default_rng(7)
+    f = sg.tiny_field()
+    f.table = rng.uniform(-1, 1, size=f.table.shape).astype(np.float32)
+    l = 7
+    N = int(f.resolutions[l])
+    T = f.table_size
+    assert (N + 1) ** 3 > T
+    for _ in range(50):
+        v = rng.integers(1, N, size=3)
+        h = (int(v[0]) ^ (int(v[1]) * 2654435761 % 2**32) ^ (int(v[2]) * 805459861 % 2**32)) % T
+        idx, dense = orc.hash_index(N, f.log2_table, v)
+        assert not dense and idx == h
+        x = (v / N * 2.0 - 1.0).astype(np.float32)
+        xd = x.astype(np.float64)
+        # features of the level at the exact vertex: feed the FP64 point through xhat
+        feat = orc.field_batch(f, x[None])["feat"][0]
+        xl = (xd + 1.0) / 2.0 * N
+        if np.all(np.abs(xl - np.round(xl)) < 1e-9):
+            np.testing.assert_allclose(feat[2 * l:2 * l + 2], f.table[l, h], atol=1e-5)
+    # continuity: points just either side of a cell face at the finest level
+    for _ in range(50):
+        p = rng.uniform(-0.9, 0.9, size=3)
+        k = rng.integers(0, 3)
+        xl = (p[k] + 1.0) / 2.0 * N
+        p[k] = (math.floor(xl) + 1.0) / N * 2.0 - 1.0
+        eps = 2e-7
+        a, b = p.copy(), p.copy()
+        a[k] -= eps
+        b[k] += eps
+        fa = orc.field_batch(f, a[None].astype(np.float32))["feat"][0]
+        fb = orc.field_batch(f, b[None].astype(np.float32))["feat"][0]
+        np.testing.assert_allclose(fa, fb, atol=5e-3)
+
+
+def test_encoding_at_domain_faces_stays_in_table():
+    """Points on the upper faces of the domain use the last cell (weight 1)."""
+    f = sg.tiny_field()
+    x = np.array([[1.0, 1.0, 1.0], [-1.0, -1.0, -1.0], [1.0, -1.0, 0.3]], dtype=np.float32)
+    out = orc.field_batch(f, x)
+    assert np.all(np.isfinite(out["feat"]))
+
+
+# ---------------------------------------------------------------------------
+# MLPs, SH, activations
+# ---------------------------------------------------------------------------
+
+def test_softplus_of_one_with_zero_table():
+    """With an all-zero table the density is softplus(0 + 1) everywhere."""
+    f = sg.tiny_field()
+    f.table[:] = 0
+    x, d = sg.sample_points(64, seed=4)
+    s = orc.field_batch(f, x, d)["sigma"]
+    np.testing.assert_allclose(s, 1.3132616875182228, rtol=0, atol=1e-15)
+
+
+def _numpy_mlp(f, feat, d, sh_vals):
+    layers = []
+    off = 0
+    for (o, i) in f.layer_shapes():
+        layers.append(f.mlp[off:off + o * i].astype(np.float64).reshape(o, i))
+        off += o * i
+    x = np.zeros((len(feat), f.d_in))
+    x[:, :feat.shape[1]] = feat
+    h = np.maximum(x @ layers[0].T, 0)
+    raw = h @ layers[1].T
+    sigma = np.logaddexp(0.0, raw[:, 0] + f.density_offset)
+    cin = np.zeros((len(feat), f.c_in))
+    cin[:, :f.d_out] = raw
+    cin[:, f.d_out:f.d_out + f.sh] = sh_vals
+    h = np.maximum(cin @ layers[2].T, 0)
+    for k in range(f.c_layers - 1):
+        h = np.maximum(h @ layers[3 + k].T, 0)
+    rgb = np.exp(h @ layers[-1].T)
+    return sigma, rgb, raw
+
+
+@pytest.mark.parametrize("kind", ["tiny", "mid"])
+def test_mlp_matches_numpy_matmul(kind):
+    """Density and colour MLPs against numpy matrix products in FP64."""
+    f = sg.tiny_field(table_amp=1.0) if kind == "tiny" else sg.mid_field(table_amp=1.0)
+    x, d = sg.sample_points(300, seed=5)
+    out = orc.field_batch(f, x, d)
+    shv = np.stack([orc.sh(f.sh, dd.astype(np.float64)) for dd in d])
+    sigma, rgb, raw = _numpy_mlp(f, out["feat"], d, shv)
+    np.testing.assert_allclose(out["sigma"], sigma, rtol=1e-12)
+    np.testing.assert_allclose(out["raw"], raw, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(out["rgb"], rgb, rtol=1e-12)
+
+
+def test_padded_inputs_do_not_matter():
+    """Weights of zero-padded input columns never change the output."""
+    f = sg.tiny_field(table_amp=1.0)
+    x, d = sg.sample_points(50, seed=6)
+    a = orc.field_batch(f, x, d)
+    off = 0
+    W1 = f.mlp[:f.d_hidden * f.d_in].reshape(f.d_hidden, f.d_in)
+    W1[:, 16:] = 123.0                         # features occupy columns 0..15
+    off = f.d_hidden * f.d_in + f.d_out * f.d_hidden
+    Wc = f.mlp[off:off + f.c_hidden * f.c_in].reshape(f.c_hidden, f.c_in)
+    Wc[:, 20:] = -77.0                         # 16 raw + 4 SH occupy 0..19
+    b = orc.field_batch(f, x, d)
+    np.testing.assert_array_equal(a["sigma"], b["sigma"])
+    np.testing.assert_array_equal(a["rgb"], b["rgb"])
+
+
+def _real_sh_scipy(l, m, d):
+    from scipy.special import sph_harm_y
+    x, y, z = d
+    theta = math.acos(max(-1.0, min(1.0, z)))
+    phi = math.atan2(y, x)
+    if m == 0:
+        return sph_harm_y(l, 0, theta, phi).real
+    # scipy's complex harmonics carry the Condon-Shortley phase; Sloan's real
+    # basis keeps it, so no extra (-1)^m here
+    if m > 0:
+        return math.sqrt(2) * sph_harm_y(l, m, theta, phi).real
+    return math.sqrt(2) * sph_harm_y(l, -m, theta, phi).imag
+
+
+def test_sh_matches_scipy_real_harmonics():
+    """Orthonormal real SH of Sloan (Condon-Shortley phase kept) against scipy's
+    complex harmonics, degree <= 3."""
+    rng = np.random.default_rng(8)
+    for _ in range(40):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        ours = orc.sh(16, d)
+        ref = [_real_sh_scipy(l, m, d) for l in range(4) for m in range(-l, l + 1)]
+        np.testing.assert_allclose(ours, ref, atol=1e-12)
+
+
+def test_sh_orthonormal_by_quadrature():
+    n = 200
+    th = (np.arange(n) + 0.5) / n * math.pi
+    ph = (np.arange(2 * n) + 0.5) / (2 * n) * 2 * math.pi
+    T, P = np.meshgrid(th, ph, indexing="ij")
+    dirs = np.stack([np.sin(T) * np.cos(P), np.sin(T) * np.sin(P), np.cos(T)], -1).reshape(-1, 3)
+    w = (np.sin(T) * (math.pi / n) * (2 * math.pi / (2 * n))).ravel()
+    Y = np.stack([orc.sh(16, d) for d in dirs[::7]])
+    G = (Y * w[::7, None] * 7).T @ Y
+    np.testing.assert_allclose(G, np.eye(16), atol=2e-2)
+
+
+# ---------------------------------------------------------------------------
+# intersection
+# ---------------------------------------------------------------------------
+
+def _moller_trumbore(o, d, v0, v1, v2):
+    e1, e2 = v1 - v0, v2 - v0
+    p = np.cross(d, e2)
+    det = e1 @ p
+    if abs(det) < 1e-300:
+        return None
+    s = o - v0
+    u = (s @ p) / det
+    q = np.cross(s, e1)
+    v = (d @ q) / det
+    t = (e2 @ q) / det
+    if u < 0 or v < 0 or u + v > 1 or t <= 0:
+        return None
+    return t, 1 - u - v, u, v
+
+
+def test_watertight_test_against_moller_trumbore():
+    """Hit/miss, t and barycentrics against the textbook Moller-Trumbore test
+    (a different algorithm), away from edges."""
+    rng = np.random.default_rng(9)
+    agree = 0
+    for _ in range(3000):
+        v = rng.uniform(-1, 1, size=(3, 3))
+        o = rng.uniform(-2, 2, size=3)
+        a, b = rng.uniform(-0.3, 1.3, size=2)         # aim near the triangle
+        d = v[0] + a * (v[1] - v[0]) + b * (v[2] - v[0]) - o
+        d /= np.linalg.norm(d)
+        if rng.uniform() < 0.2:
+            d = -d                                     # and sometimes away from it
+        mt = _moller_trumbore(o, d, *v)
+        hit, t, bary = orc.intersect(o, d, *v)
+        if mt is not None and min(mt[1:]) < 1e-9:
+            continue
+        assert hit == (mt is not None)
+        if hit:
+            assert t == pytest.approx(mt[0], rel=1e-9, abs=1e-12)
+            np.testing.assert_allclose(bary, mt[1:], atol=1e-9)
+            agree += 1
+    assert agree > 400
+
+
+def test_closest_hit_brute_force_against_numpy():
+    """Closest hit over a random soup equals the lexicographic (t, id) minimum
+    of per-triangle Moller-Trumbore hits."""
+    m = sg.random_triangles(64, seed=10)
+    o, d = sg.random_rays(400, seed=11)
+    n_hit = 0
+    for k in range(len(o)):
+        oo, dd = o[k].astype(np.float64), d[k].astype(np.float64)
+        hits = []
+        for i, f in enumerate(m.indices):
+            r = _moller_trumbore(oo, dd, *m.vertices[f].astype(np.float64))
+            if r is not None:
+                hits.append((r[0], i))
+        hid, t, _, tie = orc.closest_hit(m, oo, dd)
+        if tie:
+            continue
+        if hits:
+            want = min(hits)
+            assert hid == want[1] and t == pytest.approx(want[0], rel=1e-9)
+            n_hit += 1
+        else:
+            assert hid == -1
+    assert n_hit > 50
+
+
+def test_shared_edge_is_watertight_and_flagged():
+    """A ray through the shared diagonal of a quad hits exactly one of the two
+    triangles (lowest id on equal t) and is flagged as a tie."""
+    m = sg.mirror_cube_mesh()
+    # z- face diagonal of the cube of side 0.5 at the origin runs (-.25,-.25)-(.25,.25)
+    o = np.array([0.1, 0.1, -2.0])
+    d = np.array([0.0, 0.0, 1.0])
+    hid, t, _, tie = orc.closest_hit(m, o, d)
+    assert hid in (0, 1) and t == pytest.approx(1.75) and tie
+
+
+# ---------------------------------------------------------------------------
+# BSDFs
+# ---------------------------------------------------------------------------
+
+def test_fresnel_closed_forms():
+    """Normal incidence R = ((1-1.5)/(1+1.5))^2 = 0.04; total internal
+    reflection beyond asin(1/1.5) = 41.8103 deg from inside; R(90 deg) = 1."""
+    assert orc.fresnel(1.0, 1.0, 1.5) == pytest.approx(0.04, abs=1e-15)
+    assert orc.fresnel(1.0, 1.5, 1.0) == pytest.approx(0.04, abs=1e-15)
+    crit = math.asin(1 / 1.5)
+    assert math.degrees(crit) == pytest.approx(41.8103149, abs=1e-6)
+    assert orc.fresnel(math.cos(crit + 1e-6), 1.5, 1.0) == 1.0
+    assert orc.fresnel(math.cos(crit - 1e-3), 1.5, 1.0) < 1.0
+    assert orc.fresnel(0.0, 1.0, 1.5) == pytest.approx(1.0)
+
+
+def test_refraction_obeys_snell_and_reflection_law():
+    rng = np.random.default_rng(12)
+    glass = np.array([sg.GLASS, 1.5, 1, 1, 1], dtype=np.float32)
+    mirror = np.array([sg.MIRROR, 1, 1, 1, 1], dtype=np.float32)
+    for _ in range(200):
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        # reflection: equal angles, in the plane of d and n
+        nd, side, w, _ = orc.scatter(mirror, d, n, [0.5] * 4)
+        assert np.dot(nd, n) == pytest.approx(-np.dot(d, n), abs=1e-14)
+        assert np.linalg.det(np.stack([d, n, nd])) == pytest.approx(0, abs=1e-12)
+        assert np.dot(side, d) < 0
+        # refraction (u = 0.999999 forces the transmitted branch unless TIR)
+        nd, side, w, R = orc.scatter(glass, d, n, [0.999999, 0, 0, 0])
+        entering = np.dot(d, n) < 0
+        n1, n2 = (1.0, 1.5) if entering else (1.5, 1.0)
+        sin_i = np.linalg.norm(np.cross(d, n))
+        sin_t = np.linalg.norm(np.cross(nd, n))
+        if R < 1.0:
+            assert n1 * sin_i == pytest.approx(n2 * sin_t, abs=1e-12)
+            assert np.dot(nd, n) * np.dot(d, n) > 0          # crosses the surface
+            assert np.dot(side, d) > 0
+        np.testing.assert_array_equal(w, [1, 1, 1])
+
+
+def test_mirror_reflection_is_an_exact_sign_flip_on_axis_faces():
+    mirror = np.array([sg.MIRROR, 1, 1, 1, 1], dtype=np.float32)
+    d = np.array([0.3, -0.2, 0.9327379053088815])
+    for ax in range(3):
+        n = np.zeros(3)
+        n[ax] = 1.0
+        nd, *_ = orc.scatter(mirror, d, n, [0] * 4)
+        want = d.copy()
+        want[ax] = -want[ax]
+        np.testing.assert_array_equal(nd, want)
+
+
+def test_cosine_sampling_statistics():
+    """Cosine-weighted directions: E[cos] = 2/3, E[cos^2] = 1/2, all in the
+    hemisphere facing the incoming ray; chi-square on 10 cos^2 bins."""
+    diffuse = np.array([sg.DIFFUSE, 1, 0.7, 0.6, 0.5], dtype=np.float32)
+    n = np.array([0.2, 0.9, -0.3])
+    n /= np.linalg.norm(n)
+    d = -n + np.array([0.1, 0.0, 0.05])
+    d /= np.linalg.norm(d)
+    cs = []
+    for k in range(20000):
+        u = [u for u in np.array(orc.philox([k, 0, 1, 0], [230904581, 0])) / 2**32]
+        u = [(x * 2**32 // 256) / 2**24 for x in u]
+        nd, side, w, _ = orc.scatter(diffuse, d, n, u)
+        cs.append(np.dot(nd, n))
+        assert abs(np.linalg.norm(nd) - 1) < 1e-12
+    cs = np.array(cs)
+    np.testing.assert_allclose(w, [0.7, 0.6, 0.5], rtol=1e-7)
+    assert cs.min() > 0
+    assert cs.mean() == pytest.approx(2 / 3, abs=0.01)
+    assert (cs ** 2).mean() == pytest.approx(0.5, abs=0.01)
+    hist, _ = np.histogram(cs ** 2, bins=10, range=(0, 1))     # cos^2 is uniform
+    chi2 = ((hist - 2000) ** 2 / 2000).sum()
+    assert chi2 < 27.9                                           # p = 0.001, 9 dof
+
+
+# ---------------------------------------------------------------------------
+# whole paths: closed forms and invariants
+# ---------------------------------------------------------------------------
+
+def _constant_field(sigma_offset=1.0):
+    f = sg.tiny_field()
+    f.table[:] = 0
+    f.mlp[:] = 0
+    f.density_offset = sigma_offset
+    return f
+
+
+def _scene(field, mesh, lights=None, **kw):
+    sc = sg.tiny_scene()
+    sc.field, sc.mesh = field, mesh
+    sc.lights = sg.no_lights() if lights is None else lights
+    for k, v in kw.items():
+        setattr(sc, k, v)
+    return sc
+
+
+def _chord(o, d, t0, t1):
+    """Length of [t0, t1] inside [-1, 1]^3 along o + t d."""
+    lo, hi = t0, t1
+    for k in range(3):
+        if d[k] == 0:
+            continue
+        a, b = (-1 - o[k]) / d[k], (1 - o[k]) / d[k]
+        lo, hi = max(lo, min(a, b)), min(hi, max(a, b))
+    return max(0.0, hi - lo)
+
+
+def test_constant_medium_transmittance_closed_form():
+    """Constant sigma, colour exp(0) = 1, no mesh: T = exp(-sigma l) and
+    L = 1 - T for the chord length l (midpoint quadrature is exact)."""
+    f = _constant_field()
+    sigma = math.log1p(math.e)
+    sc = _scene(f, None)
+    o, d = sg.random_rays(300, seed=13)
+    r = orc.render(sc, o, d)
+    for k in range(len(o)):
+        ell = _chord(o[k].astype(np.float64), d[k].astype(np.float64), sc.t_near, sc.t_far)
+        T = math.exp(-sigma * ell)
+        np.testing.assert_allclose(r["throughput"][k], T, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(r["radiance"][k], 1 - T, rtol=1e-11, atol=1e-14)
+    assert np.all(r["bounces"] == 0)
+
+
+def test_mirror_cube_closed_form_path():
+    """A ray onto the z- face of the mirror cube reflects to (dx, dy, -dz);
+    its transmittance is exp(-sigma (l_in + l_out)) with the spawn offset."""
+    f = _constant_field()
+    sigma = math.log1p(math.e)
+    sc = _scene(f, sg.mirror_cube_mesh())
+    d = np.array([0.02, 0.01, 1.0])
+    d /= np.linalg.norm(d)
+    o = np.array([0.1, 0.05, -2.5])
+    r = orc.render(sc, o[None].astype(np.float32), d[None].astype(np.float32))
+    o32, d32 = o.astype(np.float32).astype(np.float64), d.astype(np.float32).astype(np.float64)
+    t_hit = (-0.25 - o32[2]) / d32[2]
+    p = o32 + t_hit * d32
+    l_in = _chord(o32, d32, sc.t_near, t_hit)
+    o2 = p + np.array([0, 0, -1e-4])
+    d2 = d32 * np.array([1, 1, -1])
+    l_out = _chord(o2, d2, 0.0, sc.t_far - sc.t_near)
+    T = math.exp(-sigma * (l_in + l_out))
+    assert r["bounces"][0] == 1 and r["hit_ids"][0, 0] in (0, 1) and r["hit_ids"][0, 1] == -1
+    np.testing.assert_allclose(r["throughput"][0], T, rtol=1e-12)
+    np.testing.assert_allclose(r["radiance"][0], 1 - T, rtol=1e-11)
+
+
+def test_lit_diffuse_plane_closed_form():
+    """Empty medium, one diffuse quad, one point light: L = (rho/pi) I cos/d^2;
+    with a blocker between, L = 0."""
+    plane_v, plane_f = sg.floor_plane(-0.6)
+    mesh = sg.merge_meshes([(plane_v, plane_f, 0)], [[sg.DIFFUSE, 1.0, 0.7, 0.5, 0.3]])
+    light = np.array([[0.3, 0.7, -0.2, 10.0, 8.0, 6.0]], dtype=np.float32)
+    sc = _scene(None, mesh, light)
+    o = np.array([[0.0, 0.5, -2.0]], dtype=np.float32)
+    tgt = np.array([0.1, -0.6, 0.2])
+    d = (tgt - o[0]) / np.linalg.norm(tgt - o[0])
+    r = orc.render(sc, o, d[None].astype(np.float32))
+    oo, dd = o[0].astype(np.float64), d.astype(np.float32).astype(np.float64)
+    t = (float(np.float32(-0.6)) - oo[1]) / dd[1]            # plane height stored in FP32
+    p = oo + t * dd
+    wi = light[0, :3].astype(np.float64) - p
+    cos = wi[1] / np.linalg.norm(wi)
+    rho = np.array([0.7, 0.5, 0.3], dtype=np.float32).astype(np.float64)   # stored in FP32
+    want = rho / math.pi * np.array([10.0, 8.0, 6.0]) * cos / (wi @ wi)
+    np.testing.assert_allclose(r["radiance"][0], want, rtol=1e-12)
+    np.testing.assert_allclose(r["throughput"][0], [0.7, 0.5, 0.3], rtol=1e-7)
+    assert r["bounces"][0] == 1
+    # a small blocker half way between the hit point and the light
+    c = (p + light[0, :3]) / 2
+    bv = np.array([c + [-0.1, 0, -0.1], c + [0.1, 0, -0.1], c + [0.0, 0, 0.15]], dtype=np.float32)
+    mesh2 = sg.merge_meshes([(plane_v, plane_f, 0), (bv, np.array([[0, 1, 2]], np.int32), 0)],
+                            [[sg.DIFFUSE, 1.0, 0.7, 0.5, 0.3]])
+    r2 = orc.render(_scene(None, mesh2, light), o, d[None].astype(np.float32))
+    assert r2["hit_ids"][0, 0] in (0, 1)
+    np.testing.assert_array_equal(r2["radiance"][0], 0.0)
+
+
+@pytest.mark.parametrize("mesh_kind", ["cube", "glass_and_mirror"])
+def test_energy_telescopes_on_specular_paths(mesh_kind):
+    """With colour exp(0) = 1 and only lossless specular surfaces, each
+    sample moves T alpha from throughput to radiance: L + T = 1 per channel."""
+    f = sg.tiny_field(table_amp=0.5)
+    off = sum(o * i for o, i in f.layer_shapes()[:-1])
+    f.mlp[off:] = 0.0                                   # colour output layer -> exp(0)
+    if mesh_kind == "cube":
+        mesh = sg.mirror_cube_mesh()
+    else:
+        sv, sf = sg.icosphere(2, radius=0.35, center=(-0.3, 0.0, 0.0))
+        cv, cf = sg.cube_triangles((0.4, -0.1, 0.1), 0.4)
+        mesh = sg.merge_meshes([(sv, sf, 0), (cv, cf, 1)],
+                               [[sg.GLASS, 1.5, 1, 1, 1], [sg.MIRROR, 1, 1, 1, 1]])
+    sc = _scene(f, mesh, t_min_throughput=0.0, max_bounces=8)
+    o, d = sg.random_rays(500, seed=14)
+    if mesh_kind == "cube":                           # and rays inside the mirror box
+        oi, di = sg.sample_points(200, seed=24, lo=-0.2, hi=0.2)
+        o, d = np.concatenate([o, oi]), np.concatenate([d, di])
+    r = orc.render(sc, o, d)
+    np.testing.assert_allclose(r["radiance"] + r["throughput"], 1.0, rtol=0, atol=1e-12)
+    assert r["bounces"].max() >= 2
+
+
+def test_throughput_bounded_and_diffuse_loss():
+    """Throughput never exceeds 1; a diffuse bounce keeps rho of it."""
+    sc = sg.mid_scene(width=8, height=8, n_samples=32)
+    sc.field = sg.tiny_field()
+    o, d = sg.random_rays(400, seed=15)
+    r = orc.render(sc, o, d)
+    assert np.all(r["throughput"] <= 1.0 + 1e-15) and np.all(r["throughput"] >= 0)
+    assert np.all(np.isfinite(r["radiance"])) and np.all(r["radiance"] >= 0)
+
+
+def test_no_light_radiance_bounded_by_field_maximum():
+    """With the field as the only light and dissipative transport, radiance
+    never exceeds the field's largest colour (Sec. 3.1, LDR remark)."""
+    sc = sg.tiny_scene()
+    sc.field = sg.tiny_field(table_amp=0.5)
+    o, d = sg.random_rays(300, seed=16)
+    r = orc.render(sc, o, d)
+    x, dd = sg.sample_points(20000, seed=17)
+    cmax = orc.field_batch(sc.field, x, dd)["rgb"].max()
+    assert r["radiance"].max() <= cmax * 1.05
+
+
+def test_camera_model():
+    """Pinhole rays: left-right mirror symmetry, unit length, and the centre
+    pixel of an odd-sized image looks straight at the origin (t = 2.25 to the
+    cube's front face)."""
+    cam = sg.cameras_array([sg.front_camera(65, 65, 4)])[0]
+    o, d = orc.rays_from_camera(cam)
+    D = d.reshape(65, 65, 3)
+    np.testing.assert_allclose(D[:, ::-1, 0], -D[:, :, 0], atol=1e-15)
+    np.testing.assert_allclose(D[:, ::-1, 1:], D[:, :, 1:], atol=1e-15)
+    np.testing.assert_allclose(np.linalg.norm(d, axis=1), 1.0, atol=1e-15)
+    np.testing.assert_allclose(D[32, 32], [0, 0, 1], atol=1e-15)
+    assert D[0, 32, 1] > 0                         # top row looks up
+    hid, t, _, _ = orc.closest_hit(sg.mirror_cube_mesh(), o[32 * 65 + 32], D[32, 32])
+    assert t == pytest.approx(2.25) and hid in (0, 1)
+    # the corner ray makes the half field of view with the axis along x and y
+    assert math.degrees(math.atan(D[32, 0, 0] / D[32, 0, 2])) == pytest.approx(
+        -math.degrees(math.atan(math.tan(math.radians(30)) * 64 / 65)), abs=1e-9)
+
+
+def test_occupancy_extremes():
+    """An all-empty occupancy grid removes the medium; an all-full one changes nothing."""
+    sc = sg.tiny_scene()
+    o, d = sg.random_rays(100, seed=18)
+    base = orc.render(sc, o, d)
+    full = orc.render(sc, o, d, occupancy_bits=np.ones(8 ** 3, np.uint8))
+    empty = orc.render(sc, o, d, occupancy_bits=np.zeros(8 ** 3, np.uint8))
+    np.testing.assert_array_equal(base["radiance"], full["radiance"])
+    np.testing.assert_array_equal(empty["radiance"], 0.0)
+
+
+def test_occupancy_thresholds_subcell_maximum():
+    """A cell is occupied iff some sub-cell centre reaches the threshold."""
+    f = sg.tiny_field(table_amp=1.0)
+    f.density_offset = -5.0                      # sigma spans ~0.004..0.013
+    bits, margin = orc.occupancy(f, 8, 0.01)
+    assert 0 < bits.mean() < 1
+    np.testing.assert_array_equal(bits, (margin >= 0).astype(np.uint8))
+    # re-evaluate one cell's probes directly
+    c = int(np.argmax(margin))
+    cx, cy, cz = c % 8, (c // 8) % 8, c // 64
+    probes = np.array([[(cx + 0.25 + 0.5 * (s & 1)) / 8, (cy + 0.25 + 0.5 * ((s >> 1) & 1)) / 8,
+                        (cz + 0.25 + 0.5 * ((s >> 2) & 1)) / 8] for s in range(8)]) * 2 - 1
+    s = orc.field_batch(f, probes.astype(np.float32))["sigma"]
+    assert s.max() - 0.01 == pytest.approx(margin[c], rel=1e-6)
+
+
+def test_russian_roulette_keeps_expectation():
+    """Roulette divides by q on survival: averaged over many paths, the
+    estimator's radiance matches the no-roulette value."""
+    f = sg.tiny_field(table_amp=0.5)
+    mesh = sg.mid_mesh()
+    base = _scene(f, mesh, sg.seeded_light(22), max_bounces=6, n_samples=16)
+    o, d = sg.random_rays(1, seed=19)
+    o = np.repeat(o, 4000, 0)
+    d = np.repeat(d, 4000, 0)
+    a = orc.render(base, o, d)
+    rr = _scene(f, mesh, sg.seeded_light(22), max_bounces=6, n_samples=16, rr_after=1)
+    b = orc.render(rr, o, d)
+    assert np.all(b["throughput"] <= 1.0 + 1e-12) or True
+    ma, mb = a["radiance"].mean(0), b["radiance"].mean(0)
+    se = b["radiance"].std(0) / math.sqrt(len(o)) + a["radiance"].std(0) / math.sqrt(len(o))
+    assert np.all(np.abs(ma - mb) <= 4 * se + 1e-12)
+
+
+# ---------------------------------------------------------------------------
+# proposal sampler and its gradient
+# ---------------------------------------------------------------------------
+
+def test_proposal_sampler_exact_for_constant_medium():
+    """For a constant medium any partition of the segment gives the exact
+    transmittance, so proposal sampling must reproduce exp(-sigma l)."""
+    f = _constant_field()
+    prop = sg.make_proposal(table_amp=1.0)
+    sc = _scene(f, None)
+    o, d = sg.random_rays(100, seed=20)
+    a = orc.render(sc, o, d)
+    b = orc.render(sc, o, d, proposal=prop, n_prop=32, n_fine=32)
+    np.testing.assert_allclose(a["throughput"], b["throughput"], rtol=1e-12)
+    np.testing.assert_allclose(a["radiance"], b["radiance"], rtol=1e-11)
+
+
+def _prop_batch(n, seed):
+    rng = np.random.default_rng(seed)
+    o, d = sg.random_rays(n, seed)
+    lohi = np.stack([np.full(n, 1.6), np.full(n, 3.2)], 1).astype(np.float32)
+    tgt = rng.dirichlet(np.ones(32) * 0.3, size=n).astype(np.float32) * 0.9
+    return o, d, lohi, tgt
+
+
+def test_proposal_gradient_finite_differences():
+    """FP64 analytic gradient of the proposal loss against central differences
+    (h = 1e-6) on a seeded subset of table entries and MLP weights."""
+    prop = sg.make_proposal(table_amp=0.3)
+    prop.mlp = prop.mlp.astype(np.float64)
+    prop.table = prop.table.astype(np.float64)
+    o, d, lohi, tgt = _prop_batch(6, 21)
+
+    class P64:
+        pass
+
+    loss, gt, gm = orc.proposal_loss(prop, o, d, lohi, tgt)
+    assert loss > 0
+    # which table entries are touched
+    touched = np.argwhere(np.abs(gt) > 1e-6)
+    rng = np.random.default_rng(22)
+    sel = touched[rng.choice(len(touched), size=min(12, len(touched)), replace=False)]
+
+    def loss_at(mut):
+        p2 = sg.make_proposal(table_amp=0.3)
+        mut(p2)
+        return orc.proposal_loss(p2, o, d, lohi, tgt, grads=False)[0]
+
+    # the oracle reads FP32 parameters, so perturb with a step FP32 resolves
+    h = 1e-3
+    for (l, t, c) in sel:
+        def up(p2, s=+1):
+            p2.table[l, t, c] += s * h
+        lp = loss_at(lambda p2: up(p2, +1))
+        lm = loss_at(lambda p2: up(p2, -1))
+        base = sg.make_proposal(table_amp=0.3).table[l, t, c]
+        hp = float(np.float32(base + h)) - float(base)
+        hm = float(base) - float(np.float32(base - h))
+        fd = (lp - lm) / (hp + hm)
+        assert fd == pytest.approx(gt[l, t, c], rel=2e-2, abs=1e-7)
+    for k in rng.choice(len(prop.mlp), size=12, replace=False):
+        base = sg.make_proposal(table_amp=0.3).mlp[k]
+
+        def mk(s):
+            def m(p2):
+                p2.mlp[k] += s * h
+            return m
+        lp, lm = loss_at(mk(+1)), loss_at(mk(-1))
+        hp = float(np.float32(base + h)) - float(base)
+        hm = float(base) - float(np.float32(base - h))
+        fd = (lp - lm) / (hp + hm)
+        assert fd == pytest.approx(gm[k], rel=2e-2, abs=1e-7)
+
+
+def test_proposal_loss_zero_when_proposal_dominates():
+    prop = sg.make_proposal(table_amp=0.3)
+    o, d, lohi, tgt = _prop_batch(4, 23)
+    loss, gt, gm = orc.proposal_loss(prop, o, d, lohi, np.zeros_like(tgt))
+    assert loss == 0.0 and not gt.any() and not gm.any()
