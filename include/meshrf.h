@@ -1,0 +1,228 @@
+/* meshrf -- hybrid surface-volumetric ray marcher for MI355X (gfx950).
+ *
+ * C ABI of the rendering path of "Dynamic Mesh-Aware Radiance Fields"
+ * (Qiao, Gao et al., ICCV 2023): each ray marches a radiance field (hash grid +
+ * small MLPs, linear HDR colour), alpha-composites radiance and throughput,
+ * finds the closest mesh surface through a BVH and scatters off mirror, glass
+ * or diffuse surfaces, with shadow rays to point lights, for any number of
+ * bounces (Sec. 3.1 "Hybrid Rendering Algorithm", Algorithm 1, Eq. 8-13).
+ *
+ * Conventions (all entry points):
+ *  - Every call returns an mr_status; on failure mr_last_error() returns a
+ *    thread-local message.  Arguments are validated on the host before any
+ *    launch; a call that fails validation touches no memory.
+ *  - Pointers named host_* are host memory read during the call only.  All
+ *    other array pointers are device memory owned by the caller; they must stay
+ *    valid until the stream reaches the call.  Handles are owned by the library
+ *    and released by the matching *_destroy.
+ *  - stream is a hipStream_t passed as void*; NULL is the null stream.  Render
+ *    calls are asynchronous on it and never synchronise with the host, so they
+ *    can be captured into a HIP graph.
+ *  - Arrays of 3-vectors are row-major (n, 3) float32.
+ */
+#ifndef MESHRF_H
+#define MESHRF_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MR_OK = 0,
+  MR_ERR_INVALID_ARG = 1, /* bad shape, value or pointer                  */
+  MR_ERR_OOM = 2,         /* device or host allocation failed             */
+  MR_ERR_DEVICE = 3,      /* a HIP call failed                            */
+  MR_ERR_UNSUPPORTED = 4, /* valid but not implemented (e.g. network size) */
+  MR_ERR_STATE = 5        /* handle in the wrong state                    */
+} mr_status;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* mr_last_error(void);
+
+/* Library version string. */
+const char* mr_version(void);
+
+enum { MR_F32 = 0, MR_F16 = 1, MR_BF16 = 2 };
+enum { MR_MIRROR = 0, MR_GLASS = 1, MR_DIFFUSE = 2 };
+enum { MR_SAMPLER_UNIFORM = 0, MR_SAMPLER_PROPOSAL = 1 };
+
+/* ------------------------------------------------------------------------ */
+/* Radiance field: multiresolution hash grid + density MLP + colour MLP     */
+/* (the pretrained Instant-NGP field of Sec. 3.3; colour in linear HDR as   */
+/* required by Sec. 3.1 "Unifying color space").                            */
+/*                                                                          */
+/* Level l has integer resolution N_l.  Vertex v of level l is stored at    */
+/* vx + vy(N+1) + vz(N+1)^2 when (N+1)^3 <= 2^log2_table_size, otherwise at */
+/* (vx ^ vy*2654435761 ^ vz*805459861) mod 2^log2_table_size (uint32).      */
+/* A point p maps to xhat = (p - aabb_min)/(aabb_max - aabb_min), clamped   */
+/* to [0,1]; corners floor(xhat N) (at most N-1) + {0,1}^3, trilinear.      */
+/* Features are level-major, zero padded to density_in.                     */
+/* density: h = relu(W0 f), raw = W1 h (density_out values, no biases),     */
+/*          sigma = softplus(raw[0] + density_offset).                      */
+/* colour:  c_in = raw ++ SH(d) (real orthonormal SH, sh_components of      */
+/*          1/4/9/16, Condon-Shortley phase), zero padded to color_in;      */
+/*          color_hidden_layers ReLU layers of width color_hidden, then a   */
+/*          3-wide output layer; rgb = exp(out).                            */
+/* A proposal field has color_hidden_layers = 0 and density_out = 1.        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n_levels;           /* 1..16 */
+  int32_t feats_per_level;    /* 2 */
+  int32_t log2_table_size;    /* 10..24 */
+  const int32_t* host_resolutions; /* n_levels integers >= 1 */
+  int32_t table_dtype;        /* MR_F32 or MR_F16 (device copy of the table) */
+  int32_t mlp_dtype;          /* MR_F32, or MR_BF16 (MFMA with FP32 accumulation) */
+  int32_t density_in, density_hidden, density_out;
+  int32_t color_in, color_hidden, color_hidden_layers, sh_components;
+  float density_offset;
+  float aabb_min[3], aabb_max[3];
+} mr_field_desc;
+
+typedef struct mr_field mr_field;
+
+/* Create a field from FP32 master parameters.
+ * host_table: [n_levels][2^log2_table_size][feats_per_level] float32.
+ * host_mlp:   all layers in forward order, each [out][in] row-major float32:
+ *             density (hidden x density_in), (density_out x hidden), colour
+ *             (color_hidden x color_in), (color_hidden x color_hidden) per
+ *             extra hidden layer, (3 x color_hidden).  For a proposal field
+ *             (color_hidden_layers = 0) only the two density layers.
+ * Supported shapes: density_in = 32 (or n_levels*feats <= 16 for a proposal),
+ * density_hidden = 64 (16 for a proposal), density_out = 16 (1), color_in =
+ * 32, color_hidden = 64, color_hidden_layers 1 or 2, sh_components 4 or 16.
+ * Non-finite parameters are MR_ERR_INVALID_ARG; other shapes are
+ * MR_ERR_UNSUPPORTED.  The table is converted to table_dtype and the MLP
+ * copied (and rounded to bf16 for MR_BF16) on the device. */
+mr_status mr_field_create(const mr_field_desc* desc, const float* host_table,
+                          const float* host_mlp, void* stream, mr_field** out);
+mr_status mr_field_destroy(mr_field* f);
+
+/* Evaluate the field at n points (device arrays).
+ * x, dirs: (n, 3); sigma: (n); rgb: (n, 3) or NULL; feat: (n, n_levels*feats)
+ * or NULL (interpolated hash features, FP32); raw: (n, density_out) or NULL. */
+mr_status mr_field_query(const mr_field* f, int64_t n, const float* x, const float* dirs,
+                         float* sigma, float* rgb, float* feat, float* raw, void* stream);
+
+/* Occupancy bit grid for empty-space skipping (attached to the field).
+ * Cell (i, j, k) of a res^3 grid over the field box (x fastest) is occupied
+ * when sigma >= thresh at any of the centres of its 2x2x2 sub-cells.
+ * bits_out: optional device uint8 (res^3) export of the grid.
+ * res in 1..512. */
+mr_status mr_field_build_occupancy(mr_field* f, int32_t res, float thresh, uint8_t* bits_out,
+                                   void* stream);
+
+/* Device pointers of the field's parameters (for training and inspection).
+ * table: [L][T][F] in table_dtype; mlp: FP32 flat weights. */
+mr_status mr_field_params(mr_field* f, void** table, float** mlp, int64_t* n_table,
+                          int64_t* n_mlp);
+
+/* ------------------------------------------------------------------------ */
+/* Triangle meshes with per-triangle materials, and their BVH (the surfaces */
+/* of Sec. 3.1 "Surface Rendering Equation"; ray casting t(p, w), Eq. 3).   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t kind;    /* MR_MIRROR | MR_GLASS | MR_DIFFUSE */
+  float ior;       /* glass index of refraction (> 1) */
+  float albedo[3]; /* diffuse reflectance in [0, 1] */
+} mr_material;
+
+typedef struct mr_mesh mr_mesh;
+
+/* Build a binary BVH with the surface-area heuristic (binned, on the host)
+ * and upload it.  host_vertices (nv, 3); host_indices (nf, 3), each in
+ * [0, nv); host_mat_ids (nf) in [0, n_materials).  Triangle ids reported by
+ * mr_render are the row numbers of host_indices.  Degenerate (zero-area)
+ * triangles are kept and never hit.  Surfaces are two-sided; a triangle's
+ * geometric normal is (v1 - v0) x (v2 - v0), and for glass it must point
+ * out of the solid. */
+mr_status mr_mesh_build_bvh(const float* host_vertices, int32_t nv, const int32_t* host_indices,
+                            int32_t nf, const int32_t* host_mat_ids,
+                            const mr_material* host_materials, int32_t n_materials,
+                            void* stream, mr_mesh** out);
+
+/* Refit the BVH to new vertex positions (device (nv, 3), same topology),
+ * bottom-up on the device; no host round trip. */
+mr_status mr_mesh_refit(mr_mesh* m, const float* vertices, void* stream);
+mr_status mr_mesh_destroy(mr_mesh* m);
+
+/* Statistics of the tree (host values): node count, depth, leaf count. */
+mr_status mr_mesh_info(const mr_mesh* m, int32_t* n_nodes, int32_t* depth, int32_t* n_leaves);
+
+/* Closest hit for n rays (device arrays): t in (0, t_max], lexicographic
+ * minimum of (t, triangle id).  t_hit (n) = +inf on a miss, tri (n) = -1. */
+mr_status mr_mesh_closest_hit(const mr_mesh* m, int64_t n, const float* origins,
+                              const float* dirs, float t_max, float* t_hit, int32_t* tri,
+                              void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Rendering (Algorithm 1).                                                 */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  float pos[3];
+  float intensity[3];
+} mr_light;
+
+typedef struct {
+  float t_near, t_far;       /* camera segment [t_near, t_far]; later segments
+                                start at their spawn point with the same length */
+  int32_t n_samples;         /* uniform intervals per segment length */
+  int32_t sampler;           /* MR_SAMPLER_UNIFORM | MR_SAMPLER_PROPOSAL */
+  const mr_field* proposal;  /* proposal field when sampler = PROPOSAL */
+  int32_t n_proposal;        /* proposal intervals per segment (32) */
+  int32_t n_fine;            /* fine samples drawn from the proposal (32) */
+  int32_t use_occupancy;     /* skip empty cells of the field's occupancy grid */
+  int32_t rr_after;          /* Russian roulette once this many scatters happened; -1 off */
+  float t_min_throughput;    /* terminate when max channel of T drops below (1e-4) */
+  uint32_t seed;             /* Philox4x32-10 key */
+} mr_render_opts;
+
+typedef struct {
+  float* radiance;           /* (n, 3) linear radiance L */
+  float* throughput;         /* (n, 3) throughput T at termination (0 if killed by roulette) */
+  int32_t* bounces;          /* (n) number of scattering events */
+  int32_t* hit_ids;          /* optional (n, hit_stride): triangle hit by segment s, -1 = none */
+  int32_t hit_stride;        /* >= max_bounces + 1 when hit_ids is set */
+  int64_t* counters;         /* optional device int64[4]: samples, segments, shadow rays, scatters */
+} mr_render_out;
+
+/* Bytes of device workspace mr_render needs for n rays. */
+size_t mr_render_workspace_size(int64_t n);
+
+/* Render n rays: origins, dirs (n, 3) device, unit directions.
+ * max_bounces >= 0 is the limit on scattering events; per_ray_max_bounces
+ * (optional device int32 (n)) overrides it per ray (each <= max_bounces).
+ * Each ray marches at most max_bounces + 1 segments.  field NULL = empty
+ * medium; mesh NULL = no surfaces.  host_lights: n_lights point lights.
+ * workspace: device buffer of mr_render_workspace_size(n) bytes, 256-byte
+ * aligned, not shared with a concurrent call. */
+mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64_t n, const float* origins,
+                    const float* dirs, int32_t max_bounces, const int32_t* per_ray_max_bounces,
+                    const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
+                    mr_render_out* out, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Pinhole camera rays (device output), camera-major, then row-major with the
+ * top row first.  host_cams: n_cams records of 12 floats: position (3),
+ * look-at (3), up (3), vertical fov in degrees, width, height.  forward =
+ * normalize(look_at - pos), right = normalize(up x forward), up' = forward x
+ * right; pixel (i, j) looks along forward + u right + v up' with
+ * u = (2(i+.5)/W - 1) tan(fov/2) W/H, v = (1 - 2(j+.5)/H) tan(fov/2).
+ * capacity >= total pixel count.  Optional per-ray camera index (int32). */
+mr_status mr_rays_from_cameras(const float* host_cams, int32_t n_cams, float* origins,
+                               float* dirs, int32_t* cam_index, int64_t capacity, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel timing for measurement.  While enabled, mr_render records a HIP   */
+/* event pair on its stream around each kernel it launches.  mr_profile_read */
+/* waits for those events and returns, per stage (0 closest hit, 1 march,   */
+/* 2 shade, 3 other), the summed milliseconds and the number of launches,   */
+/* then clears them.  Process-wide; not for use under graph capture.        */
+/* ------------------------------------------------------------------------ */
+mr_status mr_profile_enable(int32_t on);
+mr_status mr_profile_read(double* ms /*[4]*/, int64_t* launches /*[4]*/);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -424,13 +424,17 @@ static int slab(const orc_field* f, const double o[3], const double d[3], double
   return hi > lo;
 }
 
-static int occupied(const orc_opts* opt, const orc_field* f, const double x[3]) {
+/* Occupancy lookup; a sample within tie_eps (in cells) of a cell face is a
+ * tie, since single precision may place it in the neighbouring cell. */
+static int occupied(const orc_opts* opt, const orc_field* f, const double x[3], int* tie) {
   if (!opt->occ) return 1;
   int R = opt->occ_res;
   int c[3];
   for (int k = 0; k < 3; ++k) {
     double xh = (x[k] - f->aabb_min[k]) / (f->aabb_max[k] - f->aabb_min[k]);
-    int ci = (int)floor(xh * R);
+    double xr = xh * R;
+    if (fabs(xr - floor(xr + 0.5)) < opt->tie_eps * R) *tie = 1;
+    int ci = (int)floor(xr);
     c[k] = ci < 0 ? 0 : (ci >= R ? R - 1 : ci);
   }
   return opt->occ[((int64_t)c[2] * R + c[1]) * R + c[0]] != 0;
@@ -439,11 +443,12 @@ static int occupied(const orc_opts* opt, const orc_field* f, const double x[3]) 
 /* Composite one interval [a, b] at its midpoint: alpha = 1 - exp(-sigma D),
  * L += T alpha c, T *= (1 - alpha).  Returns the number of field samples. */
 static int composite_interval(const orc_field* f, const orc_opts* opt, const double o[3],
-                              const double d[3], double a, double b, double T[3], double L[3]) {
+                              const double d[3], double a, double b, double T[3], double L[3],
+                              int* tie) {
   if (!(b > a)) return 0;
   double tm = 0.5 * (a + b), D = b - a, x[3], sigma, rgb[3];
   for (int k = 0; k < 3; ++k) x[k] = o[k] + tm * d[k];
-  if (!occupied(opt, f, x)) return 0;
+  if (!occupied(opt, f, x, tie)) return 0;
   orc_field_eval(f, x, d, &sigma, rgb, NULL);
   double alpha = -expm1(-sigma * D);
   for (int c = 0; c < 3; ++c) {
@@ -470,7 +475,8 @@ void orc_proposal_weights(const orc_field* p, const double o[3], const double d[
 /* Segment march over [lo, hi]: uniform grid of n_samples intervals of width
  * (t_far - t_near)/n_samples anchored at t_a, or the proposal's fine intervals. */
 static int64_t march(const orc_field* f, const orc_opts* opt, const double o[3],
-                     const double d[3], double t_a, double t_hit, double T[3], double L[3]) {
+                     const double d[3], double t_a, double t_hit, double T[3], double L[3],
+                     int* tie) {
   if (!f) return 0;
   double span = opt->t_far - opt->t_near;
   double box0, box1;
@@ -495,7 +501,7 @@ static int64_t march(const orc_field* f, const orc_opts* opt, const double o[3],
       double fr = (u - cdf[j]) / (cdf[j + 1] - cdf[j]);
       edges[k] = lo + (j + fr) * step;
     }
-    for (int k = 0; k < nf; ++k) ns += composite_interval(f, opt, o, d, edges[k], edges[k + 1], T, L);
+    for (int k = 0; k < nf; ++k) ns += composite_interval(f, opt, o, d, edges[k], edges[k + 1], T, L, tie);
     return ns;
   }
   double delta = span / opt->n_samples;
@@ -503,7 +509,7 @@ static int64_t march(const orc_field* f, const orc_opts* opt, const double o[3],
     double a = t_a + k * delta, b = t_a + (k + 1) * delta;
     if (b <= lo) continue;
     if (a >= hi) break;
-    ns += composite_interval(f, opt, o, d, fmax(a, lo), fmin(b, hi), T, L);
+    ns += composite_interval(f, opt, o, d, fmax(a, lo), fmin(b, hi), T, L, tie);
   }
   return ns;
 }
@@ -624,7 +630,7 @@ static void render_ray(const job_t* J, int64_t r) {
     int hit = m ? orc_closest_hit(m, o, d, t_max, opt->tie_eps, &t_hit, bary, &t_tie) : -1;
     tie |= t_tie;
     if (J->out->hit_ids) J->out->hit_ids[r * stride + s] = hit;
-    nsamp += march(J->f, opt, o, d, t_a, hit >= 0 ? t_hit : INFINITY, T, L);
+    nsamp += march(J->f, opt, o, d, t_a, hit >= 0 ? t_hit : INFINITY, T, L, &tie);
     ++segs;
     if (hit < 0) break;                  /* escaped the scene: background is 0 */
     if (s == mb) break;                  /* bounce limit: stop at the surface   */

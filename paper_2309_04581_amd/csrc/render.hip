@@ -1,0 +1,702 @@
+// The hybrid rendering path (Algorithm 1 of "Dynamic Mesh-Aware Radiance
+// Fields"): per bounce, (1) cast every live ray to its closest surface
+// (Eq. 3), (2) march the radiance field along the segment up to that surface
+// and integrate throughput and radiance (Eq. 10-11, quadrature of Eq. 8-9),
+// (3) at the surface sample the BSDF, add the shadow-ray contribution of the
+// point lights at diffuse hits, update the throughput (Eq. 12-13) and apply
+// the termination rules (escape, low throughput, bounce limit), compacting
+// the survivors into the next ray queue.
+//
+// Rays live in structure-of-arrays queues in HBM; each stage is one kernel
+// reading the live count from device memory, so the host never waits and the
+// whole sequence can be captured into a HIP graph.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mr_device.h"
+#include "mr_render.h"
+
+using namespace mr;
+
+namespace mr {
+
+// ---------------------------------------------------------------------------
+// stage timing (event pairs on the launching stream)
+// ---------------------------------------------------------------------------
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+static Profiler g_prof;
+
+struct StageTimer {
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  StageTimer(int s, hipStream_t stream) : stage(s), st(stream) {
+    if (!g_prof.on) return;
+    a = g_prof.get();
+    b = g_prof.get();
+    if (a && b) (void)hipEventRecord(a, st);
+  }
+  ~StageTimer() {
+    if (!a || !b) return;
+    (void)hipEventRecord(b, st);
+    g_prof.pending.push_back({stage, {a, b}});
+  }
+};
+
+size_t queue_bytes(int64_t cap) { return (size_t)kQueueArrays * 4 * (size_t)cap; }
+
+RayQueue queue_at(void* base, int64_t cap) {
+  RayQueue q;
+  float* f = reinterpret_cast<float*>(base);
+  q.ox = f + 0 * cap; q.oy = f + 1 * cap; q.oz = f + 2 * cap;
+  q.dx = f + 3 * cap; q.dy = f + 4 * cap; q.dz = f + 5 * cap;
+  q.tr = f + 6 * cap; q.tg = f + 7 * cap; q.tb = f + 8 * cap;
+  q.lr = f + 9 * cap; q.lg = f + 10 * cap; q.lb = f + 11 * cap;
+  q.rid = reinterpret_cast<int*>(f + 12 * cap);
+  q.depth = reinterpret_cast<int*>(f + 13 * cap);
+  q.hit_t = f + 14 * cap;
+  q.hit_p = reinterpret_cast<int*>(f + 15 * cap);
+  return q;
+}
+
+}  // namespace mr
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// queue initialisation from caller rays
+// ---------------------------------------------------------------------------
+__global__ void k_init(int64_t n, const float* __restrict__ o, const float* __restrict__ d,
+                       const int32_t* __restrict__ per_ray_mb, int max_bounces, RayQueue q, int* __restrict__ counts,
+                       int n_counts, int32_t* __restrict__ hit_ids, int hit_stride, unsigned long long* __restrict__ stats) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid == 0) {
+    for (int k = 0; k < n_counts; ++k) counts[k] = 0;
+    counts[0] = (int)n;
+    if (stats)
+      for (int k = 0; k < 4; ++k) stats[k] = 0ull;
+  }
+  for (int64_t i = tid; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    q.ox[i] = o[3 * i]; q.oy[i] = o[3 * i + 1]; q.oz[i] = o[3 * i + 2];
+    q.dx[i] = d[3 * i]; q.dy[i] = d[3 * i + 1]; q.dz[i] = d[3 * i + 2];
+    q.tr[i] = 1.0f; q.tg[i] = 1.0f; q.tb[i] = 1.0f;
+    q.lr[i] = 0.0f; q.lg[i] = 0.0f; q.lb[i] = 0.0f;
+    q.rid[i] = (int)i;
+    const int mb = per_ray_mb ? min(max(per_ray_mb[i], 0), max_bounces) : max_bounces;
+    q.depth[i] = mb << 16;
+    if (hit_ids)
+      for (int s = 0; s < hit_stride; ++s) hit_ids[i * hit_stride + s] = -1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// closest hit of every live ray
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kTraceBlock) void k_trace(RayQueue q, const int* __restrict__ count, BvhView B,
+                                                       float t_far, float span, int32_t* __restrict__ hit_ids,
+                                                       int hit_stride) {
+  __shared__ int stack[kStack * kTraceBlock];
+  const int cnt = *count;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+    const int seg = q.depth[i] & 0xFFFF;
+    const RayPre r = ray_pre(v3(q.ox[i], q.oy[i], q.oz[i]), v3(q.dx[i], q.dy[i], q.dz[i]));
+    float t = INFINITY;
+    const int p = B.n_prims ? bvh_trace<false>(B, r, seg == 0 ? t_far : span, t, stack + threadIdx.x, kTraceBlock) : -1;
+    q.hit_t[i] = p >= 0 ? t : INFINITY;
+    q.hit_p[i] = p;
+    if (hit_ids && seg < hit_stride) hit_ids[(int64_t)q.rid[i] * hit_stride + seg] = p >= 0 ? __float_as_int(B.tris[3 * p].w) : -1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// segment march: one wave per ray, one sample per lane, 64 samples a step
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float wave_scan_mul(float v, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const float u = __shfl_up(v, off, 64);
+    if (lane >= off) v *= u;
+  }
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ bool slab(const FieldView& F, float ox, float oy, float oz, float dx, float dy, float dz,
+                                     float& t0, float& t1) {
+  float lo = -INFINITY, hi = INFINITY;
+  const float o[3] = {ox, oy, oz}, d[3] = {dx, dy, dz};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (d[k] == 0.0f) {
+      if (o[k] < F.amin[k] || o[k] > F.amax[k]) return false;
+      continue;
+    }
+    const float inv = 1.0f / d[k];
+    float a = (F.amin[k] - o[k]) * inv, b = (F.amax[k] - o[k]) * inv;
+    if (a > b) { const float t = a; a = b; b = t; }
+    lo = fmaxf(lo, a);
+    hi = fminf(hi, b);
+  }
+  t0 = lo;
+  t1 = hi;
+  return hi > lo;
+}
+
+__device__ __forceinline__ bool occupied(const FieldView& F, float px, float py, float pz) {
+  float xh, yh, zh;
+  to_unit(F, px, py, pz, xh, yh, zh);
+  const int R = F.occ_res;
+  const int cx = min((int)(xh * R), R - 1), cy = min((int)(yh * R), R - 1), cz = min((int)(zh * R), R - 1);
+  const int64_t c = ((int64_t)cz * R + cy) * R + cx;
+  return (F.occ[c >> 5] >> (c & 31)) & 1u;
+}
+
+template <int NL, int SH, int CL, typename TabT>
+__global__ __launch_bounds__(256) void k_march(RayQueue q, const int* __restrict__ count, int* __restrict__ work,
+                                               FieldView F, const TabT* __restrict__ table, MarchParams P,
+                                               unsigned long long* __restrict__ stats) {
+  __shared__ __align__(16) float sW[MlpLayout<CL>::TOTAL];
+  for (int i = threadIdx.x; i < MlpLayout<CL>::TOTAL; i += blockDim.x) sW[i] = F.mlp[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int cnt = *count;
+  const bool use_occ = P.use_occupancy && F.occ;
+  unsigned long long nsamp = 0;
+  while (true) {
+    int r = 0;
+    if (lane == 0) r = atomicAdd(work, 1);
+    r = __shfl(r, 0, 64);
+    if (r >= cnt) break;
+    const float ox = q.ox[r], oy = q.oy[r], oz = q.oz[r];
+    const float dx = q.dx[r], dy = q.dy[r], dz = q.dz[r];
+    const int seg = q.depth[r] & 0xFFFF;
+    const float t_a = seg == 0 ? P.t_near : 0.0f;
+    float box0, box1;
+    if (!slab(F, ox, oy, oz, dx, dy, dz, box0, box1)) continue;
+    const float lo = fmaxf(t_a, box0);
+    const float hi = fminf(fminf(t_a + P.span, q.hit_t[r]), box1);
+    if (!(hi > lo)) continue;
+    const float delta = P.delta;
+    const int k0 = max(0, (int)floorf((lo - t_a) / delta) - 1);
+    const int k1 = min(P.n_samples, (int)ceilf((hi - t_a) / delta) + 1);
+    float Tseg = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
+    for (int kb = k0; kb < k1; kb += 64) {
+      const int k = kb + lane;
+      const float a = fmaxf(t_a + (float)k * delta, lo);
+      const float b = fminf(t_a + (float)(k + 1) * delta, hi);
+      bool valid = k < k1 && b > a;
+      const float tm = 0.5f * (a + b), D = b - a;
+      const float px = ox + tm * dx, py = oy + tm * dy, pz = oz + tm * dz;
+      if (valid && use_occ) valid = occupied(F, px, py, pz);
+      float alpha = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+      if (valid) {
+        float feat[32], raw[16], rgb[3];
+        hash_encode<NL, TabT>(F, table, px, py, pz, feat);
+        density_mlp<NL>(sW, feat, raw);
+        const float sigma = softplusf(raw[0] + F.density_offset);
+        color_mlp<SH, CL>(sW, raw, dx, dy, dz, rgb);
+        alpha = -expm1f(-sigma * D);
+        c0 = rgb[0]; c1 = rgb[1]; c2 = rgb[2];
+        ++nsamp;
+      }
+      const float incl = wave_scan_mul(1.0f - alpha, lane);
+      float excl = __shfl_up(incl, 1, 64);
+      if (lane == 0) excl = 1.0f;
+      const float w = Tseg * excl * alpha;
+      acc0 += w * c0;
+      acc1 += w * c1;
+      acc2 += w * c2;
+      Tseg *= __shfl(incl, 63, 64);
+    }
+    acc0 = wave_sum(acc0);
+    acc1 = wave_sum(acc1);
+    acc2 = wave_sum(acc2);
+    if (lane == 0) {
+      const float tr = q.tr[r], tg = q.tg[r], tb = q.tb[r];
+      q.lr[r] += tr * acc0;
+      q.lg[r] += tg * acc1;
+      q.lb[r] += tb * acc2;
+      q.tr[r] = tr * Tseg;
+      q.tg[r] = tg * Tseg;
+      q.tb[r] = tb * Tseg;
+    }
+  }
+  if (stats) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nsamp += __shfl_xor(nsamp, off, 64);
+    if (lane == 0 && nsamp) atomicAdd(stats + 0, nsamp);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// surface interaction, shadow rays, roulette, termination and compaction
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void finalize(const RenderOut& out, int rid, float tr, float tg, float tb, float lr, float lg,
+                                         float lb, int bounces) {
+  out.radiance[3 * (int64_t)rid] = lr;
+  out.radiance[3 * (int64_t)rid + 1] = lg;
+  out.radiance[3 * (int64_t)rid + 2] = lb;
+  out.throughput[3 * (int64_t)rid] = tr;
+  out.throughput[3 * (int64_t)rid + 1] = tg;
+  out.throughput[3 * (int64_t)rid + 2] = tb;
+  out.bounces[rid] = bounces;
+}
+
+__global__ __launch_bounds__(kTraceBlock) void k_shade(RayQueue qi, const int* __restrict__ count_in, RayQueue qo,
+                                                       int* __restrict__ count_out, MeshView M, ShadeParams S,
+                                                       RenderOut out, unsigned long long* __restrict__ stats) {
+  __shared__ int stack[kStack * kTraceBlock];
+  const int cnt = *count_in;
+  const int lane = threadIdx.x & 63;
+  unsigned long long n_seg = 0, n_shadow = 0, n_scat = 0;
+  for (int i0 = blockIdx.x * blockDim.x; i0 < cnt; i0 += gridDim.x * blockDim.x) {
+    const int i = i0 + threadIdx.x;
+    bool keep = false;
+    float nox = 0, noy = 0, noz = 0, ndx = 0, ndy = 0, ndz = 0, tr = 0, tg = 0, tb = 0, lr = 0, lg = 0, lb = 0;
+    int rid = 0, ndepth = 0;
+    if (i < cnt) {
+      ++n_seg;
+      rid = qi.rid[i];
+      const int depth = qi.depth[i];
+      const int seg = depth & 0xFFFF, mb = depth >> 16;
+      const int p = qi.hit_p[i];
+      tr = qi.tr[i]; tg = qi.tg[i]; tb = qi.tb[i];
+      lr = qi.lr[i]; lg = qi.lg[i]; lb = qi.lb[i];
+      if (p < 0 || seg >= mb) {
+        finalize(out, rid, tr, tg, tb, lr, lg, lb, seg);
+      } else {
+        const V3 o = v3(qi.ox[i], qi.oy[i], qi.oz[i]), d = v3(qi.dx[i], qi.dy[i], qi.dz[i]);
+        const float t = qi.hit_t[i];
+        const float4 q0 = M.bvh.tris[3 * p], q1 = M.bvh.tris[3 * p + 1], q2 = M.bvh.tris[3 * p + 2];
+        const V3 v0 = v3(q0.x, q0.y, q0.z), v1 = v3(q1.x, q1.y, q1.z), v2 = v3(q2.x, q2.y, q2.z);
+        V3 n = cross(v1 - v0, v2 - v0);
+        const float nl = sqrtf(dot(n, n));
+        n = v3(n.x / nl, n.y / nl, n.z / nl);
+        const V3 P = o + t * d;
+        const float dn = dot(d, n);
+        const V3 nf = dn < 0.0f ? n : v3(-n.x, -n.y, -n.z);
+        const Material mat = M.mat[__float_as_int(q1.w)];
+        V3 nd, side;
+        float wr = 1.0f, wg = 1.0f, wb = 1.0f;
+        if (mat.kind == MR_DIFFUSE) {
+          for (int li = 0; li < S.n_lights; ++li) {
+            const V3 lp = v3(S.lights[li][0], S.lights[li][1], S.lights[li][2]);
+            const V3 wi = lp - P;
+            const float d2 = dot(wi, wi), dist = sqrtf(d2);
+            const float cosl = dot(nf, wi) / dist;
+            if (!(cosl > 0.0f)) continue;
+            const V3 so = P + 1e-4f * nf;
+            V3 sd = lp - so;
+            const float sdist = sqrtf(dot(sd, sd));
+            sd = v3(sd.x / sdist, sd.y / sdist, sd.z / sdist);
+            const RayPre sr = ray_pre(so, sd);
+            float th;
+            ++n_shadow;
+            if (bvh_trace<true>(M.bvh, sr, sdist, th, stack + threadIdx.x, kTraceBlock) >= 0) continue;
+            const float g = cosl / d2 * (1.0f / 3.14159265358979323846f);
+            lr += tr * mat.albedo[0] * S.lights[li][3] * g;
+            lg += tg * mat.albedo[1] * S.lights[li][4] * g;
+            lb += tb * mat.albedo[2] * S.lights[li][5] * g;
+          }
+        }
+        const float4 u = draw4(S.seed, (uint32_t)rid, (uint32_t)seg, mat.kind == MR_GLASS ? kRngGlass : kRngDiffuse);
+        if (mat.kind == MR_MIRROR) {
+          nd = d - (2.0f * dn) * n;
+          side = nf;
+        } else if (mat.kind == MR_GLASS) {
+          const bool entering = dn < 0.0f;
+          const float eta_i = entering ? 1.0f : mat.ior, eta_t = entering ? mat.ior : 1.0f;
+          const float ci = fabsf(dn);
+          const float eta = eta_i / eta_t;
+          const float sin2t = eta * eta * (1.0f - ci * ci);
+          float R = 1.0f, ct = 0.0f;
+          if (sin2t < 1.0f) {
+            ct = sqrtf(1.0f - sin2t);
+            const float rs = (eta_i * ci - eta_t * ct) / (eta_i * ci + eta_t * ct);
+            const float rp = (eta_i * ct - eta_t * ci) / (eta_i * ct + eta_t * ci);
+            R = 0.5f * (rs * rs + rp * rp);
+          }
+          if (u.x < R) {
+            nd = d - (2.0f * dn) * n;
+            side = nf;
+          } else {
+            nd = eta * d + (eta * ci - ct) * nf;
+            const float nn = sqrtf(dot(nd, nd));
+            nd = v3(nd.x / nn, nd.y / nn, nd.z / nn);
+            side = v3(-nf.x, -nf.y, -nf.z);
+          }
+        } else {
+          // cosine-weighted hemisphere about nf, basis of Duff et al. 2017
+          const float rr = sqrtf(u.x), phi = 6.283185307179586f * u.y;
+          const float lx = rr * cosf(phi), ly = rr * sinf(phi), lz = sqrtf(fmaxf(0.0f, 1.0f - u.x));
+          const float sgn = copysignf(1.0f, nf.z);
+          const float a = -1.0f / (sgn + nf.z);
+          const float bb = nf.x * nf.y * a;
+          const V3 b1 = v3(1.0f + sgn * nf.x * nf.x * a, sgn * bb, -sgn * nf.x);
+          const V3 b2 = v3(bb, sgn + nf.y * nf.y * a, -nf.y);
+          nd = lx * b1 + ly * b2 + lz * nf;
+          side = nf;
+          wr = mat.albedo[0]; wg = mat.albedo[1]; wb = mat.albedo[2];
+        }
+        tr *= wr; tg *= wg; tb *= wb;
+        const int nscat = seg + 1;
+        ++n_scat;
+        bool alive = true;
+        if (S.rr_after >= 0 && nscat >= S.rr_after) {
+          const float qv = fminf(1.0f, fmaxf(tr, fmaxf(tg, tb)));
+          const float4 ur = draw4(S.seed, (uint32_t)rid, (uint32_t)seg, kRngRoulette);
+          if (!(ur.x < qv)) {
+            alive = false;
+            finalize(out, rid, 0.0f, 0.0f, 0.0f, lr, lg, lb, nscat);
+          } else {
+            tr /= qv; tg /= qv; tb /= qv;
+          }
+        }
+        if (alive && fmaxf(tr, fmaxf(tg, tb)) < S.t_min) {
+          alive = false;
+          finalize(out, rid, tr, tg, tb, lr, lg, lb, nscat);
+        }
+        if (alive) {
+          keep = true;
+          const V3 no = P + 1e-4f * side;
+          nox = no.x; noy = no.y; noz = no.z;
+          ndx = nd.x; ndy = nd.y; ndz = nd.z;
+          ndepth = (mb << 16) | nscat;
+        }
+      }
+    }
+    const unsigned long long m = __ballot(keep);
+    const int nk = __popcll(m);
+    int base = 0;
+    if (lane == 0 && nk) base = atomicAdd(count_out, nk);
+    base = __shfl(base, 0, 64);
+    if (keep) {
+      const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
+      qo.ox[slot] = nox; qo.oy[slot] = noy; qo.oz[slot] = noz;
+      qo.dx[slot] = ndx; qo.dy[slot] = ndy; qo.dz[slot] = ndz;
+      qo.tr[slot] = tr; qo.tg[slot] = tg; qo.tb[slot] = tb;
+      qo.lr[slot] = lr; qo.lg[slot] = lg; qo.lb[slot] = lb;
+      qo.rid[slot] = rid;
+      qo.depth[slot] = ndepth;
+    }
+  }
+  if (stats) {
+    // per-wave sums, one atomic each
+    unsigned long long a = n_seg, b = n_shadow, c = n_scat;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      a += __shfl_xor(a, off, 64);
+      b += __shfl_xor(b, off, 64);
+      c += __shfl_xor(c, off, 64);
+    }
+    if (lane == 0) {
+      if (a) atomicAdd(stats + 1, a);
+      if (b) atomicAdd(stats + 2, b);
+      if (c) atomicAdd(stats + 3, c);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pinhole cameras
+// ---------------------------------------------------------------------------
+struct CamBatch {
+  int n;
+  int64_t offset[kMaxCamsPerLaunch + 1];
+  float pos[kMaxCamsPerLaunch][3], f[kMaxCamsPerLaunch][3], r[kMaxCamsPerLaunch][3], u[kMaxCamsPerLaunch][3];
+  float th[kMaxCamsPerLaunch];
+  int w[kMaxCamsPerLaunch], h[kMaxCamsPerLaunch];
+  int cam_base;
+};
+
+__global__ void k_raygen(CamBatch C, int64_t total, float* __restrict__ o, float* __restrict__ d,
+                         int32_t* __restrict__ cam_index, int64_t out_base) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    int c = 0;
+    while (c + 1 < C.n && i >= C.offset[c + 1]) ++c;
+    const int64_t pix = i - C.offset[c];
+    const int W = C.w[c], H = C.h[c];
+    const int px = (int)(pix % W), py = (int)(pix / W);
+    const float su = (2.0f * ((float)px + 0.5f) / (float)W - 1.0f) * C.th[c] * ((float)W / (float)H);
+    const float sv = (1.0f - 2.0f * ((float)py + 0.5f) / (float)H) * C.th[c];
+    float v[3];
+    for (int k = 0; k < 3; ++k) v[k] = C.f[c][k] + su * C.r[c][k] + sv * C.u[c][k];
+    const float nv = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    const int64_t j = out_base + i;
+    for (int k = 0; k < 3; ++k) {
+      d[3 * j + k] = v[k] / nv;
+      o[3 * j + k] = C.pos[c][k];
+    }
+    if (cam_index) cam_index[j] = C.cam_base + c;
+  }
+}
+
+template <int NL, int SH, int CL, typename TabT>
+mr_status launch_march(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
+                       unsigned long long* stats, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL((k_march<NL, SH, CL, TabT>), dim3(blocks), dim3(256), 0, st, q, count, work, f->view,
+                     reinterpret_cast<const TabT*>(f->table_dev), P, stats);
+  MR_HIP(hipGetLastError());
+  return MR_OK;
+}
+
+mr_status dispatch_march(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
+                         unsigned long long* stats, int blocks, hipStream_t st) {
+  const auto& v = f->view;
+  const bool h = v.table_dtype == MR_F16;
+#define M(NL, SH, CL)                                                                               \
+  if (v.n_levels == NL && v.sh == SH && v.c_layers == CL)                                           \
+    return h ? launch_march<NL, SH, CL, __half>(f, q, count, work, P, stats, blocks, st)            \
+             : launch_march<NL, SH, CL, float>(f, q, count, work, P, stats, blocks, st);
+  M(8, 4, 1)
+  M(16, 16, 2)
+  M(16, 4, 1)
+  M(8, 16, 2)
+#undef M
+  return fail(MR_ERR_UNSUPPORTED, "field shape not instantiated");
+}
+
+}  // namespace
+
+namespace mr {
+
+int device_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
+mr_status validate_render(const mr_field* field, const mr_mesh* mesh, int64_t n, const float* origins,
+                          const float* dirs, int32_t max_bounces, const mr_light* lights, int32_t n_lights,
+                          const mr_render_opts* opts, const mr_render_out* out) {
+  (void)mesh;
+  if (n < 0) return fail(MR_ERR_INVALID_ARG, "n < 0");
+  if (n > 0x3FFFFFFF) return fail(MR_ERR_INVALID_ARG, "at most 2^30 rays per call");
+  if (!opts || !out) return fail(MR_ERR_INVALID_ARG, "null opts or out");
+  if (n > 0 && (!origins || !dirs)) return fail(MR_ERR_INVALID_ARG, "null rays");
+  if (n > 0 && (!out->radiance || !out->throughput || !out->bounces)) return fail(MR_ERR_INVALID_ARG, "null outputs");
+  if (max_bounces < 0 || max_bounces > kMaxBounces) return fail(MR_ERR_INVALID_ARG, "max_bounces must be in 0..60");
+  if (out->hit_ids && out->hit_stride < max_bounces + 1)
+    return fail(MR_ERR_INVALID_ARG, "hit_stride must be >= max_bounces + 1");
+  if (n_lights < 0 || n_lights > kMaxLights) return fail(MR_ERR_INVALID_ARG, "n_lights must be in 0..8");
+  if (n_lights > 0 && !lights) return fail(MR_ERR_INVALID_ARG, "null lights");
+  for (int i = 0; i < n_lights; ++i)
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(lights[i].pos[k]) || !(lights[i].intensity[k] >= 0.0f) || !std::isfinite(lights[i].intensity[k]))
+        return fail(MR_ERR_INVALID_ARG, "light position must be finite and intensity finite >= 0");
+  if (!(opts->t_far > opts->t_near) || !(opts->t_near >= 0.0f) || !std::isfinite(opts->t_far))
+    return fail(MR_ERR_INVALID_ARG, "need 0 <= t_near < t_far < inf");
+  if (opts->n_samples < 1 || opts->n_samples > 4096) return fail(MR_ERR_INVALID_ARG, "n_samples must be in 1..4096");
+  if (!(opts->t_min_throughput >= 0.0f)) return fail(MR_ERR_INVALID_ARG, "t_min_throughput must be >= 0");
+  if (opts->sampler != MR_SAMPLER_UNIFORM && opts->sampler != MR_SAMPLER_PROPOSAL)
+    return fail(MR_ERR_INVALID_ARG, "unknown sampler");
+  if (opts->sampler == MR_SAMPLER_PROPOSAL) {
+    if (!opts->proposal || opts->proposal->view.c_layers != 0)
+      return fail(MR_ERR_INVALID_ARG, "proposal sampler needs a proposal field");
+    if (opts->n_proposal < 1 || opts->n_proposal > 64 || opts->n_fine < 1 || opts->n_fine > 64)
+      return fail(MR_ERR_INVALID_ARG, "n_proposal and n_fine must be in 1..64");
+  }
+  if (field && field->view.c_layers == 0) return fail(MR_ERR_INVALID_ARG, "field is a proposal field");
+  if (opts->use_occupancy && field && !field->occ_dev)
+    return fail(MR_ERR_STATE, "use_occupancy set but the field has no occupancy grid");
+  return MR_OK;
+}
+
+}  // namespace mr
+
+extern "C" size_t mr_render_workspace_size(int64_t n) {
+  const int64_t cap = ((std::max<int64_t>(n, 1) + 63) / 64) * 64;
+  return kHeaderBytes + 2 * queue_bytes(cap);
+}
+
+extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64_t n, const float* origins,
+                               const float* dirs, int32_t max_bounces, const int32_t* per_ray_max_bounces,
+                               const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
+                               mr_render_out* out, void* workspace, size_t workspace_bytes, void* stream) {
+  mr_status s = validate_render(field, mesh, n, origins, dirs, max_bounces, host_lights, n_lights, opts, out);
+  if (s != MR_OK) return s;
+  if (n == 0) return MR_OK;
+  if (!workspace || workspace_bytes < mr_render_workspace_size(n))
+    return fail(MR_ERR_INVALID_ARG, "workspace smaller than mr_render_workspace_size(n)");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(MR_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t cap = ((n + 63) / 64) * 64;
+  char* ws = reinterpret_cast<char*>(workspace);
+  int* counts = reinterpret_cast<int*>(ws);                 // [kMaxBounces + 2]
+  int* work = counts + (kMaxBounces + 2);                   // [kMaxBounces + 2]
+  RayQueue Q[2] = {queue_at(ws + kHeaderBytes, cap), queue_at(ws + kHeaderBytes + queue_bytes(cap), cap)};
+  unsigned long long* stats = reinterpret_cast<unsigned long long*>(out->counters);
+
+  const int init_blocks = (int)std::min<int64_t>((n + 255) / 256, 65535);
+  hipLaunchKernelGGL(k_init, dim3(init_blocks), dim3(256), 0, st, n, origins, dirs, per_ray_max_bounces, max_bounces,
+                     Q[0], counts, 2 * (kMaxBounces + 2), out->hit_ids, out->hit_ids ? out->hit_stride : 0, stats);
+  MR_HIP(hipGetLastError());
+
+  MeshView mv;
+  std::memset(&mv, 0, sizeof(mv));
+  static const BvhNode* null_nodes = nullptr;
+  if (mesh) mv = mesh->view;
+  else mv.bvh.nodes = null_nodes;
+
+  MarchParams P;
+  P.t_near = opts->t_near;
+  P.span = opts->t_far - opts->t_near;
+  P.n_samples = opts->n_samples;
+  P.delta = P.span / (float)opts->n_samples;
+  P.use_occupancy = opts->use_occupancy;
+
+  ShadeParams S;
+  std::memset(&S, 0, sizeof(S));
+  S.n_lights = n_lights;
+  for (int i = 0; i < n_lights; ++i)
+    for (int k = 0; k < 3; ++k) {
+      S.lights[i][k] = host_lights[i].pos[k];
+      S.lights[i][3 + k] = host_lights[i].intensity[k];
+    }
+  S.seed = opts->seed;
+  S.rr_after = opts->rr_after;
+  S.t_min = opts->t_min_throughput;
+
+  RenderOut ro;
+  ro.radiance = out->radiance;
+  ro.throughput = out->throughput;
+  ro.bounces = out->bounces;
+
+  const int cus = device_cus();
+  const int trace_blocks = (int)std::min<int64_t>((n + kTraceBlock - 1) / kTraceBlock, (int64_t)cus * 16);
+  const int march_blocks = (int)std::min<int64_t>((n + 3) / 4, (int64_t)cus * 8);
+  for (int b = 0; b <= max_bounces; ++b) {
+    RayQueue& qi = Q[b & 1];
+    RayQueue& qo = Q[(b + 1) & 1];
+    {
+      StageTimer tm(0, st);
+      hipLaunchKernelGGL(k_trace, dim3(trace_blocks), dim3(kTraceBlock), 0, st, qi, counts + b, mv.bvh, opts->t_far,
+                         P.span, out->hit_ids, out->hit_ids ? out->hit_stride : 0);
+      MR_HIP(hipGetLastError());
+    }
+    if (field) {
+      StageTimer tm(1, st);
+      if (opts->sampler == MR_SAMPLER_PROPOSAL)
+        s = dispatch_march_proposal(field, opts->proposal, qi, counts + b, work + b, P, opts->n_proposal, opts->n_fine,
+                                    stats, march_blocks, st);
+      else
+        s = dispatch_march(field, qi, counts + b, work + b, P, stats, march_blocks, st);
+      if (s != MR_OK) return s;
+    }
+    {
+      StageTimer tm(2, st);
+      hipLaunchKernelGGL(k_shade, dim3(trace_blocks), dim3(kTraceBlock), 0, st, qi, counts + b, qo, counts + b + 1, mv,
+                         S, ro, stats);
+      MR_HIP(hipGetLastError());
+    }
+  }
+  return MR_OK;
+}
+
+extern "C" mr_status mr_profile_enable(int32_t on) {
+  g_prof.on = on != 0;
+  return MR_OK;
+}
+
+extern "C" mr_status mr_profile_read(double* ms, int64_t* launches) {
+  if (!ms || !launches) return fail(MR_ERR_INVALID_ARG, "null output");
+  for (int k = 0; k < 4; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  mr_status s = MR_OK;
+  for (auto& p : g_prof.pending) {
+    float t = 0.0f;
+    if (hipEventSynchronize(p.second.second) != hipSuccess ||
+        hipEventElapsedTime(&t, p.second.first, p.second.second) != hipSuccess)
+      s = fail(MR_ERR_DEVICE, "event timing failed");
+    const int k = p.first < 0 || p.first > 3 ? 3 : p.first;
+    ms[k] += t;
+    launches[k] += 1;
+    g_prof.pool.push_back(p.second.first);
+    g_prof.pool.push_back(p.second.second);
+  }
+  g_prof.pending.clear();
+  return s;
+}
+
+extern "C" mr_status mr_rays_from_cameras(const float* host_cams, int32_t n_cams, float* origins, float* dirs,
+                                          int32_t* cam_index, int64_t capacity, void* stream) {
+  if (!host_cams || n_cams < 1) return fail(MR_ERR_INVALID_ARG, "need at least one camera");
+  if (!origins || !dirs) return fail(MR_ERR_INVALID_ARG, "null outputs");
+  int64_t total = 0;
+  for (int c = 0; c < n_cams; ++c) {
+    const float* cam = host_cams + 12 * c;
+    for (int k = 0; k < 10; ++k)
+      if (!std::isfinite(cam[k])) return fail(MR_ERR_INVALID_ARG, "non-finite camera");
+    const int W = (int)cam[10], H = (int)cam[11];
+    if (W < 1 || H < 1 || (float)W != cam[10] || (float)H != cam[11]) return fail(MR_ERR_INVALID_ARG, "bad camera size");
+    if (!(cam[9] > 0.0f && cam[9] < 180.0f)) return fail(MR_ERR_INVALID_ARG, "fov must be in (0, 180)");
+    total += (int64_t)W * H;
+  }
+  if (total > capacity) return fail(MR_ERR_INVALID_ARG, "capacity smaller than the pixel count");
+  hipStream_t st = (hipStream_t)stream;
+  int64_t base = 0;
+  for (int c0 = 0; c0 < n_cams; c0 += kMaxCamsPerLaunch) {
+    CamBatch B;
+    std::memset(&B, 0, sizeof(B));
+    B.n = std::min(kMaxCamsPerLaunch, n_cams - c0);
+    B.cam_base = c0;
+    int64_t off = 0;
+    for (int c = 0; c < B.n; ++c) {
+      const float* cam = host_cams + 12 * (c0 + c);
+      double pos[3] = {cam[0], cam[1], cam[2]}, at[3] = {cam[3], cam[4], cam[5]}, up[3] = {cam[6], cam[7], cam[8]};
+      double f[3] = {at[0] - pos[0], at[1] - pos[1], at[2] - pos[2]};
+      double nf = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+      if (!(nf > 0.0)) return fail(MR_ERR_INVALID_ARG, "camera looks at its own position");
+      for (double& x : f) x /= nf;
+      double r[3] = {up[1] * f[2] - up[2] * f[1], up[2] * f[0] - up[0] * f[2], up[0] * f[1] - up[1] * f[0]};
+      double nr = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+      if (!(nr > 0.0)) return fail(MR_ERR_INVALID_ARG, "camera up is parallel to the view direction");
+      for (double& x : r) x /= nr;
+      double u[3] = {f[1] * r[2] - f[2] * r[1], f[2] * r[0] - f[0] * r[2], f[0] * r[1] - f[1] * r[0]};
+      for (int k = 0; k < 3; ++k) {
+        B.pos[c][k] = (float)pos[k];
+        B.f[c][k] = (float)f[k];
+        B.r[c][k] = (float)r[k];
+        B.u[c][k] = (float)u[k];
+      }
+      B.th[c] = (float)std::tan(0.5 * (double)cam[9] * 3.14159265358979323846 / 180.0);
+      B.w[c] = (int)cam[10];
+      B.h[c] = (int)cam[11];
+      B.offset[c] = off;
+      off += (int64_t)B.w[c] * B.h[c];
+    }
+    B.offset[B.n] = off;
+    const int blocks = (int)std::min<int64_t>((off + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_raygen, dim3(blocks), dim3(256), 0, st, B, off, origins, dirs, cam_index, base);
+    MR_HIP(hipGetLastError());
+    base += off;
+  }
+  return MR_OK;
+}
