@@ -176,6 +176,13 @@ typedef struct {
   int32_t rr_after;          /* Russian roulette once this many scatters happened; -1 off */
   float t_min_throughput;    /* terminate when max channel of T drops below (1e-4) */
   uint32_t seed;             /* Philox4x32-10 key */
+  int32_t march_blocks_per_cu;  /* launch shape of the persistent march grid: blocks of
+                                   4 waves per compute unit (0 = default 8) */
+  int32_t stage_blocks_per_cu;  /* closest-hit and shade grids: blocks of 128 threads
+                                   per compute unit (0 = default 16) */
+  int32_t stage_tile;           /* rays a block takes per work-queue grab in the
+                                   closest-hit and shade stages, a multiple of 128
+                                   (0 = default 512) */
 } mr_render_opts;
 
 typedef struct {
@@ -202,6 +209,34 @@ mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64_t n, const
                     const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
                     mr_render_out* out, void* workspace, size_t workspace_bytes, void* stream);
 
+/* HIP-graph capture of one mr_render call: the same arguments (the device
+ * buffers are baked into the graph and must stay allocated) are captured once
+ * on a private stream into an executable graph; mr_graph_launch replays it on
+ * any stream, re-reading the current contents of the input buffers.  Fails
+ * with MR_ERR_STATE while kernel timing (mr_profile_enable) is on. */
+typedef struct mr_graph mr_graph;
+mr_status mr_render_graph_create(const mr_field* field, const mr_mesh* mesh, int64_t n, const float* origins,
+                                 const float* dirs, int32_t max_bounces, const int32_t* per_ray_max_bounces,
+                                 const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
+                                 mr_render_out* out, void* workspace, size_t workspace_bytes, mr_graph** graph);
+mr_status mr_graph_launch(mr_graph* graph, void* stream);
+mr_status mr_graph_destroy(mr_graph* graph);
+
+/* Launch-shape autotuner: renders the given workload once per candidate
+ * (march_blocks_per_cu, stage_blocks_per_cu, stage_tile) triple, reps times
+ * each after one warm-up, timing with HIP events on stream, and writes the
+ * fastest triple and its mean milliseconds.  Candidates are host arrays;
+ * the call synchronises with the host.  Output buffers receive the result
+ * of the last render. */
+mr_status mr_autotune_render(const mr_field* field, const mr_mesh* mesh, int64_t n, const float* origins,
+                             const float* dirs, int32_t max_bounces, const int32_t* per_ray_max_bounces,
+                             const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
+                             mr_render_out* out, void* workspace, size_t workspace_bytes,
+                             const int32_t* host_march_cands, int32_t n_march,
+                             const int32_t* host_stage_cands, int32_t n_stage,
+                             const int32_t* host_tile_cands, int32_t n_tile, int32_t reps,
+                             int32_t* best /*[3]*/, float* best_ms, void* stream);
+
 /* Pinhole camera rays (device output), camera-major, then row-major with the
  * top row first.  host_cams: n_cams records of 12 floats: position (3),
  * look-at (3), up (3), vertical fov in degrees, width, height.  forward =
@@ -211,6 +246,53 @@ mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64_t n, const
  * capacity >= total pixel count.  Optional per-ray camera index (int32). */
 mr_status mr_rays_from_cameras(const float* host_cams, int32_t n_cams, float* origins,
                                float* dirs, int32_t* cam_index, int64_t capacity, void* stream);
+
+/* Per-ray bounce limits from per-camera ones: out[i] = host_cam_limits[cam_index[i]]
+ * for n rays (device arrays); cam_index values must be in [0, n_cams). */
+mr_status mr_camera_bounce_limits(const int32_t* cam_index, int64_t n, const int32_t* host_cam_limits,
+                                  int32_t n_cams, int32_t* out, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Learned proposal sampler (not in the paper, which marches every segment   */
+/* densely; follows the proposal network and loss of Mip-NeRF 360, Barron et */
+/* al. 2022).  A proposal field is a radiance-field handle created with      */
+/* color_hidden_layers = 0, 5 levels x 2 features, MLP 10 -> 16 -> 1; it     */
+/* keeps an FP32 master copy of its table for training.  mr_render with      */
+/* sampler = MR_SAMPLER_PROPOSAL takes n_proposal uniform intervals of each  */
+/* segment's marching range [lo, hi], weights w_j = T_j alpha_j from the     */
+/* proposal density, and places the n_fine fine intervals between the       */
+/* inverse-CDF points u = k/n_fine of the density proportional to            */
+/* w_j + 1e-3/n_proposal.                                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  float lr, beta1, beta2, eps;
+} mr_adam;
+
+/* Training targets from the plain marcher: for each ray (device (n, 3)
+ * arrays) march the camera segment [t_near, t_far] clipped to the field box
+ * on the uniform n_samples grid without surfaces, and split its weights
+ * w_i = T_i alpha_i over n_bins (1..64) equal bins of the clipped range by
+ * interval overlap.  lohi (n, 2) receives the range ((0, 0) on a miss),
+ * targets (n, n_bins) the histograms. */
+mr_status mr_proposal_targets(const mr_field* fine, int64_t n, const float* origins, const float* dirs,
+                              float t_near, float t_far, int32_t n_samples, int32_t n_bins, float* lohi,
+                              float* targets, void* stream);
+
+/* Proposal loss and its gradient, averaged over n segments: for each segment
+ * the proposal weights on n_bins uniform intervals of [lo, hi] against the
+ * target histogram, loss sum_j max(0, h_j - w_j)^2 / (h_j + 1e-7).
+ * loss: device float; g_table: device FP32 [L][T][F]; g_mlp: device FP32
+ * (176).  Both are overwritten.  Uses the FP32 master table. */
+mr_status mr_proposal_grad(const mr_field* proposal, int64_t n, const float* origins, const float* dirs,
+                           const float* lohi, const float* targets, int32_t n_bins, float* loss,
+                           float* g_table, float* g_mlp, void* stream);
+
+/* One Adam step on the FP32 master parameters with the gradient above; the
+ * render copy of the table (FP16 or FP32) is refreshed.  The optimiser state
+ * is allocated (hipMalloc) on the first call.  loss: device float. */
+mr_status mr_proposal_train_step(mr_field* proposal, int64_t n, const float* origins, const float* dirs,
+                                 const float* lohi, const float* targets, int32_t n_bins, const mr_adam* adam,
+                                 float* loss, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing for measurement.  While enabled, mr_render records a HIP   */

@@ -989,3 +989,43 @@ double orc_proposal_loss(const orc_field* p, int64_t n_seg, const float* o, cons
   for (int i = 0; i < n_threads; ++i) { free(jobs[i].g_table); free(jobs[i].g_mlp); }
   return loss * inv;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Proposal training targets: the plain marcher's weights w_i = T_i alpha_i  */
+/* on the uniform grid of the first (camera) segment, without surfaces, split */
+/* over n_bins equal bins of the clipped range [lo, hi] in proportion to the */
+/* overlap of each interval with each bin.  lohi = (0, 0) and zero targets   */
+/* for rays that miss the field box.                                         */
+/* ------------------------------------------------------------------------- */
+void orc_proposal_targets(const orc_field* f, int64_t n, const float* origins, const float* dirs,
+                          double t_near, double t_far, int32_t n_samples, int32_t n_bins,
+                          double* lohi, double* target) {
+  double span = t_far - t_near, delta = span / n_samples;
+  for (int64_t r = 0; r < n; ++r) {
+    double o[3], d[3], b0, b1;
+    for (int k = 0; k < 3; ++k) { o[k] = origins[3 * r + k]; d[k] = dirs[3 * r + k]; }
+    for (int j = 0; j < n_bins; ++j) target[r * n_bins + j] = 0.0;
+    lohi[2 * r] = lohi[2 * r + 1] = 0.0;
+    if (!slab(f, o, d, &b0, &b1)) continue;
+    double lo = fmax(t_near, b0), hi = fmin(t_far, b1);
+    if (!(hi > lo)) continue;
+    lohi[2 * r] = lo;
+    lohi[2 * r + 1] = hi;
+    double bw = (hi - lo) / n_bins, T = 1.0;
+    for (int k = 0; k < n_samples; ++k) {
+      double a = fmax(t_near + k * delta, lo), b = fmin(t_near + (k + 1) * delta, hi);
+      if (!(b > a)) continue;
+      double tm = 0.5 * (a + b), x[3], sigma;
+      for (int q = 0; q < 3; ++q) x[q] = o[q] + tm * d[q];
+      orc_field_eval(f, x, d, &sigma, NULL, NULL);
+      double alpha = -expm1(-sigma * (b - a));
+      double w = T * alpha;
+      T *= 1.0 - alpha;
+      for (int j = 0; j < n_bins; ++j) {
+        double c0 = lo + j * bw, c1 = lo + (j + 1) * bw;
+        double ov = fmin(b, c1) - fmax(a, c0);
+        if (ov > 0.0) target[r * n_bins + j] += w * ov / (b - a);
+      }
+    }
+  }
+}

@@ -95,6 +95,9 @@ void orc_build_occupancy(const orc_field* f, int32_t res, double thresh, uint8_t
 /* ---- proposal sampler and its loss (proposal forward / backward) ---- */
 void orc_proposal_weights(const orc_field* p, const double o[3], const double d[3],
                           double lo, double hi, int32_t n, double* w);
+void orc_proposal_targets(const orc_field* f, int64_t n, const float* origins, const float* dirs,
+                          double t_near, double t_far, int32_t n_samples, int32_t n_bins,
+                          double* lohi, double* target);
 double orc_proposal_loss(const orc_field* p, int64_t n_seg, const float* o, const float* d,
                          const float* lohi, const float* target, int32_t n_bins,
                          double* g_table, double* g_mlp, int32_t n_threads);

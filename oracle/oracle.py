@@ -298,3 +298,17 @@ def fresnel(cos_i, eta_i, eta_t):
     f = lib().orc_fresnel
     f.restype = C.c_double
     return float(f(C.c_double(cos_i), C.c_double(eta_i), C.c_double(eta_t)))
+
+
+def proposal_targets(field, o, d, t_near, t_far, n_samples, n_bins):
+    """Plain-marcher weight histograms of the camera segment (training targets)."""
+    of = OField(field)
+    o = np.ascontiguousarray(o, dtype=np.float32)
+    d = np.ascontiguousarray(d, dtype=np.float32)
+    n = len(o)
+    lohi = np.zeros((n, 2))
+    tgt = np.zeros((n, n_bins))
+    lib().orc_proposal_targets(of.ptr, C.c_int64(n), _p(o), _p(d), C.c_double(t_near),
+                               C.c_double(t_far), C.c_int32(n_samples), C.c_int32(n_bins),
+                               _p(lohi), _p(tgt))
+    return lohi, tgt

@@ -4,6 +4,7 @@
 // meshes in (Sec. 3.3, an Instant-NGP model; colour emitted as linear HDR
 // radiance per Sec. 3.1 "Unifying color space").
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -90,6 +91,15 @@ mr_status launch_occ(mr_field* f, int res, float thresh, uint8_t* bytes, hipStre
 }  // namespace
 
 namespace mr {
+
+bool use_valu_mlp() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("MESHRF_MLP");
+    v = (e && std::strcmp(e, "valu") == 0) ? 1 : 0;
+  }
+  return v == 1;
+}
 
 bool field_supported(const mr_field_desc& d, std::string& why) {
   if (d.color_hidden_layers == 0) {
@@ -200,6 +210,22 @@ extern "C" mr_status mr_field_create(const mr_field_desc* desc, const float* hos
     (void)hipFree(tmp);
     if (!ok) return cleanup(MR_ERR_DEVICE, "fp16 conversion");
   }
+  if (d.color_hidden_layers == 0) {
+    if (hipMalloc(&f->master_dev, n_table * sizeof(float)) != hipSuccess) return cleanup(MR_ERR_OOM, "master alloc");
+    if (hipMemcpyAsync(f->master_dev, host_table, n_table * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return cleanup(MR_ERR_DEVICE, "master upload");
+  }
+  if (d.color_hidden_layers > 0) {
+    for (int k = 0; k < 2; ++k) {
+      const std::vector<uint32_t> fr = build_fragments(d, host_mlp, k == 1);
+      uint32_t** dst = k == 0 ? &f->frag_f32_dev : &f->frag_bf16_dev;
+      if (hipMalloc(dst, fr.size() * sizeof(uint32_t)) != hipSuccess) return cleanup(MR_ERR_OOM, "fragment alloc");
+      if (hipMemcpyAsync(*dst, fr.data(), fr.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return cleanup(MR_ERR_DEVICE, "fragment upload");
+    }
+  }
   if (hipStreamSynchronize(st) != hipSuccess) return cleanup(MR_ERR_DEVICE, "upload sync");
 
   FieldView& v = f->view;
@@ -246,6 +272,10 @@ extern "C" mr_status mr_field_destroy(mr_field* f) {
   if (f->mlp_dev) (void)hipFree(f->mlp_dev);
   if (f->mlp_bf16_dev) (void)hipFree(f->mlp_bf16_dev);
   if (f->occ_dev) (void)hipFree(f->occ_dev);
+  if (f->frag_f32_dev) (void)hipFree(f->frag_f32_dev);
+  if (f->frag_bf16_dev) (void)hipFree(f->frag_bf16_dev);
+  if (f->master_dev) (void)hipFree(f->master_dev);
+  if (f->opt_dev) (void)hipFree(f->opt_dev);
   delete f;
   return MR_OK;
 }
@@ -267,9 +297,8 @@ extern "C" mr_status mr_field_query(const mr_field* f, int64_t n, const float* x
   if (!x || !sigma) return fail(MR_ERR_INVALID_ARG, "x and sigma are required");
   if (rgb && !dirs) return fail(MR_ERR_INVALID_ARG, "rgb needs dirs");
   if (f->view.c_layers == 0) return fail(MR_ERR_UNSUPPORTED, "use the proposal entry points for proposal fields");
-  if (f->view.mlp_dtype != MR_F32)
-    return mr_field_query_bf16(f, n, x, dirs, sigma, rgb, feat, raw, stream);
   hipStream_t st = (hipStream_t)stream;
+  if (f->view.mlp_dtype != MR_F32 || !use_valu_mlp()) return query_mfma(f, n, x, dirs, sigma, rgb, feat, raw, st);
   const auto& v = f->view;
   const bool h = v.table_dtype == MR_F16;
 #define Q(NL, SH, CL)                                                                                   \

@@ -1,0 +1,304 @@
+// Segment march and point queries with the field MLPs on the matrix cores.
+//
+// Same quadrature as the vector-unit march (Eq. 10-11: alpha compositing of
+// midpoint samples on the fixed interval grid, Eq. 8-9), but a wave works
+// through a ray's samples 16 at a time: each lane gathers the hash features
+// of one level group for one sample (mr_mfma.h), the density and colour MLPs
+// run as 16x16 MFMA tiles (FP32, or BF16 with FP32 accumulation), and the
+// compositing is a 16-lane prefix product carried from tile to tile.
+#include <cstring>
+#include <vector>
+
+#include "mr_field_kernels.h"
+#include "mr_mfma.h"
+#include "mr_render.h"
+
+using namespace mr;
+
+namespace {
+
+__device__ __forceinline__ float scan16_mul(float v, int j) {
+#pragma unroll
+  for (int off = 1; off < 16; off <<= 1) {
+    const float u = __shfl_up(v, off, 16);
+    if (j >= off) v *= u;
+  }
+  return v;
+}
+
+__device__ __forceinline__ float sum16(float v) {
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 16);
+  return v;
+}
+
+__device__ __forceinline__ bool slab_box(const FieldView& F, float ox, float oy, float oz, float dx, float dy, float dz,
+                                         float& t0, float& t1) {
+  float lo = -INFINITY, hi = INFINITY;
+  const float o[3] = {ox, oy, oz}, d[3] = {dx, dy, dz};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (d[k] == 0.0f) {
+      if (o[k] < F.amin[k] || o[k] > F.amax[k]) return false;
+      continue;
+    }
+    const float inv = 1.0f / d[k];
+    float a = (F.amin[k] - o[k]) * inv, b = (F.amax[k] - o[k]) * inv;
+    if (a > b) { const float t = a; a = b; b = t; }
+    lo = fmaxf(lo, a);
+    hi = fminf(hi, b);
+  }
+  t0 = lo;
+  t1 = hi;
+  return hi > lo;
+}
+
+__device__ __forceinline__ bool occ_lookup(const FieldView& F, float px, float py, float pz) {
+  float xh, yh, zh;
+  to_unit(F, px, py, pz, xh, yh, zh);
+  const int R = F.occ_res;
+  const int cx = min((int)(xh * R), R - 1), cy = min((int)(yh * R), R - 1), cz = min((int)(zh * R), R - 1);
+  const int64_t c = ((int64_t)cz * R + cy) * R + cx;
+  return (F.occ[c >> 5] >> (c & 31)) & 1u;
+}
+
+template <int NL, int SH, int CL, typename TabT, bool BF>
+__global__ __launch_bounds__(256) void k_march_mfma(RayQueue q, const int* __restrict__ count, int* __restrict__ work,
+                                                    FieldView F, const TabT* __restrict__ table,
+                                                    const uint32_t* __restrict__ frags, MarchParams P,
+                                                    unsigned long long* __restrict__ stats) {
+  using LY = FragLayout<NL, SH, CL, BF>;
+  __shared__ __align__(16) uint32_t sW[LY::TOTAL];
+  for (int i = threadIdx.x; i < LY::TOTAL; i += blockDim.x) sW[i] = frags[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+  const int cnt = *count;
+  const bool use_occ = P.use_occupancy && F.occ;
+  unsigned long long nsamp = 0;
+  while (true) {
+    int r = 0;
+    if (lane == 0) r = atomicAdd(work, 1);
+    r = __shfl(r, 0, 64);
+    if (r >= cnt) break;
+    const float ox = q.ox[r], oy = q.oy[r], oz = q.oz[r];
+    const float dx = q.dx[r], dy = q.dy[r], dz = q.dz[r];
+    const int seg = q.depth[r] & 0xFFFF;
+    const float t_a = seg == 0 ? P.t_near : 0.0f;
+    float box0, box1;
+    if (!slab_box(F, ox, oy, oz, dx, dy, dz, box0, box1)) continue;
+    const float lo = fmaxf(t_a, box0);
+    const float hi = fminf(fminf(t_a + P.span, q.hit_t[r]), box1);
+    if (!(hi > lo)) continue;
+    const float delta = P.delta;
+    const int k0 = max(0, (int)floorf((lo - t_a) / delta) - 1);
+    const int k1 = min(P.n_samples, (int)ceilf((hi - t_a) / delta) + 1);
+    float u[4][4];
+    sh_rows<NL, SH, CL, BF>(sW, dx, dy, dz, lane, u);
+    float Tseg = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
+    for (int kb = k0; kb < k1; kb += 16) {
+      const int k = kb + j;
+      const float a = fmaxf(t_a + (float)k * delta, lo);
+      const float b = fminf(t_a + (float)(k + 1) * delta, hi);
+      bool valid = k < k1 && b > a;
+      const float tm = 0.5f * (a + b), D = b - a;
+      const float px = ox + tm * dx, py = oy + tm * dy, pz = oz + tm * dz;
+      if (valid && use_occ) valid = occ_lookup(F, px, py, pz);
+      if (__ballot(valid) == 0ull) continue;
+      float fe[LY::NF];
+      encode_group<NL, TabT>(F, table, px, py, pz, g, fe);
+      float sigma, rgb[3];
+      f4v raw;
+      mlp_tile<NL, SH, CL, BF>(sW, fe, u, F.density_offset, lane, sigma, rgb, raw);
+      const float alpha = valid ? -expm1f(-sigma * D) : 0.0f;
+      const float incl = scan16_mul(1.0f - alpha, j);
+      float excl = __shfl_up(incl, 1, 16);
+      if (j == 0) excl = 1.0f;
+      const float w = Tseg * excl * alpha;
+      acc0 += w * rgb[0];
+      acc1 += w * rgb[1];
+      acc2 += w * rgb[2];
+      Tseg *= __shfl(incl, 15, 16);
+      if (g == 0 && valid) ++nsamp;
+    }
+    acc0 = sum16(acc0);
+    acc1 = sum16(acc1);
+    acc2 = sum16(acc2);
+    if (lane == 0) {
+      const float tr = q.tr[r], tg = q.tg[r], tb = q.tb[r];
+      q.lr[r] += tr * acc0;
+      q.lg[r] += tg * acc1;
+      q.lb[r] += tb * acc2;
+      q.tr[r] = tr * Tseg;
+      q.tg[r] = tg * Tseg;
+      q.tb[r] = tb * Tseg;
+    }
+  }
+  if (stats) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nsamp += __shfl_xor(nsamp, off, 64);
+    if (lane == 0 && nsamp) atomicAdd(stats + 0, nsamp);
+  }
+}
+
+template <int NL, int SH, int CL, typename TabT, bool BF>
+__global__ __launch_bounds__(256) void k_query_mfma(FieldView F, const TabT* __restrict__ table,
+                                                    const uint32_t* __restrict__ frags, int64_t n,
+                                                    const float* __restrict__ x, const float* __restrict__ dirs,
+                                                    float* __restrict__ sigma_out, float* __restrict__ rgb_out,
+                                                    float* __restrict__ feat_out, float* __restrict__ raw_out) {
+  using LY = FragLayout<NL, SH, CL, BF>;
+  __shared__ __align__(16) uint32_t sW[LY::TOTAL];
+  for (int i = threadIdx.x; i < LY::TOTAL; i += blockDim.x) sW[i] = frags[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  for (int64_t t = wave; t * 16 < n; t += waves) {
+    const int64_t p = t * 16 + j;
+    const bool valid = p < n;
+    const int64_t pc = valid ? p : n - 1;
+    const float px = x[3 * pc], py = x[3 * pc + 1], pz = x[3 * pc + 2];
+    float dx = 0.0f, dy = 0.0f, dz = 1.0f;
+    if (dirs) { dx = dirs[3 * pc]; dy = dirs[3 * pc + 1]; dz = dirs[3 * pc + 2]; }
+    float u[4][4];
+    sh_rows<NL, SH, CL, BF>(sW, dx, dy, dz, lane, u);
+    float fe[LY::NF];
+    encode_group<NL, TabT>(F, table, px, py, pz, g, fe);
+    float sigma, rgb[3];
+    f4v raw;
+    mlp_tile<NL, SH, CL, BF>(sW, fe, u, F.density_offset, lane, sigma, rgb, raw);
+    if (!valid) continue;
+    if (g == 0) {
+      sigma_out[p] = sigma;
+      if (rgb_out) {
+        rgb_out[3 * p] = rgb[0];
+        rgb_out[3 * p + 1] = rgb[1];
+        rgb_out[3 * p + 2] = rgb[2];
+      }
+    }
+    if (feat_out)
+#pragma unroll
+      for (int k = 0; k < LY::NF; ++k) feat_out[p * 2 * NL + g * LY::NF + k] = fe[k];
+    if (raw_out)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) raw_out[p * 16 + 4 * g + v] = raw[v];
+  }
+}
+
+template <int NL, int SH, int CL, typename TabT, bool BF>
+mr_status launch_march_mfma(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
+                            unsigned long long* stats, int blocks, hipStream_t st) {
+  const uint32_t* fr = BF ? f->frag_bf16_dev : f->frag_f32_dev;
+  hipLaunchKernelGGL((k_march_mfma<NL, SH, CL, TabT, BF>), dim3(blocks), dim3(256), 0, st, q, count, work, f->view,
+                     reinterpret_cast<const TabT*>(f->table_dev), fr, P, stats);
+  MR_HIP(hipGetLastError());
+  return MR_OK;
+}
+
+template <int NL, int SH, int CL, typename TabT, bool BF>
+mr_status launch_query_mfma(const mr_field* f, int64_t n, const float* x, const float* dirs, float* sigma, float* rgb,
+                            float* feat, float* raw, hipStream_t st) {
+  const uint32_t* fr = BF ? f->frag_bf16_dev : f->frag_f32_dev;
+  const int blocks = (int)std::min<int64_t>((n + 63) / 64, 4096);
+  hipLaunchKernelGGL((k_query_mfma<NL, SH, CL, TabT, BF>), dim3(blocks), dim3(256), 0, st, f->view,
+                     reinterpret_cast<const TabT*>(f->table_dev), fr, n, x, dirs, sigma, rgb, feat, raw);
+  MR_HIP(hipGetLastError());
+  return MR_OK;
+}
+
+}  // namespace
+
+namespace mr {
+
+// Weight fragments in the order mlp_tile reads them (see mr_mfma.h).
+std::vector<uint32_t> build_fragments(const mr_field_desc& d, const float* mlp, bool bf) {
+  const int NL = d.n_levels, SH = d.sh_components, CL = d.color_hidden_layers;
+  const int NF = NL / 2;
+  const int Wd = bf ? 2 : 1;
+  const int KS1 = bf ? NF / 4 : NF, KS2 = bf ? 4 : 16, KSC = bf ? 1 : 4;
+  const int L1 = 0, L2 = L1 + 4 * KS1 * 64 * Wd, C1 = L2 + KS2 * 64 * Wd, C2 = C1 + 4 * KSC * 64 * Wd;
+  const int OUT = C2 + (CL == 2 ? 4 * KS2 * 64 * Wd : 0), SHW = OUT + 192, TOTAL = SHW + 64 * SH;
+  std::vector<uint32_t> w(TOTAL, 0u);
+  const float* W1 = mlp;
+  const float* W2 = W1 + 64 * d.density_in;
+  const float* Wc1 = W2 + 16 * 64;
+  const float* Wc2 = Wc1 + 64 * d.color_in;
+  const float* Wout = Wc2 + (CL == 2 ? 64 * 64 : 0);
+  auto bits = [](float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return u;
+  };
+  auto bf16 = [&](float f) {
+    const uint32_t u = bits(f);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+  };
+  auto put = [&](int base, int mt, int ks, int nks, const float* M, int in_dim, int rows, int kind) {
+    for (int lane = 0; lane < 64; ++lane) {
+      const int g = lane / 16, row = mt * 16 + lane % 16;
+      const int slot = (mt * nks + ks) * 64 + lane;
+      if (!bf) {
+        const int k = frag_k(kind, false, NF, ks, g, 0);
+        w[base + slot] = row < rows ? bits(M[row * in_dim + k]) : 0u;
+      } else {
+        for (int e = 0; e < 4; ++e) {
+          const int k = frag_k(kind, true, NF, ks, g, e);
+          const uint32_t v = row < rows ? bf16(M[row * in_dim + k]) : 0u;
+          w[base + 2 * slot + e / 2] |= v << (16 * (e % 2));
+        }
+      }
+    }
+  };
+  for (int mt = 0; mt < 4; ++mt)
+    for (int ks = 0; ks < KS1; ++ks) put(L1, mt, ks, KS1, W1, d.density_in, 64, 0);
+  for (int ks = 0; ks < KS2; ++ks) put(L2, 0, ks, KS2, W2, 64, 16, 1);
+  for (int mt = 0; mt < 4; ++mt)
+    for (int ks = 0; ks < KSC; ++ks) put(C1, mt, ks, KSC, Wc1, d.color_in, 64, 2);
+  if (CL == 2)
+    for (int mt = 0; mt < 4; ++mt)
+      for (int ks = 0; ks < KS2; ++ks) put(C2, mt, ks, KS2, Wc2, 64, 64, 1);
+  for (int i = 0; i < 192; ++i) w[OUT + i] = bits(Wout[i]);
+  for (int row = 0; row < 64; ++row)
+    for (int s = 0; s < SH; ++s) w[SHW + row * SH + s] = bits(Wc1[row * d.color_in + 16 + s]);
+  return w;
+}
+
+mr_status dispatch_march_mfma(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
+                              unsigned long long* stats, int blocks, hipStream_t st) {
+  const auto& v = f->view;
+  const bool h = v.table_dtype == MR_F16, bf = v.mlp_dtype == MR_BF16;
+#define M(NL, SH, CL)                                                                                              \
+  if (v.n_levels == NL && v.sh == SH && v.c_layers == CL) {                                                         \
+    if (bf) return h ? launch_march_mfma<NL, SH, CL, __half, true>(f, q, count, work, P, stats, blocks, st)         \
+                     : launch_march_mfma<NL, SH, CL, float, true>(f, q, count, work, P, stats, blocks, st);         \
+    return h ? launch_march_mfma<NL, SH, CL, __half, false>(f, q, count, work, P, stats, blocks, st)                \
+             : launch_march_mfma<NL, SH, CL, float, false>(f, q, count, work, P, stats, blocks, st);                \
+  }
+  M(8, 4, 1)
+  M(16, 16, 2)
+  M(16, 4, 1)
+  M(8, 16, 2)
+#undef M
+  return fail(MR_ERR_UNSUPPORTED, "field shape not instantiated");
+}
+
+mr_status query_mfma(const mr_field* f, int64_t n, const float* x, const float* dirs, float* sigma, float* rgb,
+                     float* feat, float* raw, hipStream_t st) {
+  const auto& v = f->view;
+  const bool h = v.table_dtype == MR_F16, bf = v.mlp_dtype == MR_BF16;
+#define Q(NL, SH, CL)                                                                                          \
+  if (v.n_levels == NL && v.sh == SH && v.c_layers == CL) {                                                     \
+    if (bf) return h ? launch_query_mfma<NL, SH, CL, __half, true>(f, n, x, dirs, sigma, rgb, feat, raw, st)    \
+                     : launch_query_mfma<NL, SH, CL, float, true>(f, n, x, dirs, sigma, rgb, feat, raw, st);    \
+    return h ? launch_query_mfma<NL, SH, CL, __half, false>(f, n, x, dirs, sigma, rgb, feat, raw, st)           \
+             : launch_query_mfma<NL, SH, CL, float, false>(f, n, x, dirs, sigma, rgb, feat, raw, st);           \
+  }
+  Q(8, 4, 1)
+  Q(16, 16, 2)
+  Q(16, 4, 1)
+  Q(8, 16, 2)
+#undef Q
+  return fail(MR_ERR_UNSUPPORTED, "field shape not instantiated");
+}
+
+}  // namespace mr

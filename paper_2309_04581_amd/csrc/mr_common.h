@@ -80,6 +80,9 @@ struct MeshView {
   Material mat[kMaxMaterials];
 };
 
+// Field MLP engine for FP32 fields: matrix cores unless MESHRF_MLP=valu.
+bool use_valu_mlp();
+
 }  // namespace mr
 
 struct mr_field {
@@ -89,8 +92,13 @@ struct mr_field {
   void* table_dev = nullptr;       // FP32 or FP16 copy
   float* mlp_dev = nullptr;        // FP32 weights
   uint16_t* mlp_bf16_dev = nullptr;
+  uint32_t* frag_f32_dev = nullptr;    // MFMA weight fragments, FP32
+  uint32_t* frag_bf16_dev = nullptr;   // MFMA weight fragments, bf16
   uint32_t* occ_dev = nullptr;
   int occ_res = 0;
+  float* master_dev = nullptr;        // proposal fields: FP32 master table for training
+  float* opt_dev = nullptr;           // proposal fields: gradients and Adam moments
+  int64_t opt_step = 0;
   int64_t n_table = 0, n_mlp = 0;
 };
 

@@ -35,6 +35,9 @@ __global__ __launch_bounds__(256) void k_field_query(FieldView F, const TabT* __
 
 }  // namespace mr
 
-// BF16/MFMA field query (defined with the MFMA kernels).
-mr_status mr_field_query_bf16(const mr_field* f, int64_t n, const float* x, const float* dirs, float* sigma,
-                              float* rgb, float* feat, float* raw, void* stream);
+namespace mr {
+// matrix-core field query and march, and their weight fragments (march_mfma.hip)
+std::vector<uint32_t> build_fragments(const mr_field_desc& d, const float* mlp, bool bf);
+mr_status query_mfma(const mr_field* f, int64_t n, const float* x, const float* dirs, float* sigma, float* rgb,
+                     float* feat, float* raw, hipStream_t st);
+}  // namespace mr

@@ -1,0 +1,223 @@
+// Matrix-core (MFMA) evaluation of the field MLPs on 16-sample tiles.
+//
+// One wave evaluates 16 samples at a time.  Lane l serves sample j = l % 16
+// and, for the hash encoding, the level group g = l / 16 (levels
+// g*NL/4 .. (g+1)*NL/4 - 1).  The features a lane gathers are exactly the
+// B-operand values it owns in v_mfma_f32_16x16x4f32 (one K value per lane)
+// or v_mfma_f32_16x16x16bf16 (four K values per lane) for the product
+// W (M = output rows) x X^T (N = 16 samples).  A 16x16 accumulator leaves
+// row 4g + v, column j in register v of lane l, which is again the B layout of
+// the next layer up to a fixed permutation of K; the weight fragments staged
+// in LDS are written in that permuted order once, on the host.
+#pragma once
+#include "mr_device.h"
+
+namespace mr {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef short s4v __attribute__((ext_vector_type(4)));
+
+// Fragment layout sizes (in 32-bit words) for a field shape.
+template <int NL, int SH, int CL, bool BF>
+struct FragLayout {
+  static constexpr int NF = NL / 2;                          // features per lane (2 per level, NL/4 levels)
+  static constexpr int KS1 = BF ? NF / 4 : NF;               // K steps, density layer 1
+  static constexpr int KS2 = BF ? 4 : 16;                    // K steps over 64 hidden units
+  static constexpr int KSC = BF ? 1 : 4;                     // K steps over the 16 raw outputs
+  static constexpr int W = BF ? 2 : 1;                       // words per lane per fragment
+  static constexpr int L1 = 0;                               // [4 mt][KS1] fragments
+  static constexpr int L2 = L1 + 4 * KS1 * 64 * W;           // [KS2]
+  static constexpr int C1 = L2 + KS2 * 64 * W;               // [4 mt][KSC]
+  static constexpr int C2 = C1 + 4 * KSC * 64 * W;           // [4 mt][KS2] (two hidden colour layers)
+  static constexpr int OUT = C2 + (CL == 2 ? 4 * KS2 * 64 * W : 0);   // FP32 [3][64]
+  static constexpr int SHW = OUT + 192;                      // FP32 [64][SH]: SH columns of colour layer 1
+  static constexpr int TOTAL = SHW + 64 * SH;
+};
+
+// K index carried by (step ks, lane group g, element e) for each layer kind.
+// Layer kinds: 0 density layer 1 (features), 1 layers over 64 hidden units,
+// 2 colour layer 1 over the 16 raw outputs.
+__host__ __device__ inline int frag_k(int kind, bool bf, int nf, int ks, int g, int e) {
+  if (kind == 0) return bf ? g * nf + 4 * ks + e : g * nf + ks;
+  if (kind == 1) return bf ? ks * 16 + 4 * g + e : (ks / 4) * 16 + 4 * g + (ks % 4);
+  return bf ? 4 * g + e : 4 * g + ks;
+}
+
+__device__ __forceinline__ f4v mma(float a, float b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4v mma(uint2 a, uint2 b, f4v c) {
+  s4v av, bv;
+  av[0] = (short)(a.x & 0xFFFF); av[1] = (short)(a.x >> 16); av[2] = (short)(a.y & 0xFFFF); av[3] = (short)(a.y >> 16);
+  bv[0] = (short)(b.x & 0xFFFF); bv[1] = (short)(b.x >> 16); bv[2] = (short)(b.y & 0xFFFF); bv[3] = (short)(b.y >> 16);
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
+}
+
+// round-to-nearest-even FP32 -> bf16 bits
+__device__ __forceinline__ uint32_t bf16_bits(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ uint2 pack_bf16(float a, float b, float c, float d) {
+  return make_uint2(bf16_bits(a) | (bf16_bits(b) << 16), bf16_bits(c) | (bf16_bits(d) << 16));
+}
+
+// Hash features of the lane's level group for one point (2 per level).
+template <int NL, typename TabT>
+__device__ __forceinline__ void encode_group(const FieldView& F, const TabT* __restrict__ table, float px, float py,
+                                             float pz, int g, float* fe) {
+  constexpr int LPG = NL / 4;
+  float xh, yh, zh;
+  to_unit(F, px, py, pz, xh, yh, zh);
+  const size_t T = (size_t)F.table_mask + 1u;
+#pragma unroll
+  for (int ll = 0; ll < LPG; ++ll) {
+    const int l = g * LPG + ll;
+    uint32_t idx[8];
+    float w[8];
+    level_corners(F, l, xh, yh, zh, idx, w);
+    const TabT* tab = table + (size_t)l * T * 2;
+    float2 e[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) e[c] = load_entry<TabT>(tab, idx[c]);
+    float f0 = 0.0f, f1 = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      f0 += w[c] * e[c].x;
+      f1 += w[c] * e[c].y;
+    }
+    fe[2 * ll] = f0;
+    fe[2 * ll + 1] = f1;
+  }
+}
+
+// The MLPs on a 16-sample tile.  fe: this lane's features (its level group,
+// its sample); u[mt][v]: the colour layer-1 contribution of the SH inputs for
+// hidden row mt*16 + 4g + v (per lane's sample); W: fragments in LDS.
+// Returns sigma and rgb of sample j on every lane, and raw in C layout
+// (register v = raw output 4g + v of sample j).
+template <int NL, int SH, int CL, bool BF>
+__device__ __forceinline__ void mlp_tile(const uint32_t* __restrict__ W, const float* fe, const float (&u)[4][4],
+                                         float density_offset, int lane, float& sigma, float rgb[3], f4v& raw) {
+  using LY = FragLayout<NL, SH, CL, BF>;
+  const int g = lane >> 4, j = lane & 15;
+  const f4v zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  // density layer 1: 64 hidden x 16 samples
+  f4v h[4] = {zero, zero, zero, zero};
+  if constexpr (!BF) {
+    const float* Wf = reinterpret_cast<const float*>(W);
+#pragma unroll
+    for (int ks = 0; ks < LY::KS1; ++ks)
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) h[mt] = mma(Wf[LY::L1 + (mt * LY::KS1 + ks) * 64 + lane], fe[ks], h[mt]);
+  } else {
+    const uint2* Wb = reinterpret_cast<const uint2*>(W);
+#pragma unroll
+    for (int ks = 0; ks < LY::KS1; ++ks) {
+      const uint2 b = pack_bf16(fe[4 * ks], fe[4 * ks + 1], fe[4 * ks + 2], fe[4 * ks + 3]);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) h[mt] = mma(Wb[LY::L1 / 2 + (mt * LY::KS1 + ks) * 64 + lane], b, h[mt]);
+    }
+  }
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) h[mt][v] = fmaxf(h[mt][v], 0.0f);
+  // density layer 2: 16 raw outputs
+  raw = zero;
+  if constexpr (!BF) {
+    const float* Wf = reinterpret_cast<const float*>(W);
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) raw = mma(Wf[LY::L2 + ks * 64 + lane], h[ks / 4][ks % 4], raw);
+  } else {
+    const uint2* Wb = reinterpret_cast<const uint2*>(W);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+      raw = mma(Wb[LY::L2 / 2 + ks * 64 + lane], pack_bf16(h[ks][0], h[ks][1], h[ks][2], h[ks][3]), raw);
+  }
+  sigma = softplusf(__shfl(raw[0], j, 64) + density_offset);
+  // colour layer 1: SH part precomputed in u, raw part on the matrix cores
+  f4v c[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) c[mt][v] = u[mt][v];
+  if constexpr (!BF) {
+    const float* Wf = reinterpret_cast<const float*>(W);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) c[mt] = mma(Wf[LY::C1 + (mt * 4 + ks) * 64 + lane], raw[ks], c[mt]);
+  } else {
+    const uint2* Wb = reinterpret_cast<const uint2*>(W);
+    const uint2 b = pack_bf16(raw[0], raw[1], raw[2], raw[3]);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) c[mt] = mma(Wb[LY::C1 / 2 + mt * 64 + lane], b, c[mt]);
+  }
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) c[mt][v] = fmaxf(c[mt][v], 0.0f);
+  if constexpr (CL == 2) {
+    f4v c2[4] = {zero, zero, zero, zero};
+    if constexpr (!BF) {
+      const float* Wf = reinterpret_cast<const float*>(W);
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks)
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) c2[mt] = mma(Wf[LY::C2 + (mt * 16 + ks) * 64 + lane], c[ks / 4][ks % 4], c2[mt]);
+    } else {
+      const uint2* Wb = reinterpret_cast<const uint2*>(W);
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const uint2 b = pack_bf16(c[ks][0], c[ks][1], c[ks][2], c[ks][3]);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) c2[mt] = mma(Wb[LY::C2 / 2 + (mt * 4 + ks) * 64 + lane], b, c2[mt]);
+      }
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) c[mt][v] = fmaxf(c2[mt][v], 0.0f);
+  }
+  // 3-wide output layer on the vector units, reduced over the four lane groups
+  const float* Wo = reinterpret_cast<const float*>(W) + LY::OUT;
+  float o[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    float s = 0.0f;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) s += Wo[ch * 64 + mt * 16 + 4 * g + v] * c[mt][v];
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    o[ch] = s;
+  }
+  rgb[0] = expf(o[0]);
+  rgb[1] = expf(o[1]);
+  rgb[2] = expf(o[2]);
+}
+
+// SH contribution to colour layer 1 for hidden rows mt*16 + 4g + v.
+template <int NL, int SH, int CL, bool BF>
+__device__ __forceinline__ void sh_rows(const uint32_t* __restrict__ W, float dx, float dy, float dz, int lane,
+                                        float (&u)[4][4]) {
+  using LY = FragLayout<NL, SH, CL, BF>;
+  const float* Ws = reinterpret_cast<const float*>(W) + LY::SHW;
+  float shv[SH];
+  sh_eval<SH>(dx, dy, dz, shv);
+  const int g = lane >> 4;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = mt * 16 + 4 * g + v;
+      float s = 0.0f;
+#pragma unroll
+      for (int k = 0; k < SH; ++k) s += Ws[row * SH + k] * shv[k];
+      u[mt][v] = s;
+    }
+}
+
+}  // namespace mr

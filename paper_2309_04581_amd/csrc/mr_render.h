@@ -44,6 +44,10 @@ size_t queue_bytes(int64_t cap);
 RayQueue queue_at(void* base, int64_t cap);
 int device_cus();
 
+// matrix-core march (march_mfma.hip)
+mr_status dispatch_march_mfma(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
+                              unsigned long long* stats, int blocks, hipStream_t st);
+
 // proposal-sampled march (defined with the proposal kernels)
 mr_status dispatch_march_proposal(const mr_field* f, const mr_field* prop, RayQueue q, const int* count, int* work,
                                   const MarchParams& P, int n_prop, int n_fine, unsigned long long* stats, int blocks,

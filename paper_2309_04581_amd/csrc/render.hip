@@ -108,19 +108,29 @@ __global__ void k_init(int64_t n, const float* __restrict__ o, const float* __re
 // ---------------------------------------------------------------------------
 // closest hit of every live ray
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kTraceBlock) void k_trace(RayQueue q, const int* __restrict__ count, BvhView B,
-                                                       float t_far, float span, int32_t* __restrict__ hit_ids,
-                                                       int hit_stride) {
+__global__ __launch_bounds__(kTraceBlock) void k_trace(RayQueue q, const int* __restrict__ count, int* __restrict__ work,
+                                                       int tile, BvhView B, float t_far, float span,
+                                                       int32_t* __restrict__ hit_ids, int hit_stride) {
   __shared__ int stack[kStack * kTraceBlock];
+  __shared__ int s_base;
   const int cnt = *count;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
-    const int seg = q.depth[i] & 0xFFFF;
-    const RayPre r = ray_pre(v3(q.ox[i], q.oy[i], q.oz[i]), v3(q.dx[i], q.dy[i], q.dz[i]));
-    float t = INFINITY;
-    const int p = B.n_prims ? bvh_trace<false>(B, r, seg == 0 ? t_far : span, t, stack + threadIdx.x, kTraceBlock) : -1;
-    q.hit_t[i] = p >= 0 ? t : INFINITY;
-    q.hit_p[i] = p;
-    if (hit_ids && seg < hit_stride) hit_ids[(int64_t)q.rid[i] * hit_stride + seg] = p >= 0 ? __float_as_int(B.tris[3 * p].w) : -1;
+  while (true) {
+    if (threadIdx.x == 0) s_base = atomicAdd(work, tile);
+    __syncthreads();
+    const int base = s_base;
+    __syncthreads();
+    if (base >= cnt) break;
+    const int end = min(base + tile, cnt);
+    for (int i = base + threadIdx.x; i < end; i += blockDim.x) {
+      const int seg = q.depth[i] & 0xFFFF;
+      const RayPre r = ray_pre(v3(q.ox[i], q.oy[i], q.oz[i]), v3(q.dx[i], q.dy[i], q.dz[i]));
+      float t = INFINITY;
+      const int p = B.n_prims ? bvh_trace<false>(B, r, seg == 0 ? t_far : span, t, stack + threadIdx.x, kTraceBlock) : -1;
+      q.hit_t[i] = p >= 0 ? t : INFINITY;
+      q.hit_p[i] = p;
+      if (hit_ids && seg < hit_stride)
+        hit_ids[(int64_t)q.rid[i] * hit_stride + seg] = p >= 0 ? __float_as_int(B.tris[3 * p].w) : -1;
+    }
   }
 }
 
@@ -263,19 +273,28 @@ __device__ __forceinline__ void finalize(const RenderOut& out, int rid, float tr
   out.bounces[rid] = bounces;
 }
 
-__global__ __launch_bounds__(kTraceBlock) void k_shade(RayQueue qi, const int* __restrict__ count_in, RayQueue qo,
+__global__ __launch_bounds__(kTraceBlock) void k_shade(RayQueue qi, const int* __restrict__ count_in,
+                                                       int* __restrict__ work, int tile, RayQueue qo,
                                                        int* __restrict__ count_out, MeshView M, ShadeParams S,
                                                        RenderOut out, unsigned long long* __restrict__ stats) {
   __shared__ int stack[kStack * kTraceBlock];
+  __shared__ int s_base;
   const int cnt = *count_in;
   const int lane = threadIdx.x & 63;
   unsigned long long n_seg = 0, n_shadow = 0, n_scat = 0;
-  for (int i0 = blockIdx.x * blockDim.x; i0 < cnt; i0 += gridDim.x * blockDim.x) {
+  while (true) {
+  if (threadIdx.x == 0) s_base = atomicAdd(work, tile);
+  __syncthreads();
+  const int tbase = s_base;
+  __syncthreads();
+  if (tbase >= cnt) break;
+  const int tend = min(tbase + tile, cnt);
+  for (int i0 = tbase; i0 < tend; i0 += blockDim.x) {
     const int i = i0 + threadIdx.x;
     bool keep = false;
     float nox = 0, noy = 0, noz = 0, ndx = 0, ndy = 0, ndz = 0, tr = 0, tg = 0, tb = 0, lr = 0, lg = 0, lb = 0;
     int rid = 0, ndepth = 0;
-    if (i < cnt) {
+    if (i < tend) {
       ++n_seg;
       rid = qi.rid[i];
       const int depth = qi.depth[i];
@@ -401,6 +420,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade(RayQueue qi, const int* _
       qo.depth[slot] = ndepth;
     }
   }
+  }
   if (stats) {
     // per-wave sums, one atomic each
     unsigned long long a = n_seg, b = n_shadow, c = n_scat;
@@ -522,6 +542,11 @@ mr_status validate_render(const mr_field* field, const mr_mesh* mesh, int64_t n,
       return fail(MR_ERR_INVALID_ARG, "n_proposal and n_fine must be in 1..64");
   }
   if (field && field->view.c_layers == 0) return fail(MR_ERR_INVALID_ARG, "field is a proposal field");
+  if (opts->march_blocks_per_cu < 0 || opts->march_blocks_per_cu > 64 || opts->stage_blocks_per_cu < 0 ||
+      opts->stage_blocks_per_cu > 64)
+    return fail(MR_ERR_INVALID_ARG, "blocks per compute unit must be in 0..64");
+  if (opts->stage_tile < 0 || opts->stage_tile % kTraceBlock != 0 || opts->stage_tile > (1 << 20))
+    return fail(MR_ERR_INVALID_ARG, "stage_tile must be a multiple of 128 (or 0)");
   if (opts->use_occupancy && field && !field->occ_dev)
     return fail(MR_ERR_STATE, "use_occupancy set but the field has no occupancy grid");
   return MR_OK;
@@ -548,13 +573,15 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
   const int64_t cap = ((n + 63) / 64) * 64;
   char* ws = reinterpret_cast<char*>(workspace);
   int* counts = reinterpret_cast<int*>(ws);                 // [kMaxBounces + 2]
-  int* work = counts + (kMaxBounces + 2);                   // [kMaxBounces + 2]
+  int* work = counts + (kMaxBounces + 2);                   // march ray queue heads
+  int* twork = work + (kMaxBounces + 2);                    // closest-hit tile queue heads
+  int* swork = twork + (kMaxBounces + 2);                   // shade tile queue heads
   RayQueue Q[2] = {queue_at(ws + kHeaderBytes, cap), queue_at(ws + kHeaderBytes + queue_bytes(cap), cap)};
   unsigned long long* stats = reinterpret_cast<unsigned long long*>(out->counters);
 
   const int init_blocks = (int)std::min<int64_t>((n + 255) / 256, 65535);
   hipLaunchKernelGGL(k_init, dim3(init_blocks), dim3(256), 0, st, n, origins, dirs, per_ray_max_bounces, max_bounces,
-                     Q[0], counts, 2 * (kMaxBounces + 2), out->hit_ids, out->hit_ids ? out->hit_stride : 0, stats);
+                     Q[0], counts, 4 * (kMaxBounces + 2), out->hit_ids, out->hit_ids ? out->hit_stride : 0, stats);
   MR_HIP(hipGetLastError());
 
   MeshView mv;
@@ -588,15 +615,18 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
   ro.bounces = out->bounces;
 
   const int cus = device_cus();
-  const int trace_blocks = (int)std::min<int64_t>((n + kTraceBlock - 1) / kTraceBlock, (int64_t)cus * 16);
-  const int march_blocks = (int)std::min<int64_t>((n + 3) / 4, (int64_t)cus * 8);
+  const int tile = opts->stage_tile > 0 ? opts->stage_tile : 512;
+  const int sbpc = opts->stage_blocks_per_cu > 0 ? opts->stage_blocks_per_cu : 16;
+  const int mbpc = opts->march_blocks_per_cu > 0 ? opts->march_blocks_per_cu : 8;
+  const int trace_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + tile - 1) / tile, (int64_t)cus * sbpc));
+  const int march_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 3) / 4, (int64_t)cus * mbpc));
   for (int b = 0; b <= max_bounces; ++b) {
     RayQueue& qi = Q[b & 1];
     RayQueue& qo = Q[(b + 1) & 1];
     {
       StageTimer tm(0, st);
-      hipLaunchKernelGGL(k_trace, dim3(trace_blocks), dim3(kTraceBlock), 0, st, qi, counts + b, mv.bvh, opts->t_far,
-                         P.span, out->hit_ids, out->hit_ids ? out->hit_stride : 0);
+      hipLaunchKernelGGL(k_trace, dim3(trace_blocks), dim3(kTraceBlock), 0, st, qi, counts + b, twork + b, tile, mv.bvh,
+                         opts->t_far, P.span, out->hit_ids, out->hit_ids ? out->hit_stride : 0);
       MR_HIP(hipGetLastError());
     }
     if (field) {
@@ -604,14 +634,16 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
       if (opts->sampler == MR_SAMPLER_PROPOSAL)
         s = dispatch_march_proposal(field, opts->proposal, qi, counts + b, work + b, P, opts->n_proposal, opts->n_fine,
                                     stats, march_blocks, st);
-      else
+      else if (field->view.mlp_dtype == MR_F32 && use_valu_mlp())
         s = dispatch_march(field, qi, counts + b, work + b, P, stats, march_blocks, st);
+      else
+        s = dispatch_march_mfma(field, qi, counts + b, work + b, P, stats, march_blocks, st);
       if (s != MR_OK) return s;
     }
     {
       StageTimer tm(2, st);
-      hipLaunchKernelGGL(k_shade, dim3(trace_blocks), dim3(kTraceBlock), 0, st, qi, counts + b, qo, counts + b + 1, mv,
-                         S, ro, stats);
+      hipLaunchKernelGGL(k_shade, dim3(trace_blocks), dim3(kTraceBlock), 0, st, qi, counts + b, swork + b, tile, qo,
+                         counts + b + 1, mv, S, ro, stats);
       MR_HIP(hipGetLastError());
     }
   }
@@ -698,5 +730,146 @@ extern "C" mr_status mr_rays_from_cameras(const float* host_cams, int32_t n_cams
     MR_HIP(hipGetLastError());
     base += off;
   }
+  return MR_OK;
+}
+
+
+struct mr_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" mr_status mr_render_graph_create(const mr_field* field, const mr_mesh* mesh, int64_t n, const float* origins,
+                                            const float* dirs, int32_t max_bounces, const int32_t* per_ray_max_bounces,
+                                            const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
+                                            mr_render_out* out, void* workspace, size_t workspace_bytes,
+                                            mr_graph** graph) {
+  if (!graph) return fail(MR_ERR_INVALID_ARG, "null graph");
+  if (g_prof.on) return fail(MR_ERR_STATE, "kernel timing is on; disable it before capturing");
+  mr_status s = validate_render(field, mesh, n, origins, dirs, max_bounces, host_lights, n_lights, opts, out);
+  if (s != MR_OK) return s;
+  if (!workspace || workspace_bytes < mr_render_workspace_size(n))
+    return fail(MR_ERR_INVALID_ARG, "workspace smaller than mr_render_workspace_size(n)");
+  hipStream_t st = nullptr;
+  MR_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  mr_graph* g = new mr_graph();
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipStreamDestroy(st);
+    delete g;
+    return fail(MR_ERR_DEVICE, "hipStreamBeginCapture failed");
+  }
+  s = mr_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, host_lights, n_lights, opts, out,
+                workspace, workspace_bytes, st);
+  const hipError_t e = hipStreamEndCapture(st, &g->graph);
+  (void)hipStreamDestroy(st);
+  if (s != MR_OK || e != hipSuccess) {
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return s != MR_OK ? s : fail(MR_ERR_DEVICE, "hipStreamEndCapture failed");
+  }
+  if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g->graph);
+    delete g;
+    return fail(MR_ERR_DEVICE, "hipGraphInstantiate failed");
+  }
+  *graph = g;
+  return MR_OK;
+}
+
+extern "C" mr_status mr_graph_launch(mr_graph* graph, void* stream) {
+  if (!graph || !graph->exec) return fail(MR_ERR_INVALID_ARG, "null graph");
+  MR_HIP(hipGraphLaunch(graph->exec, (hipStream_t)stream));
+  return MR_OK;
+}
+
+extern "C" mr_status mr_graph_destroy(mr_graph* graph) {
+  if (!graph) return MR_OK;
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  delete graph;
+  return MR_OK;
+}
+
+extern "C" mr_status mr_autotune_render(const mr_field* field, const mr_mesh* mesh, int64_t n, const float* origins,
+                                        const float* dirs, int32_t max_bounces, const int32_t* per_ray_max_bounces,
+                                        const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
+                                        mr_render_out* out, void* workspace, size_t workspace_bytes,
+                                        const int32_t* host_march_cands, int32_t n_march,
+                                        const int32_t* host_stage_cands, int32_t n_stage,
+                                        const int32_t* host_tile_cands, int32_t n_tile, int32_t reps, int32_t* best,
+                                        float* best_ms, void* stream) {
+  if (!opts || !best || !best_ms) return fail(MR_ERR_INVALID_ARG, "null argument");
+  if (n_march < 1 || n_stage < 1 || n_tile < 1 || !host_march_cands || !host_stage_cands || !host_tile_cands)
+    return fail(MR_ERR_INVALID_ARG, "need at least one candidate of each kind");
+  if (reps < 1 || reps > 100) return fail(MR_ERR_INVALID_ARG, "reps must be in 1..100");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t a = nullptr, b = nullptr;
+  MR_HIP(hipEventCreate(&a));
+  MR_HIP(hipEventCreate(&b));
+  float best_t = INFINITY;
+  mr_status s = MR_OK;
+  for (int im = 0; im < n_march && s == MR_OK; ++im)
+    for (int is = 0; is < n_stage && s == MR_OK; ++is)
+      for (int it = 0; it < n_tile && s == MR_OK; ++it) {
+        mr_render_opts o = *opts;
+        o.march_blocks_per_cu = host_march_cands[im];
+        o.stage_blocks_per_cu = host_stage_cands[is];
+        o.stage_tile = host_tile_cands[it];
+        s = mr_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, host_lights, n_lights, &o, out,
+                      workspace, workspace_bytes, stream);
+        if (s != MR_OK) break;
+        if (hipEventRecord(a, st) != hipSuccess) { s = fail(MR_ERR_DEVICE, "event record"); break; }
+        for (int r = 0; r < reps && s == MR_OK; ++r)
+          s = mr_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, host_lights, n_lights, &o,
+                        out, workspace, workspace_bytes, stream);
+        if (s != MR_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+            hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+          s = fail(MR_ERR_DEVICE, "event timing");
+          break;
+        }
+        ms /= reps;
+        if (ms < best_t) {
+          best_t = ms;
+          best[0] = o.march_blocks_per_cu;
+          best[1] = o.stage_blocks_per_cu;
+          best[2] = o.stage_tile;
+        }
+      }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (s == MR_OK) *best_ms = best_t;
+  return s;
+}
+
+namespace {
+struct CamLimits {
+  int n;
+  int lim[64];
+};
+__global__ void k_cam_limits(const int32_t* __restrict__ ci, int64_t n, CamLimits L, int32_t* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = ci[i];
+    out[i] = (c >= 0 && c < L.n) ? L.lim[c] : 0;
+  }
+}
+}  // namespace
+
+extern "C" mr_status mr_camera_bounce_limits(const int32_t* cam_index, int64_t n, const int32_t* host_cam_limits,
+                                             int32_t n_cams, int32_t* out, void* stream) {
+  if (n < 0) return fail(MR_ERR_INVALID_ARG, "n < 0");
+  if (n == 0) return MR_OK;
+  if (!cam_index || !out || !host_cam_limits) return fail(MR_ERR_INVALID_ARG, "null array");
+  if (n_cams < 1 || n_cams > 64) return fail(MR_ERR_INVALID_ARG, "n_cams must be in 1..64");
+  CamLimits L;
+  L.n = n_cams;
+  for (int c = 0; c < n_cams; ++c) {
+    if (host_cam_limits[c] < 0 || host_cam_limits[c] > kMaxBounces) return fail(MR_ERR_INVALID_ARG, "limit out of range");
+    L.lim[c] = host_cam_limits[c];
+  }
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65535);
+  hipLaunchKernelGGL(k_cam_limits, dim3(blocks), dim3(256), 0, (hipStream_t)stream, cam_index, n, L, out);
+  MR_HIP(hipGetLastError());
   return MR_OK;
 }

@@ -27,6 +27,9 @@ EXPORTED = [
     "mr_field_build_occupancy", "mr_field_params", "mr_mesh_build_bvh", "mr_mesh_refit",
     "mr_mesh_destroy", "mr_mesh_info", "mr_mesh_closest_hit", "mr_render_workspace_size",
     "mr_render", "mr_rays_from_cameras", "mr_profile_enable", "mr_profile_read",
+    "mr_proposal_targets", "mr_proposal_grad", "mr_proposal_train_step",
+    "mr_render_graph_create", "mr_graph_launch", "mr_graph_destroy", "mr_autotune_render",
+    "mr_camera_bounce_limits",
 ]
 
 
@@ -59,7 +62,13 @@ class RenderOpts(C.Structure):
     _fields_ = [("t_near", C.c_float), ("t_far", C.c_float), ("n_samples", C.c_int32),
                 ("sampler", C.c_int32), ("proposal", C.c_void_p), ("n_proposal", C.c_int32),
                 ("n_fine", C.c_int32), ("use_occupancy", C.c_int32), ("rr_after", C.c_int32),
-                ("t_min_throughput", C.c_float), ("seed", C.c_uint32)]
+                ("t_min_throughput", C.c_float), ("seed", C.c_uint32),
+                ("march_blocks_per_cu", C.c_int32), ("stage_blocks_per_cu", C.c_int32),
+                ("stage_tile", C.c_int32)]
+
+
+class Adam(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
 
 
 class RenderOut(C.Structure):
@@ -346,3 +355,128 @@ def mr_profile_read():
     n = (C.c_int64 * 4)()
     _check(lib().mr_profile_read(ms, n))
     return list(ms), list(n)
+
+
+def mr_proposal_targets(fine, n, origins, dirs, t_near, t_far, n_samples, n_bins, lohi, targets, stream=None):
+    _check(lib().mr_proposal_targets(fine, C.c_int64(n), _ptr(origins), _ptr(dirs), C.c_float(t_near),
+                                     C.c_float(t_far), C.c_int32(n_samples), C.c_int32(n_bins),
+                                     _ptr(lohi), _ptr(targets), _stream(stream)))
+
+
+def mr_proposal_grad(prop, n, origins, dirs, lohi, targets, n_bins, loss, g_table, g_mlp, stream=None):
+    _check(lib().mr_proposal_grad(prop, C.c_int64(n), _ptr(origins), _ptr(dirs), _ptr(lohi),
+                                  _ptr(targets), C.c_int32(n_bins), _ptr(loss), _ptr(g_table),
+                                  _ptr(g_mlp), _stream(stream)))
+
+
+def mr_proposal_train_step(prop, n, origins, dirs, lohi, targets, n_bins, adam, loss, stream=None):
+    _check(lib().mr_proposal_train_step(prop, C.c_int64(n), _ptr(origins), _ptr(dirs), _ptr(lohi),
+                                        _ptr(targets), C.c_int32(n_bins), C.byref(adam), _ptr(loss),
+                                        _stream(stream)))
+
+
+class ProposalTrainer:
+    """Targets and Adam steps for a proposal field (bookkeeping only: the
+    targets, loss, gradients and updates are computed by the library)."""
+
+    def __init__(self, proposal: "Field", n_bins=32, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15):
+        import torch
+        self.prop = proposal
+        self.n_bins = n_bins
+        self.adam = Adam()
+        self.adam.lr, self.adam.beta1, self.adam.beta2, self.adam.eps = lr, beta1, beta2, eps
+        self.loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+
+    def targets(self, fine: "Field", origins, dirs, t_near, t_far, n_samples):
+        import torch
+        n = origins.shape[0]
+        lohi = torch.empty(n, 2, dtype=torch.float32, device="cuda")
+        tgt = torch.empty(n, self.n_bins, dtype=torch.float32, device="cuda")
+        mr_proposal_targets(fine.handle, n, origins, dirs, t_near, t_far, n_samples, self.n_bins, lohi, tgt)
+        return lohi, tgt
+
+    def step(self, origins, dirs, lohi, targets):
+        mr_proposal_train_step(self.prop.handle, origins.shape[0], origins, dirs, lohi, targets,
+                               self.n_bins, self.adam, self.loss)
+        return self.loss
+
+    def train(self, origins, dirs, lohi, targets, steps, batch):
+        """Cycle through consecutive slices of a training set (rows already in
+        random order); returns the per-step loss history (device tensor)."""
+        import torch
+        n = origins.shape[0]
+        hist = torch.empty(steps, dtype=torch.float32, device="cuda")
+        nb = max(1, n // batch)
+        for s in range(steps):
+            b = (s % nb) * batch
+            e = min(n, b + batch)
+            self.step(origins[b:e], dirs[b:e], lohi[b:e], targets[b:e])
+            hist[s:s + 1].copy_(self.loss)
+        return hist
+
+
+def _lights_arr(lights):
+    nl = len(lights)
+    arr = (Light * max(nl, 1))()
+    for i, row in enumerate(lights):
+        arr[i].pos = (C.c_float * 3)(*[float(x) for x in row[:3]])
+        arr[i].intensity = (C.c_float * 3)(*[float(x) for x in row[3:6]])
+    return arr, nl
+
+
+def mr_render_graph_create(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, lights, opts, out,
+                           workspace, workspace_bytes):
+    arr, nl = _lights_arr(lights)
+    g = C.c_void_p()
+    _check(lib().mr_render_graph_create(field, mesh, C.c_int64(n), _ptr(origins), _ptr(dirs),
+                                        C.c_int32(max_bounces), _ptr(per_ray_max_bounces), arr,
+                                        C.c_int32(nl), C.byref(opts), C.byref(out), _ptr(workspace),
+                                        C.c_size_t(workspace_bytes), C.byref(g)))
+    return g
+
+
+def mr_graph_launch(graph, stream=None):
+    _check(lib().mr_graph_launch(graph, _stream(stream)))
+
+
+def mr_graph_destroy(graph):
+    _check(lib().mr_graph_destroy(graph))
+
+
+def mr_autotune_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, lights, opts, out,
+                       workspace, workspace_bytes, march_cands, stage_cands, tile_cands, reps=2, stream=None):
+    arr, nl = _lights_arr(lights)
+    mc = np.ascontiguousarray(march_cands, dtype=np.int32)
+    sc = np.ascontiguousarray(stage_cands, dtype=np.int32)
+    tc = np.ascontiguousarray(tile_cands, dtype=np.int32)
+    best = (C.c_int32 * 3)()
+    ms = C.c_float()
+    _check(lib().mr_autotune_render(field, mesh, C.c_int64(n), _ptr(origins), _ptr(dirs), C.c_int32(max_bounces),
+                                    _ptr(per_ray_max_bounces), arr, C.c_int32(nl), C.byref(opts), C.byref(out),
+                                    _ptr(workspace), C.c_size_t(workspace_bytes), _ptr(mc), C.c_int32(len(mc)),
+                                    _ptr(sc), C.c_int32(len(sc)), _ptr(tc), C.c_int32(len(tc)), C.c_int32(reps),
+                                    best, C.byref(ms), _stream(stream)))
+    return tuple(best), ms.value
+
+
+def mr_camera_bounce_limits(cam_index, n, cam_limits, out, stream=None):
+    lim = np.ascontiguousarray(cam_limits, dtype=np.int32)
+    _check(lib().mr_camera_bounce_limits(_ptr(cam_index), C.c_int64(n), _ptr(lim), C.c_int32(len(lim)),
+                                         _ptr(out), _stream(stream)))
+
+
+def autotune_cached(cache_path, key, tune):
+    """Launch shapes from a JSON cache keyed by (arch, workload); `tune()` runs
+    the autotuner on a miss and returns ((march, stage, tile), ms)."""
+    import json
+    cache = {}
+    if os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+    if key in cache:
+        return tuple(cache[key]["best"]), cache[key]["ms"], True
+    best, ms = tune()
+    cache[key] = {"best": list(best), "ms": ms}
+    with open(cache_path, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    return best, ms, False

@@ -190,6 +190,32 @@ def mid_field(seed=2, table_amp=1e-4, density_offset=1.0) -> Field:
                       table_amp=table_amp, density_offset=density_offset)
 
 
+def shell_field(seed=3, radius=0.5, width=0.08, gain=30.0, density_offset=-4.0) -> Field:
+    """The tiny field layout with a thin spherical shell of density: the
+    coarsest (dense) level stores exp(-((|p| - radius)/width)^2) at each grid
+    vertex, the density MLP routes that feature to its first output with gain
+    `gain`, and the other weights and levels are small seeded noise.  Far from
+    the shell sigma = softplus(offset); on it sigma is about softplus(gain +
+    offset).  A concentrated density for proposal-sampler experiments."""
+    f = tiny_field(seed=seed, table_amp=1e-3, density_offset=density_offset)
+    rng = np.random.default_rng(seed + 1000)
+    N = int(f.resolutions[0])
+    g = np.linspace(-1.0, 1.0, N + 1)
+    Z, Y, X = np.meshgrid(g, g, g, indexing="ij")
+    r = np.sqrt(X ** 2 + Y ** 2 + Z ** 2)
+    vals = np.exp(-((r - radius) / width) ** 2).ravel()
+    f.table[0, :vals.size, 0] = vals.astype(np.float32)
+    f.table[0, :vals.size, 1] = 0.0
+    W1 = f.mlp[:f.d_hidden * f.d_in].reshape(f.d_hidden, f.d_in)
+    W1[:] = rng.uniform(-0.01, 0.01, size=W1.shape)
+    W1[0, 0] = 1.0
+    off = f.d_hidden * f.d_in
+    W2 = f.mlp[off:off + f.d_out * f.d_hidden].reshape(f.d_out, f.d_hidden)
+    W2[:] = rng.uniform(-0.01, 0.01, size=W2.shape)
+    W2[0, 0] = gain
+    return f
+
+
 def make_proposal(seed=5, n_levels=5, feats=2, log2_table=17, n_min=16, n_max=256,
                   hidden=16, table_amp=1e-4, density_offset=0.0) -> Proposal:
     rng = np.random.default_rng(seed)

@@ -1,0 +1,97 @@
+"""Reduced-precision field evaluation: FP16 hash table and BF16 MLPs on the
+matrix cores with FP32 accumulation, compositing, intersection and Fresnel
+in FP32.  Hit ids and bounce counts stay bit-exact against the FP64 oracle on
+non-tie rays; the radiance error is bounded (and reported by bench.py)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2309_04581_amd import scenegen as sg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from test_gpu_parity import (assert_close_rel, compare_render, dev, gpu_render, host,  # noqa: E402
+                             lattice_points, mr, oracle_camera_rays)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    orc.build(force=False)
+
+
+def bf16_round(a):
+    """Round-to-nearest-even to bfloat16, returned as float32."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def rounded_field(f):
+    g = sg.Field(**{k: getattr(f, k) for k in f.__dataclass_fields__})
+    g.table = f.table.astype(np.float16).astype(np.float32)
+    g.mlp = bf16_round(f.mlp)
+    return g
+
+
+def test_fp16_table_is_round_to_nearest_with_subnormals():
+    """The device FP16 table equals numpy's float16 rounding bit for bit
+    (about 61% of U(-1e-4, 1e-4) entries are FP16 subnormals)."""
+    M = mr()
+    f = sg.tiny_field()
+    F = M.Field(f, table_dtype=M.MR_F16, mlp_dtype=M.MR_BF16)
+    tab_ptr, _, n_table, _ = M.mr_field_params(F.handle)
+    t = torch.empty(n_table, dtype=torch.float16, device="cuda")
+    import ctypes
+    torch.cuda.synchronize()
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    assert hip.hipMemcpy(ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(tab_ptr), ctypes.c_size_t(2 * n_table), 3) == 0
+    got = host(t).view(np.uint16)
+    want = f.table.ravel().astype(np.float16).view(np.uint16)
+    np.testing.assert_array_equal(got, want)
+    sub = np.abs(f.table.ravel().astype(np.float16).astype(np.float32)) < 6.103515625e-05
+    assert sub.mean() > 0.5
+
+
+@pytest.mark.parametrize("kind", ["tiny", "mid"])
+def test_bf16_field_query_close_to_rounded_parameters(kind):
+    """Against the FP64 oracle run on the FP16/BF16-rounded parameters, the
+    remaining error is the BF16 rounding of activations (2^-9 relative per
+    layer input): sigma within 1e-2, rgb within 5e-2 relative."""
+    M = mr()
+    f = sg.tiny_field(table_amp=1.0) if kind == "tiny" else sg.mid_field(table_amp=1.0)
+    x, d = lattice_points(f, 3000, seed=201)
+    F = M.Field(f, table_dtype=M.MR_F16, mlp_dtype=M.MR_BF16)
+    out = F.query(dev(x), dev(d))
+    ref = orc.field_batch(rounded_field(f), x, d)
+    assert_close_rel(host(out["sigma"]), ref["sigma"], 1e-2, 1e-4, "bf16 sigma")
+    assert_close_rel(host(out["rgb"]), ref["rgb"], 5e-2, 1e-4, "bf16 rgb")
+    full = orc.field_batch(f, x, d)
+    err = np.abs(host(out["rgb"]) - full["rgb"]) / full["rgb"]
+    print(f"{kind}: rgb rel. error vs FP64 master params: max {err.max():.3e} mean {err.mean():.3e}")
+
+
+def test_reduced_precision_render_keeps_hits_exact():
+    """The tiny workload with FP16 table + BF16 MLPs: geometry decisions are
+    unchanged (bit-exact hit ids and bounces on non-tie rays); radiance within
+    1e-2 relative of the FP64 oracle on master parameters."""
+    sc = sg.tiny_scene()
+    o, d = oracle_camera_rays(sc)
+    r = orc.render(sc, o, d)
+    M = mr()
+    g = gpu_render(sc, o, d, table_dtype=M.MR_F16, mlp_dtype=M.MR_BF16)
+    compare_render(g, r, "fp16/bf16 tiny", rtol=1e-2, atol=1e-5)
+    ok = ~r["tie"]
+    rel = np.abs(g["radiance"][ok] - r["radiance"][ok]) / np.abs(r["radiance"][ok])
+    print(f"fp16/bf16 tiny radiance rel. error: max {rel.max():.3e} mean {rel.mean():.3e}")
+
+
+def test_fp32_engines_agree():
+    """The matrix-core FP32 MLP (default) and the rounding order of the
+    oracle agree to 1e-4 on the mid workload at 40x40."""
+    sc = sg.mid_scene(width=40, height=40)
+    o, d = oracle_camera_rays(sc)
+    r = orc.render(sc, o, d)
+    compare_render(gpu_render(sc, o, d), r, "mid fp32 mfma")

@@ -677,3 +677,27 @@ def test_proposal_loss_zero_when_proposal_dominates():
     o, d, lohi, tgt = _prop_batch(4, 23)
     loss, gt, gm = orc.proposal_loss(prop, o, d, lohi, np.zeros_like(tgt))
     assert loss == 0.0 and not gt.any() and not gm.any()
+
+
+def test_proposal_targets_sum_to_opacity():
+    """The binned plain-marcher weights of a segment sum to 1 - T over it; for
+    a constant medium that is 1 - exp(-sigma l) for the clipped chord l, and
+    every bin is non-negative."""
+    f = _constant_field()
+    sigma = math.log1p(math.e)
+    o, d = sg.random_rays(50, seed=25)
+    lohi, tgt = orc.proposal_targets(f, o, d, 0.05, 4.0, 256, 32)
+    for k in range(len(o)):
+        ell = _chord(o[k].astype(np.float64), d[k].astype(np.float64), 0.05, 4.0)
+        assert tgt[k].sum() == pytest.approx(1 - math.exp(-sigma * ell), rel=1e-12, abs=1e-15)
+        if ell > 0:
+            assert lohi[k, 1] - lohi[k, 0] == pytest.approx(ell, rel=1e-12)
+    assert np.all(tgt >= 0)
+    # a shell of density: the mass sits in the bins that cross the shell
+    shell = sg.shell_field()
+    o = np.array([[0.0, 0.0, -2.5]], np.float32)
+    d = np.array([[0.0, 0.0, 1.0]], np.float32)
+    lohi, tgt = orc.proposal_targets(shell, o, d, 0.05, 4.0, 256, 32)
+    centers = lohi[0, 0] + (np.arange(32) + 0.5) * (lohi[0, 1] - lohi[0, 0]) / 32
+    peak = centers[np.argmax(tgt[0])]
+    assert abs(peak - 2.0) < 0.1                      # the front of the shell (|z| = 0.5) at t = 2
