@@ -424,20 +424,39 @@ static int slab(const orc_field* f, const double o[3], const double d[3], double
   return hi > lo;
 }
 
-/* Occupancy lookup; a sample within tie_eps (in cells) of a cell face is a
- * tie, since single precision may place it in the neighbouring cell. */
+/* Occupancy lookup; a sample within tie_eps of a face between an occupied and
+ * an empty cell is a tie, since single precision may place it on the other
+ * side (a face between cells of equal state changes nothing). */
+static int occ_cell(const orc_opts* opt, const int c[3]) {
+  int R = opt->occ_res;
+  for (int k = 0; k < 3; ++k)
+    if (c[k] < 0 || c[k] >= R) return -1;
+  return opt->occ[((int64_t)c[2] * R + c[1]) * R + c[0]] != 0;
+}
+
 static int occupied(const orc_opts* opt, const orc_field* f, const double x[3], int* tie) {
   if (!opt->occ) return 1;
   int R = opt->occ_res;
   int c[3];
+  double xr[3];
   for (int k = 0; k < 3; ++k) {
     double xh = (x[k] - f->aabb_min[k]) / (f->aabb_max[k] - f->aabb_min[k]);
-    double xr = xh * R;
-    if (fabs(xr - floor(xr + 0.5)) < opt->tie_eps * R) *tie = 1;
-    int ci = (int)floor(xr);
+    xr[k] = xh * R;
+    int ci = (int)floor(xr[k]);
     c[k] = ci < 0 ? 0 : (ci >= R ? R - 1 : ci);
   }
-  return opt->occ[((int64_t)c[2] * R + c[1]) * R + c[0]] != 0;
+  int here = occ_cell(opt, c);
+  for (int k = 0; k < 3; ++k) {
+    double face = floor(xr[k] + 0.5);
+    if (fabs(xr[k] - face) < opt->tie_eps * R) {
+      int nb[3] = {c[0], c[1], c[2]};
+      nb[k] = (face > xr[k] || face == (double)c[k] + 1.0) ? c[k] + 1 : c[k] - 1;
+      if (nb[k] == c[k]) continue;
+      int there = occ_cell(opt, nb);
+      if (there >= 0 && there != here) *tie = 1;
+    }
+  }
+  return here;
 }
 
 /* Composite one interval [a, b] at its midpoint: alpha = 1 - exp(-sigma D),
