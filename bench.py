@@ -41,6 +41,143 @@ def gather_bytes(f, bytes_per_value=4):
     return f.n_levels * 8 * f.feats * bytes_per_value
 
 
+def psnr_tonemapped(a, b):
+    """PSNR after Reinhard L/(1+L) and the sRGB transfer curve, peak 1."""
+    import numpy as np
+
+    def psi(L):
+        x = np.clip(L / (1.0 + L), 0.0, 1.0)
+        return np.where(x <= 0.0031308, 12.92 * x, 1.055 * np.power(x, 1 / 2.4) - 0.055)
+    mse = float(np.mean((psi(np.asarray(a, np.float64)) - psi(np.asarray(b, np.float64))) ** 2))
+    return float("inf") if mse == 0 else 10.0 * math.log10(1.0 / mse)
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def proposal_variant(M, sg, sc, F_plain, G, cams, n, plain_img, steps, warmup, train_steps):
+    """Proposal (32 + 32) with FP16 table and BF16 MLPs on the same workload,
+    trained on the plain marcher's histograms; PSNR against the plain image."""
+    import torch
+    F16 = M.Field(sc.field, table_dtype=M.MR_F16, mlp_dtype=M.MR_BF16)
+    P = M.Field(sg.make_proposal(), table_dtype=M.MR_F16)
+    T = M.ProposalTrainer(P)
+    to, td = sg.random_rays(1 << 18, seed=505)
+    to = torch.from_numpy(to).cuda()
+    td = torch.from_numpy(td).cuda()
+    lohi, tgt = T.targets(F_plain, to, td, sc.t_near, sc.t_far, sc.n_samples)
+    t0 = time.perf_counter()
+    hist = T.train(to, td, lohi, tgt, steps=train_steps, batch=1 << 14).cpu().numpy()
+    train_s = time.perf_counter() - t0
+    o = torch.empty(n, 3, device="cuda")
+    d = torch.empty(n, 3, device="cuda")
+    R = M.Renderer(n, sc.max_bounces, with_hits=False)
+    opts = M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P)
+
+    def step():
+        M.mr_rays_from_cameras(cams, o, d, None, n)
+        R.render(F16, G, o, d, sc.lights, opts)
+    ms = timed(step, steps, warmup)
+    img = R.radiance.cpu().numpy()
+    return {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms, 3),
+            "psnr_db_vs_plain_fp32": round(psnr_tonemapped(img, plain_img), 2),
+            "samples": "32 proposal + 32 fine per segment", "table": "fp16", "mlp": "bf16 (MFMA, fp32 accumulate)",
+            "train": {"steps": train_steps, "batch_segments": 1 << 14, "loss_first": float(hist[0]),
+                      "loss_last": float(hist[-1]), "seconds": round(train_s, 2)}}
+
+
+def precision_report(M, sg):
+    """Tiny workload with FP16 table + BF16 MLPs against the FP64 oracle."""
+    import numpy as np
+    import torch
+    from oracle import oracle as orc
+    sc = sg.tiny_scene()
+    cam = sg.cameras_array(sc.cameras)[0]
+    o, d = orc.rays_from_camera(cam)
+    o, d = o.astype(np.float32), d.astype(np.float32)
+    ref = orc.render(sc, o, d)
+    out = {}
+    for name, td, md in (("fp32", M.MR_F32, M.MR_F32), ("fp16_table_bf16_mlp", M.MR_F16, M.MR_BF16)):
+        F, G = M.Field(sc.field, td, md), M.Mesh(sc.mesh)
+        R = M.Renderer(len(o), sc.max_bounces)
+        R.render(F, G, torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), sc.lights, M.make_opts(sc))
+        torch.cuda.synchronize()
+        ok = ~ref["tie"]
+        L = R.radiance.cpu().numpy().astype(np.float64)[ok]
+        rel = np.abs(L - ref["radiance"][ok]) / np.abs(ref["radiance"][ok])
+        same = np.array_equal(R.hit_ids.cpu().numpy()[ok], ref["hit_ids"][ok])
+        out[name] = {"max_rel_err": float(rel.max()), "mean_rel_err": float(rel.mean()),
+                     "hit_ids_bit_exact_non_tie": bool(same), "tie_rays": int((~ok).sum())}
+    return out
+
+
+def multicam(M, sg, steps):
+    """16 cameras of uneven size and bounce depth in one queue, replayed as a graph."""
+    import numpy as np
+    import torch
+    sc = sg.multicam_scene()
+    cams = sg.cameras_array(sc.cameras)
+    o, d, ci = M.camera_rays(cams)
+    n = o.shape[0]
+    limits = np.array([c.max_bounces for c in sc.cameras], np.int32)
+    mb = torch.empty(n, dtype=torch.int32, device="cuda")
+    M.mr_camera_bounce_limits(ci, n, limits, mb)
+    F, G = M.Field(sc.field), M.Mesh(sc.mesh)
+    R = M.Renderer(n, int(limits.max()), with_hits=False)
+    opts = M.make_opts(sc)
+    g = M.mr_render_graph_create(F.handle, G.handle, n, o, d, int(limits.max()), mb, sc.lights, opts, R.out,
+                                 R.workspace, R.ws_bytes)
+    try:
+        ms = timed(lambda: M.mr_graph_launch(g), steps, 1)
+    finally:
+        M.mr_graph_destroy(g)
+    c = R.counters.cpu().numpy()
+    return {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "rays": n, "ms_per_frame": round(ms, 3),
+            "segments_per_s": round(int(c[1]) / (ms / 1e3), 1), "graph": True,
+            "bounce_histogram": np.bincount(R.bounces.cpu().numpy(), minlength=17).tolist()}
+
+
+def cloth(M, sg, frames):
+    """Cloth of 7 938 triangles, BVH refit every frame, 800x800, 8 bounces,
+    tiny field: plain 256-sample march."""
+    import numpy as np
+    import torch
+    sc = sg.cloth_scene(0)
+    cams = sg.cameras_array(sc.cameras)
+    n = sc.n_rays
+    F, G = M.Field(sc.field), M.Mesh(sc.mesh)
+    o = torch.empty(n, 3, device="cuda")
+    d = torch.empty(n, 3, device="cuda")
+    R = M.Renderer(n, sc.max_bounces, with_hits=False)
+    opts = M.make_opts(sc)
+    verts = [torch.from_numpy(sg.cloth_vertices(f)).cuda() for f in range(frames)]
+    M.mr_rays_from_cameras(cams, o, d, None, n)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for f in range(frames):
+        G.refit(verts[f])
+        R.render(F, G, o, d, sc.lights, opts)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / frames
+    return {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "frames": frames,
+            "ms_per_frame_incl_refit": round(ms, 3)}
+
+
 def cpu_baseline(sc, o, d, frac):
     from oracle import oracle as orc
     import numpy as np
@@ -63,6 +200,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-frac", type=int, default=64, help="oracle runs on 1/frac of the rays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="headline workload only")
+    ap.add_argument("--train-steps", type=int, default=1000)
+    ap.add_argument("--cloth-frames", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the path is not sharded "
@@ -140,6 +280,13 @@ def main():
         "gather": {"achieved": round(gbs, 1), "unit": "GB/s", "peak_hbm": HBM_PEAK_GBS,
                    "bytes_per_sample": gather_bytes(sc.field)},
     }
+    plain_img = R.radiance.cpu().numpy()
+    if not args.no_extras:
+        line["proposal_fp16"] = proposal_variant(M, sg, sc, F, G, cams, n, plain_img, args.steps, 1,
+                                                 args.train_steps)
+        line["precision_tiny_vs_fp64_oracle"] = precision_report(M, sg)
+        line["multicam_16_cameras"] = multicam(M, sg, 2)
+        line["cloth_refit"] = cloth(M, sg, args.cloth_frames)
     if not args.no_cpu_baseline:
         oh = o.cpu().numpy()
         dh = d.cpu().numpy()

@@ -260,9 +260,10 @@ mr_status mr_camera_bounce_limits(const int32_t* cam_index, int64_t n, const int
 /* keeps an FP32 master copy of its table for training.  mr_render with      */
 /* sampler = MR_SAMPLER_PROPOSAL takes n_proposal uniform intervals of each  */
 /* segment's marching range [lo, hi], weights w_j = T_j alpha_j from the     */
-/* proposal density, and places the n_fine fine intervals between the       */
-/* inverse-CDF points u = k/n_fine of the density proportional to            */
-/* w_j + 1e-3/n_proposal.                                                    */
+/* proposal density, dilates them to max(w_{j-1}, w_j, w_{j+1}), mixes them */
+/* half and half with a uniform density (adding their mean and 1e-3/n), and */
+/* places the n_fine fine intervals between the inverse-CDF points          */
+/* u = k/n_fine of that piecewise-constant density.                         */
 /* ------------------------------------------------------------------------ */
 typedef struct {
   float lr, beta1, beta2, eps;

@@ -492,7 +492,11 @@ void orc_proposal_weights(const orc_field* p, const double o[3], const double d[
 }
 
 /* Segment march over [lo, hi]: uniform grid of n_samples intervals of width
- * (t_far - t_near)/n_samples anchored at t_a, or the proposal's fine intervals. */
+ * (t_far - t_near)/n_samples anchored at t_a, or the proposal's fine intervals:
+ * proposal weights w_j on n_prop uniform intervals, dilated to
+ * max(w_{j-1}, w_j, w_{j+1}), plus their mean (a half-and-half mixture with a
+ * uniform density) plus 1e-3/n_prop; the n_fine + 1 edges are the inverse CDF
+ * of that piecewise-constant density at u = k/n_fine. */
 static int64_t march(const orc_field* f, const orc_opts* opt, const double o[3],
                      const double d[3], double t_a, double t_hit, double T[3], double L[3],
                      int* tie) {
@@ -509,7 +513,16 @@ static int64_t march(const orc_field* f, const orc_opts* opt, const double o[3],
     orc_proposal_weights(opt->proposal, o, d, lo, hi, np, w);
     double tot = 0.0;
     cdf[0] = 0.0;
-    for (int j = 0; j < np; ++j) { tot += w[j] + 1e-3 / np; cdf[j + 1] = tot; }
+    /* dilate over adjacent bins, then mix half and half with a uniform density */
+    double wd[1024], sw = 0.0;
+    for (int j = 0; j < np; ++j) {
+      double m = w[j];
+      if (j > 0 && w[j - 1] > m) m = w[j - 1];
+      if (j + 1 < np && w[j + 1] > m) m = w[j + 1];
+      wd[j] = m;
+      sw += m;
+    }
+    for (int j = 0; j < np; ++j) { tot += wd[j] + sw / np + 1e-3 / np; cdf[j + 1] = tot; }
     double step = (hi - lo) / np;
     int j = 0;
     for (int k = 0; k <= nf; ++k) {

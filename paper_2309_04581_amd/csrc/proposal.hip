@@ -6,9 +6,10 @@
 // The paper marches every segment with the field (Eq. 10-11) and does not use
 // a proposal network; this sampler follows the proposal loss of Mip-NeRF 360
 // (Barron et al., CVPR 2022).  Proposal weights w_j = T_j alpha_j on n_p
-// uniform intervals of [lo, hi] give a piecewise-constant density
-// proportional to w_j + 1e-3/n_p; the n_f + 1 edges of the fine intervals are
-// its inverse CDF at u = k/n_f.  The loss per segment is
+// uniform intervals of [lo, hi], dilated to max(w_{j-1}, w_j, w_{j+1}) and
+// mixed half and half with a uniform density (plus 1e-3/n_p), give a
+// piecewise-constant density; the n_f + 1 edges of the fine intervals are its
+// inverse CDF at u = k/n_f.  The loss per segment is
 // sum_j max(0, h_j - w_j)^2 / (h_j + 1e-7) against the histogram h of the
 // plain marcher's weights over the same n_p bins.
 #include <cmath>
@@ -156,7 +157,14 @@ __global__ __launch_bounds__(256) void k_march_prop(RayQueue q, const int* __res
     const float inclT = wscan_mul(1.0f - alpha_p, lane);
     float exclT = __shfl_up(inclT, 1, 64);
     if (lane == 0) exclT = 1.0f;
-    const float wp = lane < n_prop ? exclT * alpha_p + 1e-3f / (float)n_prop : 0.0f;
+    // dilate over adjacent bins and mix half and half with a uniform density
+    const float wraw = lane < n_prop ? exclT * alpha_p : 0.0f;
+    float wl = __shfl_up(wraw, 1, 64), wr = __shfl_down(wraw, 1, 64);
+    if (lane == 0) wl = 0.0f;
+    if (lane >= n_prop - 1) wr = 0.0f;
+    const float wdil = lane < n_prop ? fmaxf(wraw, fmaxf(wl, wr)) : 0.0f;
+    const float wmean = wsum(wdil) / (float)n_prop;
+    const float wp = lane < n_prop ? wdil + wmean + 1e-3f / (float)n_prop : 0.0f;
     const float cdf = wscan_add(wp, lane);
     const float tot = __shfl(cdf, n_prop - 1, 64);
     // edges of the fine intervals by inverse CDF (lane e holds edge e)
