@@ -182,8 +182,17 @@ typedef struct {
                                    per compute unit (0 = default 16) */
   int32_t stage_tile;           /* rays a block takes per work-queue grab in the
                                    closest-hit and shade stages, a multiple of 128
-                                   (0 = default 512) */
+                                   (0 = default 128) */
+  int32_t march_chunk;          /* march ray queue: 0 = one queue for the device; k > 0 =
+                                   chunks of k consecutive rays dealt round-robin to the
+                                   8 dies (workgroup i runs on die i % 8), each die's
+                                   waves taking their own chunks first */
 } mr_render_opts;
+
+/* One launch shape (the launch fields of mr_render_opts). */
+typedef struct {
+  int32_t march_blocks_per_cu, stage_blocks_per_cu, stage_tile, march_chunk;
+} mr_launch_cfg;
 
 typedef struct {
   float* radiance;           /* (n, 3) linear radiance L */
@@ -223,19 +232,17 @@ mr_status mr_graph_launch(mr_graph* graph, void* stream);
 mr_status mr_graph_destroy(mr_graph* graph);
 
 /* Launch-shape autotuner: renders the given workload once per candidate
- * (march_blocks_per_cu, stage_blocks_per_cu, stage_tile) triple, reps times
- * each after one warm-up, timing with HIP events on stream, and writes the
- * fastest triple and its mean milliseconds.  Candidates are host arrays;
- * the call synchronises with the host.  Output buffers receive the result
- * of the last render. */
+ * launch shape (host array), reps times each after one warm-up, timing with
+ * HIP events on stream, and writes the index of the fastest candidate and its
+ * mean milliseconds.  The call synchronises with the host.  Output buffers
+ * receive the result of the last render; results do not depend on the
+ * launch shape. */
 mr_status mr_autotune_render(const mr_field* field, const mr_mesh* mesh, int64_t n, const float* origins,
                              const float* dirs, int32_t max_bounces, const int32_t* per_ray_max_bounces,
                              const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
                              mr_render_out* out, void* workspace, size_t workspace_bytes,
-                             const int32_t* host_march_cands, int32_t n_march,
-                             const int32_t* host_stage_cands, int32_t n_stage,
-                             const int32_t* host_tile_cands, int32_t n_tile, int32_t reps,
-                             int32_t* best /*[3]*/, float* best_ms, void* stream);
+                             const mr_launch_cfg* host_cands, int32_t n_cands, int32_t reps,
+                             int32_t* best_index, float* best_ms, void* stream);
 
 /* Pinhole camera rays (device output), camera-major, then row-major with the
  * top row first.  host_cams: n_cams records of 12 floats: position (3),

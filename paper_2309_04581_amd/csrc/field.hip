@@ -4,7 +4,6 @@
 // meshes in (Sec. 3.3, an Instant-NGP model; colour emitted as linear HDR
 // radiance per Sec. 3.1 "Unifying color space").
 #include <cmath>
-#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -67,17 +66,6 @@ __global__ __launch_bounds__(256) void k_occupancy(FieldView F, const TabT* __re
   }
 }
 
-template <int NL, int SH, int CL, typename TabT>
-mr_status launch_query(const mr_field* f, int64_t n, const float* x, const float* dirs, float* sigma,
-                       float* rgb, float* feat, float* raw, hipStream_t st) {
-  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
-  const TabT* tab = reinterpret_cast<const TabT*>(f->table_dev);
-  hipLaunchKernelGGL((k_field_query<NL, SH, CL, TabT>), dim3(blocks), dim3(256), 0, st, f->view, tab,
-                     n, x, dirs, sigma, rgb, feat, raw);
-  MR_HIP(hipGetLastError());
-  return MR_OK;
-}
-
 template <int NL, typename TabT>
 mr_status launch_occ(mr_field* f, int res, float thresh, uint8_t* bytes, hipStream_t st) {
   const int64_t n = (int64_t)res * res * res;
@@ -91,15 +79,6 @@ mr_status launch_occ(mr_field* f, int res, float thresh, uint8_t* bytes, hipStre
 }  // namespace
 
 namespace mr {
-
-bool use_valu_mlp() {
-  static int v = -1;
-  if (v < 0) {
-    const char* e = std::getenv("MESHRF_MLP");
-    v = (e && std::strcmp(e, "valu") == 0) ? 1 : 0;
-  }
-  return v == 1;
-}
 
 bool field_supported(const mr_field_desc& d, std::string& why) {
   if (d.color_hidden_layers == 0) {
@@ -297,20 +276,7 @@ extern "C" mr_status mr_field_query(const mr_field* f, int64_t n, const float* x
   if (!x || !sigma) return fail(MR_ERR_INVALID_ARG, "x and sigma are required");
   if (rgb && !dirs) return fail(MR_ERR_INVALID_ARG, "rgb needs dirs");
   if (f->view.c_layers == 0) return fail(MR_ERR_UNSUPPORTED, "use the proposal entry points for proposal fields");
-  hipStream_t st = (hipStream_t)stream;
-  if (f->view.mlp_dtype != MR_F32 || !use_valu_mlp()) return query_mfma(f, n, x, dirs, sigma, rgb, feat, raw, st);
-  const auto& v = f->view;
-  const bool h = v.table_dtype == MR_F16;
-#define Q(NL, SH, CL)                                                                                   \
-  if (v.n_levels == NL && v.sh == SH && v.c_layers == CL)                                               \
-    return h ? launch_query<NL, SH, CL, __half>(f, n, x, dirs, sigma, rgb, feat, raw, st)               \
-             : launch_query<NL, SH, CL, float>(f, n, x, dirs, sigma, rgb, feat, raw, st);
-  Q(8, 4, 1)
-  Q(16, 16, 2)
-  Q(16, 4, 1)
-  Q(8, 16, 2)
-#undef Q
-  return fail(MR_ERR_UNSUPPORTED, "field shape not instantiated");
+  return query_mfma(f, n, x, dirs, sigma, rgb, feat, raw, (hipStream_t)stream);
 }
 
 extern "C" mr_status mr_field_build_occupancy(mr_field* f, int32_t res, float thresh, uint8_t* bits_out,

@@ -63,7 +63,7 @@ __device__ __forceinline__ bool occ_lookup(const FieldView& F, float px, float p
 }
 
 template <int NL, int SH, int CL, typename TabT, bool BF>
-__global__ __launch_bounds__(256) void k_march_mfma(RayQueue q, const int* __restrict__ count, int* __restrict__ work,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_march_mfma(RayQueue q, const int* __restrict__ count, int* __restrict__ work,
                                                     FieldView F, const TabT* __restrict__ table,
                                                     const uint32_t* __restrict__ frags, MarchParams P,
                                                     unsigned long long* __restrict__ stats) {
@@ -76,10 +76,8 @@ __global__ __launch_bounds__(256) void k_march_mfma(RayQueue q, const int* __res
   const bool use_occ = P.use_occupancy && F.occ;
   unsigned long long nsamp = 0;
   while (true) {
-    int r = 0;
-    if (lane == 0) r = atomicAdd(work, 1);
-    r = __shfl(r, 0, 64);
-    if (r >= cnt) break;
+    const int r = next_ray(work, cnt, P.chunk, lane);
+    if (r < 0) break;
     const float ox = q.ox[r], oy = q.oy[r], oz = q.oz[r];
     const float dx = q.dx[r], dy = q.dy[r], dz = q.dz[r];
     const int seg = q.depth[r] & 0xFFFF;

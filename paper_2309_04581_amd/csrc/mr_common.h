@@ -80,9 +80,6 @@ struct MeshView {
   Material mat[kMaxMaterials];
 };
 
-// Field MLP engine for FP32 fields: matrix cores unless MESHRF_MLP=valu.
-bool use_valu_mlp();
-
 }  // namespace mr
 
 struct mr_field {

@@ -1,6 +1,6 @@
-// Device building blocks of the marcher: Philox, hash-grid encoding, SH,
-// FP32 MLPs with LDS-broadcast weights, watertight ray-triangle test and BVH
-// traversal with a per-thread stack in LDS.
+// Device building blocks of the marcher: Philox, hash-grid encoding, SH, the
+// per-thread density MLP of the occupancy grid, the watertight ray-triangle
+// test and BVH traversal with a per-thread stack in LDS.
 #pragma once
 #include "mr_common.h"
 
@@ -149,16 +149,9 @@ __device__ __forceinline__ void sh_eval(float x, float y, float z, float* o) {
 __device__ __forceinline__ float softplusf(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
 
 // ---------------------------------------------------------------------------
-// FP32 MLPs, one sample per lane, weights broadcast from LDS.
-// Layout (floats): W0 [64][32] @0, W1 [16][64] @2048, Wc0 [64][32] @3072,
-// Wc1 [64][64] @5120 (two hidden colour layers), Wout [3][64] last.
+// density MLP on one sample per lane (occupancy grid), weights broadcast from
+// LDS: W0 [64][32] at 0, W1 [16][64] at 2048.
 // ---------------------------------------------------------------------------
-template <int CL>
-struct MlpLayout {
-  static constexpr int W0 = 0, W1 = 2048, C0 = 3072, C1 = 5120;
-  static constexpr int OUT = CL == 2 ? 9216 : 5120;
-  static constexpr int TOTAL = OUT + 192;
-};
 
 template <int NIN>
 __device__ __forceinline__ float dot_row(const float* __restrict__ w, const float* x) {
@@ -184,39 +177,6 @@ __device__ __forceinline__ void density_mlp(const float* __restrict__ W, const f
 #pragma unroll
     for (int k = 0; k < 16; ++k) raw[k] += W[2048 + k * 64 + j] * h;
   }
-}
-
-// colour MLP: (16 raw ++ SH) -> 64 (ReLU) [-> 64 (ReLU)] -> 3, rgb = exp(out)
-template <int SH, int CL>
-__device__ __forceinline__ void color_mlp(const float* __restrict__ W, const float* raw, float dx,
-                                          float dy, float dz, float rgb[3]) {
-  using Ly = MlpLayout<CL>;
-  float cin[16 + SH];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) cin[k] = raw[k];
-  sh_eval<SH>(dx, dy, dz, cin + 16);
-  float o0 = 0.0f, o1 = 0.0f, o2 = 0.0f;
-  if constexpr (CL == 1) {
-    for (int j = 0; j < 64; ++j) {
-      const float h = fmaxf(dot_row<16 + SH>(W + Ly::C0 + j * 32, cin), 0.0f);
-      o0 += W[Ly::OUT + j] * h;
-      o1 += W[Ly::OUT + 64 + j] * h;
-      o2 += W[Ly::OUT + 128 + j] * h;
-    }
-  } else {
-    float h1[64];
-#pragma unroll
-    for (int j = 0; j < 64; ++j) h1[j] = fmaxf(dot_row<16 + SH>(W + Ly::C0 + j * 32, cin), 0.0f);
-    for (int j = 0; j < 64; ++j) {
-      const float h = fmaxf(dot_row<64>(W + Ly::C1 + j * 64, h1), 0.0f);
-      o0 += W[Ly::OUT + j] * h;
-      o1 += W[Ly::OUT + 64 + j] * h;
-      o2 += W[Ly::OUT + 128 + j] * h;
-    }
-  }
-  rgb[0] = expf(o0);
-  rgb[1] = expf(o1);
-  rgb[2] = expf(o2);
 }
 
 // ---------------------------------------------------------------------------

@@ -124,17 +124,21 @@ __device__ __forceinline__ void mlp_tile(const uint32_t* __restrict__ W, const f
 #pragma unroll
     for (int v = 0; v < 4; ++v) h[mt][v] = fmaxf(h[mt][v], 0.0f);
   // density layer 2: 16 raw outputs
-  raw = zero;
+  // four independent accumulator chains (one per hidden tile), summed at the end
+  f4v rp[4] = {zero, zero, zero, zero};
   if constexpr (!BF) {
     const float* Wf = reinterpret_cast<const float*>(W);
 #pragma unroll
-    for (int ks = 0; ks < 16; ++ks) raw = mma(Wf[LY::L2 + ks * 64 + lane], h[ks / 4][ks % 4], raw);
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) rp[mt] = mma(Wf[LY::L2 + (mt * 4 + v) * 64 + lane], h[mt][v], rp[mt]);
   } else {
     const uint2* Wb = reinterpret_cast<const uint2*>(W);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks)
-      raw = mma(Wb[LY::L2 / 2 + ks * 64 + lane], pack_bf16(h[ks][0], h[ks][1], h[ks][2], h[ks][3]), raw);
+      rp[ks] = mma(Wb[LY::L2 / 2 + ks * 64 + lane], pack_bf16(h[ks][0], h[ks][1], h[ks][2], h[ks][3]), rp[ks]);
   }
+  raw = (rp[0] + rp[1]) + (rp[2] + rp[3]);
   sigma = softplusf(__shfl(raw[0], j, 64) + density_offset);
   // colour layer 1: SH part precomputed in u, raw part on the matrix cores
   f4v c[4];

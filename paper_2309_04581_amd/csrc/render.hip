@@ -135,131 +135,6 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(RayQueue q, const int* __
 }
 
 // ---------------------------------------------------------------------------
-// segment march: one wave per ray, one sample per lane, 64 samples a step
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ float wave_scan_mul(float v, int lane) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const float u = __shfl_up(v, off, 64);
-    if (lane >= off) v *= u;
-  }
-  return v;
-}
-
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-__device__ __forceinline__ bool slab(const FieldView& F, float ox, float oy, float oz, float dx, float dy, float dz,
-                                     float& t0, float& t1) {
-  float lo = -INFINITY, hi = INFINITY;
-  const float o[3] = {ox, oy, oz}, d[3] = {dx, dy, dz};
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    if (d[k] == 0.0f) {
-      if (o[k] < F.amin[k] || o[k] > F.amax[k]) return false;
-      continue;
-    }
-    const float inv = 1.0f / d[k];
-    float a = (F.amin[k] - o[k]) * inv, b = (F.amax[k] - o[k]) * inv;
-    if (a > b) { const float t = a; a = b; b = t; }
-    lo = fmaxf(lo, a);
-    hi = fminf(hi, b);
-  }
-  t0 = lo;
-  t1 = hi;
-  return hi > lo;
-}
-
-__device__ __forceinline__ bool occupied(const FieldView& F, float px, float py, float pz) {
-  float xh, yh, zh;
-  to_unit(F, px, py, pz, xh, yh, zh);
-  const int R = F.occ_res;
-  const int cx = min((int)(xh * R), R - 1), cy = min((int)(yh * R), R - 1), cz = min((int)(zh * R), R - 1);
-  const int64_t c = ((int64_t)cz * R + cy) * R + cx;
-  return (F.occ[c >> 5] >> (c & 31)) & 1u;
-}
-
-template <int NL, int SH, int CL, typename TabT>
-__global__ __launch_bounds__(256) void k_march(RayQueue q, const int* __restrict__ count, int* __restrict__ work,
-                                               FieldView F, const TabT* __restrict__ table, MarchParams P,
-                                               unsigned long long* __restrict__ stats) {
-  __shared__ __align__(16) float sW[MlpLayout<CL>::TOTAL];
-  for (int i = threadIdx.x; i < MlpLayout<CL>::TOTAL; i += blockDim.x) sW[i] = F.mlp[i];
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int cnt = *count;
-  const bool use_occ = P.use_occupancy && F.occ;
-  unsigned long long nsamp = 0;
-  while (true) {
-    int r = 0;
-    if (lane == 0) r = atomicAdd(work, 1);
-    r = __shfl(r, 0, 64);
-    if (r >= cnt) break;
-    const float ox = q.ox[r], oy = q.oy[r], oz = q.oz[r];
-    const float dx = q.dx[r], dy = q.dy[r], dz = q.dz[r];
-    const int seg = q.depth[r] & 0xFFFF;
-    const float t_a = seg == 0 ? P.t_near : 0.0f;
-    float box0, box1;
-    if (!slab(F, ox, oy, oz, dx, dy, dz, box0, box1)) continue;
-    const float lo = fmaxf(t_a, box0);
-    const float hi = fminf(fminf(t_a + P.span, q.hit_t[r]), box1);
-    if (!(hi > lo)) continue;
-    const float delta = P.delta;
-    const int k0 = max(0, (int)floorf((lo - t_a) / delta) - 1);
-    const int k1 = min(P.n_samples, (int)ceilf((hi - t_a) / delta) + 1);
-    float Tseg = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
-    for (int kb = k0; kb < k1; kb += 64) {
-      const int k = kb + lane;
-      const float a = fmaxf(t_a + (float)k * delta, lo);
-      const float b = fminf(t_a + (float)(k + 1) * delta, hi);
-      bool valid = k < k1 && b > a;
-      const float tm = 0.5f * (a + b), D = b - a;
-      const float px = ox + tm * dx, py = oy + tm * dy, pz = oz + tm * dz;
-      if (valid && use_occ) valid = occupied(F, px, py, pz);
-      float alpha = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-      if (valid) {
-        float feat[32], raw[16], rgb[3];
-        hash_encode<NL, TabT>(F, table, px, py, pz, feat);
-        density_mlp<NL>(sW, feat, raw);
-        const float sigma = softplusf(raw[0] + F.density_offset);
-        color_mlp<SH, CL>(sW, raw, dx, dy, dz, rgb);
-        alpha = -expm1f(-sigma * D);
-        c0 = rgb[0]; c1 = rgb[1]; c2 = rgb[2];
-        ++nsamp;
-      }
-      const float incl = wave_scan_mul(1.0f - alpha, lane);
-      float excl = __shfl_up(incl, 1, 64);
-      if (lane == 0) excl = 1.0f;
-      const float w = Tseg * excl * alpha;
-      acc0 += w * c0;
-      acc1 += w * c1;
-      acc2 += w * c2;
-      Tseg *= __shfl(incl, 63, 64);
-    }
-    acc0 = wave_sum(acc0);
-    acc1 = wave_sum(acc1);
-    acc2 = wave_sum(acc2);
-    if (lane == 0) {
-      const float tr = q.tr[r], tg = q.tg[r], tb = q.tb[r];
-      q.lr[r] += tr * acc0;
-      q.lg[r] += tg * acc1;
-      q.lb[r] += tb * acc2;
-      q.tr[r] = tr * Tseg;
-      q.tg[r] = tg * Tseg;
-      q.tb[r] = tb * Tseg;
-    }
-  }
-  if (stats) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) nsamp += __shfl_xor(nsamp, off, 64);
-    if (lane == 0 && nsamp) atomicAdd(stats + 0, nsamp);
-  }
-}
-
-// ---------------------------------------------------------------------------
 // surface interaction, shadow rays, roulette, termination and compaction
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void finalize(const RenderOut& out, int rid, float tr, float tg, float tb, float lr, float lg,
@@ -472,31 +347,6 @@ __global__ void k_raygen(CamBatch C, int64_t total, float* __restrict__ o, float
   }
 }
 
-template <int NL, int SH, int CL, typename TabT>
-mr_status launch_march(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
-                       unsigned long long* stats, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL((k_march<NL, SH, CL, TabT>), dim3(blocks), dim3(256), 0, st, q, count, work, f->view,
-                     reinterpret_cast<const TabT*>(f->table_dev), P, stats);
-  MR_HIP(hipGetLastError());
-  return MR_OK;
-}
-
-mr_status dispatch_march(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
-                         unsigned long long* stats, int blocks, hipStream_t st) {
-  const auto& v = f->view;
-  const bool h = v.table_dtype == MR_F16;
-#define M(NL, SH, CL)                                                                               \
-  if (v.n_levels == NL && v.sh == SH && v.c_layers == CL)                                           \
-    return h ? launch_march<NL, SH, CL, __half>(f, q, count, work, P, stats, blocks, st)            \
-             : launch_march<NL, SH, CL, float>(f, q, count, work, P, stats, blocks, st);
-  M(8, 4, 1)
-  M(16, 16, 2)
-  M(16, 4, 1)
-  M(8, 16, 2)
-#undef M
-  return fail(MR_ERR_UNSUPPORTED, "field shape not instantiated");
-}
-
 }  // namespace
 
 namespace mr {
@@ -547,6 +397,7 @@ mr_status validate_render(const mr_field* field, const mr_mesh* mesh, int64_t n,
     return fail(MR_ERR_INVALID_ARG, "blocks per compute unit must be in 0..64");
   if (opts->stage_tile < 0 || opts->stage_tile % kTraceBlock != 0 || opts->stage_tile > (1 << 20))
     return fail(MR_ERR_INVALID_ARG, "stage_tile must be a multiple of 128 (or 0)");
+  if (opts->march_chunk < 0) return fail(MR_ERR_INVALID_ARG, "march_chunk must be >= 0");
   if (opts->use_occupancy && field && !field->occ_dev)
     return fail(MR_ERR_STATE, "use_occupancy set but the field has no occupancy grid");
   return MR_OK;
@@ -573,15 +424,16 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
   const int64_t cap = ((n + 63) / 64) * 64;
   char* ws = reinterpret_cast<char*>(workspace);
   int* counts = reinterpret_cast<int*>(ws);                 // [kMaxBounces + 2]
-  int* work = counts + (kMaxBounces + 2);                   // march ray queue heads
-  int* twork = work + (kMaxBounces + 2);                    // closest-hit tile queue heads
+  int* twork = counts + (kMaxBounces + 2);                  // closest-hit tile queue heads
   int* swork = twork + (kMaxBounces + 2);                   // shade tile queue heads
+  int* work = swork + (kMaxBounces + 2);                    // march: kXcds ray queue heads per segment
   RayQueue Q[2] = {queue_at(ws + kHeaderBytes, cap), queue_at(ws + kHeaderBytes + queue_bytes(cap), cap)};
   unsigned long long* stats = reinterpret_cast<unsigned long long*>(out->counters);
 
   const int init_blocks = (int)std::min<int64_t>((n + 255) / 256, 65535);
   hipLaunchKernelGGL(k_init, dim3(init_blocks), dim3(256), 0, st, n, origins, dirs, per_ray_max_bounces, max_bounces,
-                     Q[0], counts, 4 * (kMaxBounces + 2), out->hit_ids, out->hit_ids ? out->hit_stride : 0, stats);
+                     Q[0], counts, (3 + kXcds) * (kMaxBounces + 2), out->hit_ids, out->hit_ids ? out->hit_stride : 0,
+                     stats);
   MR_HIP(hipGetLastError());
 
   MeshView mv;
@@ -596,6 +448,7 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
   P.n_samples = opts->n_samples;
   P.delta = P.span / (float)opts->n_samples;
   P.use_occupancy = opts->use_occupancy;
+  P.chunk = opts->march_chunk;
 
   ShadeParams S;
   std::memset(&S, 0, sizeof(S));
@@ -615,11 +468,12 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
   ro.bounces = out->bounces;
 
   const int cus = device_cus();
-  const int tile = opts->stage_tile > 0 ? opts->stage_tile : 512;
+  const int tile = opts->stage_tile > 0 ? opts->stage_tile : 128;
   const int sbpc = opts->stage_blocks_per_cu > 0 ? opts->stage_blocks_per_cu : 16;
   const int mbpc = opts->march_blocks_per_cu > 0 ? opts->march_blocks_per_cu : 8;
   const int trace_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + tile - 1) / tile, (int64_t)cus * sbpc));
-  const int march_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 3) / 4, (int64_t)cus * mbpc));
+  // at least kXcds blocks so that every die has a home partition served
+  const int march_blocks = (int)std::max<int64_t>(kXcds, std::min<int64_t>((n + 3) / 4, (int64_t)cus * mbpc));
   for (int b = 0; b <= max_bounces; ++b) {
     RayQueue& qi = Q[b & 1];
     RayQueue& qo = Q[(b + 1) & 1];
@@ -632,12 +486,10 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
     if (field) {
       StageTimer tm(1, st);
       if (opts->sampler == MR_SAMPLER_PROPOSAL)
-        s = dispatch_march_proposal(field, opts->proposal, qi, counts + b, work + b, P, opts->n_proposal, opts->n_fine,
-                                    stats, march_blocks, st);
-      else if (field->view.mlp_dtype == MR_F32 && use_valu_mlp())
-        s = dispatch_march(field, qi, counts + b, work + b, P, stats, march_blocks, st);
+        s = dispatch_march_proposal(field, opts->proposal, qi, counts + b, work + kXcds * b, P, opts->n_proposal,
+                                    opts->n_fine, stats, march_blocks, st);
       else
-        s = dispatch_march_mfma(field, qi, counts + b, work + b, P, stats, march_blocks, st);
+        s = dispatch_march_mfma(field, qi, counts + b, work + kXcds * b, P, stats, march_blocks, st);
       if (s != MR_OK) return s;
     }
     {
@@ -794,13 +646,10 @@ extern "C" mr_status mr_autotune_render(const mr_field* field, const mr_mesh* me
                                         const float* dirs, int32_t max_bounces, const int32_t* per_ray_max_bounces,
                                         const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
                                         mr_render_out* out, void* workspace, size_t workspace_bytes,
-                                        const int32_t* host_march_cands, int32_t n_march,
-                                        const int32_t* host_stage_cands, int32_t n_stage,
-                                        const int32_t* host_tile_cands, int32_t n_tile, int32_t reps, int32_t* best,
-                                        float* best_ms, void* stream) {
-  if (!opts || !best || !best_ms) return fail(MR_ERR_INVALID_ARG, "null argument");
-  if (n_march < 1 || n_stage < 1 || n_tile < 1 || !host_march_cands || !host_stage_cands || !host_tile_cands)
-    return fail(MR_ERR_INVALID_ARG, "need at least one candidate of each kind");
+                                        const mr_launch_cfg* host_cands, int32_t n_cands, int32_t reps,
+                                        int32_t* best_index, float* best_ms, void* stream) {
+  if (!opts || !best_index || !best_ms || !host_cands) return fail(MR_ERR_INVALID_ARG, "null argument");
+  if (n_cands < 1) return fail(MR_ERR_INVALID_ARG, "need at least one candidate");
   if (reps < 1 || reps > 100) return fail(MR_ERR_INVALID_ARG, "reps must be in 1..100");
   hipStream_t st = (hipStream_t)stream;
   hipEvent_t a = nullptr, b = nullptr;
@@ -808,35 +657,32 @@ extern "C" mr_status mr_autotune_render(const mr_field* field, const mr_mesh* me
   MR_HIP(hipEventCreate(&b));
   float best_t = INFINITY;
   mr_status s = MR_OK;
-  for (int im = 0; im < n_march && s == MR_OK; ++im)
-    for (int is = 0; is < n_stage && s == MR_OK; ++is)
-      for (int it = 0; it < n_tile && s == MR_OK; ++it) {
-        mr_render_opts o = *opts;
-        o.march_blocks_per_cu = host_march_cands[im];
-        o.stage_blocks_per_cu = host_stage_cands[is];
-        o.stage_tile = host_tile_cands[it];
-        s = mr_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, host_lights, n_lights, &o, out,
-                      workspace, workspace_bytes, stream);
-        if (s != MR_OK) break;
-        if (hipEventRecord(a, st) != hipSuccess) { s = fail(MR_ERR_DEVICE, "event record"); break; }
-        for (int r = 0; r < reps && s == MR_OK; ++r)
-          s = mr_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, host_lights, n_lights, &o,
-                        out, workspace, workspace_bytes, stream);
-        if (s != MR_OK) break;
-        float ms = 0.0f;
-        if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
-            hipEventElapsedTime(&ms, a, b) != hipSuccess) {
-          s = fail(MR_ERR_DEVICE, "event timing");
-          break;
-        }
-        ms /= reps;
-        if (ms < best_t) {
-          best_t = ms;
-          best[0] = o.march_blocks_per_cu;
-          best[1] = o.stage_blocks_per_cu;
-          best[2] = o.stage_tile;
-        }
-      }
+  for (int c = 0; c < n_cands && s == MR_OK; ++c) {
+    mr_render_opts o = *opts;
+    o.march_blocks_per_cu = host_cands[c].march_blocks_per_cu;
+    o.stage_blocks_per_cu = host_cands[c].stage_blocks_per_cu;
+    o.stage_tile = host_cands[c].stage_tile;
+    o.march_chunk = host_cands[c].march_chunk;
+    s = mr_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, host_lights, n_lights, &o, out,
+                  workspace, workspace_bytes, stream);
+    if (s != MR_OK) break;
+    if (hipEventRecord(a, st) != hipSuccess) { s = fail(MR_ERR_DEVICE, "event record"); break; }
+    for (int r = 0; r < reps && s == MR_OK; ++r)
+      s = mr_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, host_lights, n_lights, &o, out,
+                    workspace, workspace_bytes, stream);
+    if (s != MR_OK) break;
+    float ms = 0.0f;
+    if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+      s = fail(MR_ERR_DEVICE, "event timing");
+      break;
+    }
+    ms /= reps;
+    if (ms < best_t) {
+      best_t = ms;
+      *best_index = c;
+    }
+  }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (s == MR_OK) *best_ms = best_t;

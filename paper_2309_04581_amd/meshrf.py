@@ -64,7 +64,12 @@ class RenderOpts(C.Structure):
                 ("n_fine", C.c_int32), ("use_occupancy", C.c_int32), ("rr_after", C.c_int32),
                 ("t_min_throughput", C.c_float), ("seed", C.c_uint32),
                 ("march_blocks_per_cu", C.c_int32), ("stage_blocks_per_cu", C.c_int32),
-                ("stage_tile", C.c_int32)]
+                ("stage_tile", C.c_int32), ("march_chunk", C.c_int32)]
+
+
+class LaunchCfg(C.Structure):
+    _fields_ = [("march_blocks_per_cu", C.c_int32), ("stage_blocks_per_cu", C.c_int32),
+                ("stage_tile", C.c_int32), ("march_chunk", C.c_int32)]
 
 
 class Adam(C.Structure):
@@ -444,19 +449,19 @@ def mr_graph_destroy(graph):
 
 
 def mr_autotune_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, lights, opts, out,
-                       workspace, workspace_bytes, march_cands, stage_cands, tile_cands, reps=2, stream=None):
+                       workspace, workspace_bytes, candidates, reps=2, stream=None):
+    """candidates: sequence of (march_blocks_per_cu, stage_blocks_per_cu, stage_tile, march_chunk)."""
     arr, nl = _lights_arr(lights)
-    mc = np.ascontiguousarray(march_cands, dtype=np.int32)
-    sc = np.ascontiguousarray(stage_cands, dtype=np.int32)
-    tc = np.ascontiguousarray(tile_cands, dtype=np.int32)
-    best = (C.c_int32 * 3)()
+    cands = (LaunchCfg * len(candidates))()
+    for i, c in enumerate(candidates):
+        cands[i].march_blocks_per_cu, cands[i].stage_blocks_per_cu, cands[i].stage_tile, cands[i].march_chunk = c
+    best = C.c_int32()
     ms = C.c_float()
     _check(lib().mr_autotune_render(field, mesh, C.c_int64(n), _ptr(origins), _ptr(dirs), C.c_int32(max_bounces),
                                     _ptr(per_ray_max_bounces), arr, C.c_int32(nl), C.byref(opts), C.byref(out),
-                                    _ptr(workspace), C.c_size_t(workspace_bytes), _ptr(mc), C.c_int32(len(mc)),
-                                    _ptr(sc), C.c_int32(len(sc)), _ptr(tc), C.c_int32(len(tc)), C.c_int32(reps),
-                                    best, C.byref(ms), _stream(stream)))
-    return tuple(best), ms.value
+                                    _ptr(workspace), C.c_size_t(workspace_bytes), cands, C.c_int32(len(cands)),
+                                    C.c_int32(reps), C.byref(best), C.byref(ms), _stream(stream)))
+    return tuple(candidates[best.value]), ms.value
 
 
 def mr_camera_bounce_limits(cam_index, n, cam_limits, out, stream=None):
