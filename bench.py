@@ -149,33 +149,62 @@ def multicam(M, sg, steps):
             "bounce_histogram": np.bincount(R.bounces.cpu().numpy(), minlength=17).tolist()}
 
 
-def cloth(M, sg, frames):
-    """Cloth of 7 938 triangles, BVH refit every frame, 800x800, 8 bounces,
-    tiny field: plain 256-sample march."""
+def cloth(M, sg, frames, train_steps):
+    """Cloth of 7 938 triangles with a BVH refit every frame, 800x800, 8
+    bounces, on the tiny field: plain FP32 (256 samples) and proposal (32 + 32,
+    trained on the tiny field's plain-marcher histograms) with FP16 table +
+    BF16 MLPs; PSNR of the proposal image against the plain one per frame."""
     import numpy as np
     import torch
     sc = sg.cloth_scene(0)
     cams = sg.cameras_array(sc.cameras)
     n = sc.n_rays
     F, G = M.Field(sc.field), M.Mesh(sc.mesh)
+    F16 = M.Field(sc.field, table_dtype=M.MR_F16, mlp_dtype=M.MR_BF16)
+    P = M.Field(sg.make_proposal(), table_dtype=M.MR_F16)
+    T = M.ProposalTrainer(P)
+    to, td = sg.random_rays(1 << 18, seed=506)
+    to = torch.from_numpy(to).cuda()
+    td = torch.from_numpy(td).cuda()
+    lohi, tgt = T.targets(F, to, td, sc.t_near, sc.t_far, sc.n_samples)
+    T.train(to, td, lohi, tgt, steps=train_steps, batch=1 << 14)
     o = torch.empty(n, 3, device="cuda")
     d = torch.empty(n, 3, device="cuda")
-    R = M.Renderer(n, sc.max_bounces, with_hits=False)
-    opts = M.make_opts(sc)
-    verts = [torch.from_numpy(sg.cloth_vertices(f)).cuda() for f in range(frames)]
     M.mr_rays_from_cameras(cams, o, d, None, n)
-    torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record()
+    R = M.Renderer(n, sc.max_bounces, with_hits=False)
+    plain = M.make_opts(sc)
+    prop = M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P)
+    verts = [torch.from_numpy(sg.cloth_vertices(f)).cuda() for f in range(frames)]
+
+    def run(field, opts):
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for f in range(frames):
+            G.refit(verts[f])
+            R.render(field, G, o, d, sc.lights, opts)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / frames
+
+    run(F, plain)
+    ms_plain = run(F, plain)
+    ms_prop = run(F16, prop)
+    psnr = []
     for f in range(frames):
         G.refit(verts[f])
-        R.render(F, G, o, d, sc.lights, opts)
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / frames
-    return {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "frames": frames,
-            "ms_per_frame_incl_refit": round(ms, 3)}
+        R.render(F, G, o, d, sc.lights, plain)
+        ref = R.radiance.cpu().numpy()
+        R.render(F16, G, o, d, sc.lights, prop)
+        psnr.append(psnr_tonemapped(R.radiance.cpu().numpy(), ref))
+    return {"plain_fp32": {"value": round(n / (ms_plain / 1e3), 1), "unit": "rays/s",
+                           "ms_per_frame_incl_refit": round(ms_plain, 3)},
+            "proposal_fp16": {"value": round(n / (ms_prop / 1e3), 1), "unit": "rays/s",
+                              "ms_per_frame_incl_refit": round(ms_prop, 3),
+                              "psnr_db_per_frame": [round(x, 2) for x in psnr],
+                              "psnr_db_min": round(min(psnr), 2)},
+            "frames": frames, "triangles": int(len(sc.mesh.indices))}
 
 
 def cpu_baseline(sc, o, d, frac):
@@ -294,7 +323,7 @@ def main():
                                                  args.train_steps)
         line["precision_tiny_vs_fp64_oracle"] = precision_report(M, sg)
         line["multicam_16_cameras"] = multicam(M, sg, 2)
-        line["cloth_refit"] = cloth(M, sg, args.cloth_frames)
+        line["cloth_refit"] = cloth(M, sg, args.cloth_frames, args.train_steps)
     if not args.no_cpu_baseline:
         oh = o.cpu().numpy()
         dh = d.cpu().numpy()

@@ -187,11 +187,12 @@ typedef struct {
                                    chunks of k consecutive rays dealt round-robin to the
                                    8 dies (workgroup i runs on die i % 8), each die's
                                    waves taking their own chunks first */
+  int32_t march_batch;          /* rays a march wave takes per queue grab, 1..64 (0 = 1) */
 } mr_render_opts;
 
 /* One launch shape (the launch fields of mr_render_opts). */
 typedef struct {
-  int32_t march_blocks_per_cu, stage_blocks_per_cu, stage_tile, march_chunk;
+  int32_t march_blocks_per_cu, stage_blocks_per_cu, stage_tile, march_chunk, march_batch;
 } mr_launch_cfg;
 
 typedef struct {

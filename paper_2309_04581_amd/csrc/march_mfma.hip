@@ -75,9 +75,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int cnt = *count;
   const bool use_occ = P.use_occupancy && F.occ;
   unsigned long long nsamp = 0;
-  while (true) {
-    const int r = next_ray(work, cnt, P.chunk, lane);
-    if (r < 0) break;
+  WorkQueue wq(work, cnt, P.chunk, P.batch);
+  for (int base = wq.next(lane); base >= 0; base = wq.next(lane))
+  for (int bi = 0; bi < wq.batch; ++bi) {
+    const int r = wq.map(base + bi);
+    if (r >= cnt) break;
     const float ox = q.ox[r], oy = q.oy[r], oz = q.oz[r];
     const float dx = q.dx[r], dy = q.dy[r], dz = q.dz[r];
     const int seg = q.depth[r] & 0xFFFF;
@@ -256,8 +258,13 @@ std::vector<uint32_t> build_fragments(const mr_field_desc& d, const float* mlp, 
     for (int mt = 0; mt < 4; ++mt)
       for (int ks = 0; ks < KS2; ++ks) put(C2, mt, ks, KS2, Wc2, 64, 64, 1);
   for (int i = 0; i < 192; ++i) w[OUT + i] = bits(Wout[i]);
-  for (int row = 0; row < 64; ++row)
-    for (int s = 0; s < SH; ++s) w[SHW + row * SH + s] = bits(Wc1[row * d.color_in + 16 + s]);
+  // SH columns of colour layer 1 as FP32 fragments [4 mt][SH/4][64]: lane
+  // (g, j) of step ks holds row mt*16 + j, SH component 4 ks + g
+  for (int mt = 0; mt < 4; ++mt)
+    for (int ks = 0; ks < SH / 4; ++ks)
+      for (int lane = 0; lane < 64; ++lane)
+        w[SHW + (mt * (SH / 4) + ks) * 64 + lane] =
+            bits(Wc1[(mt * 16 + lane % 16) * d.color_in + 16 + 4 * ks + lane / 16]);
   return w;
 }
 

@@ -30,7 +30,7 @@ struct FragLayout {
   static constexpr int C1 = L2 + KS2 * 64 * W;               // [4 mt][KSC]
   static constexpr int C2 = C1 + 4 * KSC * 64 * W;           // [4 mt][KS2] (two hidden colour layers)
   static constexpr int OUT = C2 + (CL == 2 ? 4 * KS2 * 64 * W : 0);   // FP32 [3][64]
-  static constexpr int SHW = OUT + 192;                      // FP32 [64][SH]: SH columns of colour layer 1
+  static constexpr int SHW = OUT + 192;                      // FP32 [4 mt][SH/4][64]: SH columns of colour layer 1
   static constexpr int TOTAL = SHW + 64 * SH;
 };
 
@@ -203,25 +203,32 @@ __device__ __forceinline__ void mlp_tile(const uint32_t* __restrict__ W, const f
   rgb[2] = expf(o[2]);
 }
 
-// SH contribution to colour layer 1 for hidden rows mt*16 + 4g + v.
+// SH contribution to colour layer 1 for hidden rows mt*16 + 4g + v: the
+// product Wc1[:, 16:16+SH] x SH(d), the same for every sample of a ray, as
+// FP32 MFMAs whose B operand is the SH vector in every column (lane group g
+// supplies component 4 ks + g), so the result lands in the C layout.
 template <int NL, int SH, int CL, bool BF>
 __device__ __forceinline__ void sh_rows(const uint32_t* __restrict__ W, float dx, float dy, float dz, int lane,
                                         float (&u)[4][4]) {
   using LY = FragLayout<NL, SH, CL, BF>;
   const float* Ws = reinterpret_cast<const float*>(W) + LY::SHW;
-  float shv[SH];
+  float shv[16];
   sh_eval<SH>(dx, dy, dz, shv);
   const int g = lane >> 4;
+  float b[SH / 4];
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
+  for (int ks = 0; ks < SH / 4; ++ks) {
+    const float s0 = shv[4 * ks], s1 = shv[4 * ks + 1], s2 = shv[4 * ks + 2], s3 = shv[4 * ks + 3];
+    b[ks] = g == 0 ? s0 : (g == 1 ? s1 : (g == 2 ? s2 : s3));
+  }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = mt * 16 + 4 * g + v;
-      float s = 0.0f;
+  for (int mt = 0; mt < 4; ++mt) {
+    f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int k = 0; k < SH; ++k) s += Ws[row * SH + k] * shv[k];
-      u[mt][v] = s;
-    }
+    for (int ks = 0; ks < SH / 4; ++ks) acc = mma(Ws[(mt * (SH / 4) + ks) * 64 + lane], b[ks], acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) u[mt][v] = acc[v];
+  }
 }
 
 }  // namespace mr

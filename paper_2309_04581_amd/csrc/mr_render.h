@@ -25,6 +25,7 @@ struct MarchParams {
   int n_samples;
   int use_occupancy;
   int chunk;          // rays per die chunk of the march queue (0 = one global queue)
+  int batch;          // queue positions a wave takes per atomic
 };
 
 struct ShadeParams {
@@ -43,32 +44,38 @@ struct RenderOut {
 
 constexpr int kXcds = 8;               // accelerator complex dies; workgroups go round-robin over them
 
-// Next ray for a wave.  chunk == 0: one queue for the whole device.  chunk > 0:
-// the queue [0, cnt) is cut into chunks of `chunk` rays dealt round-robin to
-// the kXcds dies; the waves of workgroups on die x = blockIdx.x % kXcds take
-// the rays of die x's chunks in order (neighbouring rays then share that die's
-// L2), then help the other dies.  ctr: kXcds counters, zero at launch.
-// Returns -1 when every ray has been taken.
-__device__ __forceinline__ int next_ray(int* __restrict__ ctr, int cnt, int chunk, int lane) {
-  int r = -1;
-  if (lane == 0) {
-    if (chunk <= 0) {
-      const int i = atomicAdd(ctr, 1);
-      r = i < cnt ? i : -1;
-    } else {
-      const int home = blockIdx.x % kXcds;
-      for (int k = 0; k < kXcds && r < 0; ++k) {
-        const int x = (home + k) % kXcds;
-        const int c0 = __hip_atomic_load(ctr + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (((int64_t)(c0 / chunk) * kXcds + x) * chunk + c0 % chunk >= cnt) continue;
-        const int i = atomicAdd(ctr + x, 1);
-        const int64_t ray = ((int64_t)(i / chunk) * kXcds + x) * chunk + i % chunk;
-        if (ray < cnt) r = (int)ray;
-      }
+// Ray work queue of the persistent march kernels.  chunk == 0: one queue for
+// the whole device.  chunk > 0: the rays [0, cnt) are cut into chunks of
+// `chunk` rays dealt round-robin to the kXcds dies; the waves of workgroups on
+// die x = blockIdx.x % kXcds take the rays of die x's chunks in order
+// (neighbouring rays then share that die's L2), then help the other dies.
+// A wave takes `batch` queue positions per atomic, when it needs them: taking
+// them any earlier widens the window of rays in flight, and the march is
+// fastest when neighbouring rays are marched at the same time (they share
+// cache lines of the hash table).  ctr: kXcds counters, zero at launch.
+struct WorkQueue {
+  int* ctr;
+  int cnt, chunk, batch, die, tries;
+  __device__ __forceinline__ WorkQueue(int* c, int n, int ch, int b)
+      : ctr(c), cnt(n), chunk(ch), batch(b > 0 ? b : 1), die(ch > 0 ? (int)(blockIdx.x % kXcds) : 0), tries(0) {}
+  __device__ __forceinline__ int map(int i) const {
+    if (chunk <= 0) return i;
+    const int64_t r = ((int64_t)(i / chunk) * kXcds + die) * chunk + i % chunk;
+    return r < cnt ? (int)r : cnt;
+  }
+  // Start of the wave's next batch in queue positions of `die`, or -1 when
+  // every ray has been taken.
+  __device__ __forceinline__ int next(int lane) {
+    while (true) {
+      int v = 0;
+      if (lane == 0) v = atomicAdd(ctr + die, batch);
+      const int base = __shfl(v, 0, 64);
+      if (map(base) < cnt) return base;
+      if (chunk <= 0 || ++tries >= kXcds) return -1;
+      die = (die + 1) % kXcds;
     }
   }
-  return __shfl(r, 0, 64);
-}
+};
 
 size_t queue_bytes(int64_t cap);
 RayQueue queue_at(void* base, int64_t cap);

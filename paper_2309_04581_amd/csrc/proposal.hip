@@ -112,6 +112,25 @@ __device__ __forceinline__ float prop_density(const FieldView& P, const TabT* __
   return softplusf(acc + P.density_offset);
 }
 
+// Forward-only proposal density for the march.  The hidden loop stays rolled
+// so the 176 weights are read from LDS as they are used instead of being held
+// in registers across the whole segment.
+template <typename TabT>
+__device__ __forceinline__ float prop_sigma(const FieldView& P, const TabT* __restrict__ table,
+                                           const float* __restrict__ W, float px, float py, float pz) {
+  float feat[kPropIn];
+  hash_encode<kPropLevels, TabT>(P, table, px, py, pz, feat);
+  float acc = 0.0f;
+#pragma unroll 1
+  for (int i = 0; i < kPropHidden; ++i) {
+    float h = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kPropIn; ++c) h += W[i * kPropIn + c] * feat[c];
+    acc += W[kPropIn * kPropHidden + i] * fmaxf(h, 0.0f);
+  }
+  return softplusf(acc + P.density_offset);
+}
+
 // ---------------------------------------------------------------------------
 // proposal-sampled march (one wave per ray)
 // ---------------------------------------------------------------------------
@@ -131,9 +150,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int cnt = *count;
   const bool use_occ = P.use_occupancy && F.occ;
   unsigned long long nsamp = 0;
-  while (true) {
-    const int r = next_ray(work, cnt, P.chunk, lane);
-    if (r < 0) break;
+  WorkQueue wq(work, cnt, P.chunk, P.batch);
+  for (int base = wq.next(lane); base >= 0; base = wq.next(lane))
+  for (int bi = 0; bi < wq.batch; ++bi) {
+    const int r = wq.map(base + bi);
+    if (r >= cnt) break;
     const float ox = q.ox[r], oy = q.oy[r], oz = q.oz[r];
     const float dx = q.dx[r], dy = q.dy[r], dz = q.dz[r];
     const int seg = q.depth[r] & 0xFFFF;
@@ -148,8 +169,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     float alpha_p = 0.0f;
     if (lane < n_prop) {
       const float tm = lo + ((float)lane + 0.5f) * Dp;
-      float feat[kPropIn], hpre[kPropHidden], z;
-      const float sp = prop_density<PTabT>(Pf, ptable, sP, ox + tm * dx, oy + tm * dy, oz + tm * dz, feat, hpre, z);
+      const float sp = prop_sigma<PTabT>(Pf, ptable, sP, ox + tm * dx, oy + tm * dy, oz + tm * dz);
       alpha_p = -expm1f(-sp * Dp);
     }
     const float inclT = wscan_mul(1.0f - alpha_p, lane);

@@ -398,6 +398,7 @@ mr_status validate_render(const mr_field* field, const mr_mesh* mesh, int64_t n,
   if (opts->stage_tile < 0 || opts->stage_tile % kTraceBlock != 0 || opts->stage_tile > (1 << 20))
     return fail(MR_ERR_INVALID_ARG, "stage_tile must be a multiple of 128 (or 0)");
   if (opts->march_chunk < 0) return fail(MR_ERR_INVALID_ARG, "march_chunk must be >= 0");
+  if (opts->march_batch < 0 || opts->march_batch > 64) return fail(MR_ERR_INVALID_ARG, "march_batch must be in 0..64");
   if (opts->use_occupancy && field && !field->occ_dev)
     return fail(MR_ERR_STATE, "use_occupancy set but the field has no occupancy grid");
   return MR_OK;
@@ -449,6 +450,7 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
   P.delta = P.span / (float)opts->n_samples;
   P.use_occupancy = opts->use_occupancy;
   P.chunk = opts->march_chunk;
+  P.batch = opts->march_batch > 0 ? opts->march_batch : 1;
 
   ShadeParams S;
   std::memset(&S, 0, sizeof(S));
@@ -663,6 +665,7 @@ extern "C" mr_status mr_autotune_render(const mr_field* field, const mr_mesh* me
     o.stage_blocks_per_cu = host_cands[c].stage_blocks_per_cu;
     o.stage_tile = host_cands[c].stage_tile;
     o.march_chunk = host_cands[c].march_chunk;
+    o.march_batch = host_cands[c].march_batch;
     s = mr_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, host_lights, n_lights, &o, out,
                   workspace, workspace_bytes, stream);
     if (s != MR_OK) break;
