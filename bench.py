@@ -14,6 +14,7 @@ shade/compaction per bounce) for all 640 000 primary rays, with field, mesh
 and workspace resident in HBM.  Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -26,6 +27,39 @@ sys.path.insert(0, ROOT)
 METRIC = "rays/sec (full bounce paths) plain FP32 vs proposal+FP16 at >=40 dB PSNR"
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3   # MI355X published dense FP32 matrix peak
+
+
+# Sources that make up the march kernel: HBM traffic taken with rocprofv3
+# counters is reported only while they are unchanged since the counters were taken.
+MARCH_SOURCES = ["march_mfma.hip", "mr_mfma.h", "mr_field_kernels.h", "mr_device.h", "mr_render.h",
+                 "mr_common.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_march_mfma_mid_hbm_traffic.md")
+
+
+def march_sources_sha256():
+    h = hashlib.sha256()
+    for f in MARCH_SOURCES + ["../../include/meshrf.h"]:
+        with open(os.path.join(ROOT, "paper_2309_04581_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per march launch (FETCH_SIZE + WRITE_SIZE, each scaled by a
+    plain copy's reading) from the committed counter summary, or None when the
+    march sources have changed since it was taken."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for ln in fh:
+                if ":" in ln and ln.split(":", 1)[0].strip() in ("traffic_bytes_per_launch", "march_sources_sha256"):
+                    k, v = ln.split(":", 1)
+                    kv[k.strip()] = v.strip().strip("`")
+        if kv.get("march_sources_sha256") != march_sources_sha256():
+            return None
+        return int(float(kv["traffic_bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def field_macs(f):
@@ -311,7 +345,8 @@ def main():
                               "shade": round(stage_ms[2] / args.steps, 3)},
         "roofline": {"kernel": "k_march_mfma", "bound": "mfma", "achieved": round(tflops, 2),
                      "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(tflops / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(tflops / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per launch (L2 fetch + write, copy-calibrated)",
                      "launch_ms": round(march_launch_ms, 4),
                      "launches_per_step": launches_per_step},
         "gather": {"achieved": round(gbs, 1), "unit": "GB/s", "peak_hbm": HBM_PEAK_GBS,

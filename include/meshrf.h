@@ -188,11 +188,19 @@ typedef struct {
                                    8 dies (workgroup i runs on die i % 8), each die's
                                    waves taking their own chunks first */
   int32_t march_batch;          /* rays a march wave takes per queue grab, 1..64 (0 = 1) */
+  int32_t march_packets;        /* leading bounce segments (uniform sampler) marched as
+                                   packets: a wave takes 16 consecutive queue rays and
+                                   steps them through the same sample index together, so
+                                   rays that are neighbours in the queue and in space
+                                   (camera pixels of one image row) share cache lines of
+                                   the table; later segments march one ray per wave, 16
+                                   samples per tile.  0 = default (1: the caller's rays),
+                                   -1 = none, k > 0 = segments 0..k-1 */
 } mr_render_opts;
 
 /* One launch shape (the launch fields of mr_render_opts). */
 typedef struct {
-  int32_t march_blocks_per_cu, stage_blocks_per_cu, stage_tile, march_chunk, march_batch;
+  int32_t march_blocks_per_cu, stage_blocks_per_cu, stage_tile, march_chunk, march_batch, march_packets;
 } mr_launch_cfg;
 
 typedef struct {

@@ -1,11 +1,19 @@
 // Segment march and point queries with the field MLPs on the matrix cores.
 //
-// Same quadrature as the vector-unit march (Eq. 10-11: alpha compositing of
-// midpoint samples on the fixed interval grid, Eq. 8-9), but a wave works
-// through a ray's samples 16 at a time: each lane gathers the hash features
-// of one level group for one sample (mr_mfma.h), the density and colour MLPs
-// run as 16x16 MFMA tiles (FP32, or BF16 with FP32 accumulation), and the
-// compositing is a 16-lane prefix product carried from tile to tile.
+// Quadrature of Eq. 10-11 (alpha compositing of midpoint samples on the
+// fixed interval grid, Eq. 8-9).  Each lane gathers the hash features of one
+// level group for one sample (mr_mfma.h) and the density and colour MLPs run
+// as 16x16 MFMA tiles (FP32, or BF16 with FP32 accumulation) whose 16 columns
+// are 16 samples.  Two ways to fill the columns:
+//   packets  - a wave takes 16 consecutive queue rays and steps them through
+//              the same sample index together (column j = ray j); neighbouring
+//              camera pixels then read the same cache lines of the table at
+//              every level, and compositing is a running product per column;
+//   per ray  - a wave takes one ray and 16 consecutive samples of it per tile
+//              (column j = sample j), composited by a 16-lane prefix product
+//              carried from tile to tile; better for incoherent bounce rays
+//              and for short queues, where one ray's samples would otherwise
+//              be walked one at a time.
 #include <cstring>
 #include <vector>
 
@@ -62,7 +70,7 @@ __device__ __forceinline__ bool occ_lookup(const FieldView& F, float px, float p
   return (F.occ[c >> 5] >> (c & 31)) & 1u;
 }
 
-template <int NL, int SH, int CL, typename TabT, bool BF>
+template <int NL, int SH, int CL, typename TabT, bool BF, bool PK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_march_mfma(RayQueue q, const int* __restrict__ count, int* __restrict__ work,
                                                     FieldView F, const TabT* __restrict__ table,
                                                     const uint32_t* __restrict__ frags, MarchParams P,
@@ -74,63 +82,132 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
   const int cnt = *count;
   const bool use_occ = P.use_occupancy && F.occ;
+  const float delta = P.delta;
   unsigned long long nsamp = 0;
-  WorkQueue wq(work, cnt, P.chunk, P.batch);
-  for (int base = wq.next(lane); base >= 0; base = wq.next(lane))
-  for (int bi = 0; bi < wq.batch; ++bi) {
-    const int r = wq.map(base + bi);
-    if (r >= cnt) break;
-    const float ox = q.ox[r], oy = q.oy[r], oz = q.oz[r];
-    const float dx = q.dx[r], dy = q.dy[r], dz = q.dz[r];
-    const int seg = q.depth[r] & 0xFFFF;
-    const float t_a = seg == 0 ? P.t_near : 0.0f;
-    float box0, box1;
-    if (!slab_box(F, ox, oy, oz, dx, dy, dz, box0, box1)) continue;
-    const float lo = fmaxf(t_a, box0);
-    const float hi = fminf(fminf(t_a + P.span, q.hit_t[r]), box1);
-    if (!(hi > lo)) continue;
-    const float delta = P.delta;
-    const int k0 = max(0, (int)floorf((lo - t_a) / delta) - 1);
-    const int k1 = min(P.n_samples, (int)ceilf((hi - t_a) / delta) + 1);
-    float u[4][4];
-    sh_rows<NL, SH, CL, BF>(sW, dx, dy, dz, lane, u);
-    float Tseg = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
-    for (int kb = k0; kb < k1; kb += 16) {
-      const int k = kb + j;
-      const float a = fmaxf(t_a + (float)k * delta, lo);
-      const float b = fminf(t_a + (float)(k + 1) * delta, hi);
-      bool valid = k < k1 && b > a;
-      const float tm = 0.5f * (a + b), D = b - a;
-      const float px = ox + tm * dx, py = oy + tm * dy, pz = oz + tm * dz;
-      if (valid && use_occ) valid = occ_lookup(F, px, py, pz);
-      if (__ballot(valid) == 0ull) continue;
-      float fe[LY::NF];
-      encode_group<NL, TabT>(F, table, px, py, pz, g, fe);
-      float sigma, rgb[3];
-      f4v raw;
-      mlp_tile<NL, SH, CL, BF>(sW, fe, u, F.density_offset, lane, sigma, rgb, raw);
-      const float alpha = valid ? -expm1f(-sigma * D) : 0.0f;
-      const float incl = scan16_mul(1.0f - alpha, j);
-      float excl = __shfl_up(incl, 1, 16);
-      if (j == 0) excl = 1.0f;
-      const float w = Tseg * excl * alpha;
-      acc0 += w * rgb[0];
-      acc1 += w * rgb[1];
-      acc2 += w * rgb[2];
-      Tseg *= __shfl(incl, 15, 16);
-      if (g == 0 && valid) ++nsamp;
+  if constexpr (PK) {
+    // A wave marches a packet of 16 consecutive queue rays in step: column j of
+    // every tile is ray j of the packet at the same sample index k.
+    WorkQueue wq(work, cnt, P.chunk, 16);
+    for (int base = wq.next(lane); base >= 0; base = wq.next(lane)) {
+      const int r = wq.map(base + j);
+      bool live = r < cnt;
+      float ox = 0.0f, oy = 0.0f, oz = 0.0f, dx = 0.0f, dy = 0.0f, dz = 1.0f;
+      float t_a = 0.0f, lo = 0.0f, hi = 0.0f;
+      int k0 = P.n_samples, k1 = 0;
+      if (live) {
+        ox = q.ox[r]; oy = q.oy[r]; oz = q.oz[r];
+        dx = q.dx[r]; dy = q.dy[r]; dz = q.dz[r];
+        t_a = (q.depth[r] & 0xFFFF) == 0 ? P.t_near : 0.0f;
+        float box0, box1;
+        live = slab_box(F, ox, oy, oz, dx, dy, dz, box0, box1);
+        if (live) {
+          lo = fmaxf(t_a, box0);
+          hi = fminf(fminf(t_a + P.span, q.hit_t[r]), box1);
+          live = hi > lo;
+        }
+        if (live) {
+          k0 = max(0, (int)floorf((lo - t_a) / delta) - 1);
+          k1 = min(P.n_samples, (int)ceilf((hi - t_a) / delta) + 1);
+        }
+      }
+      int kmin = k0, kmax = k1;
+  #pragma unroll
+      for (int off = 1; off < 16; off <<= 1) {
+        kmin = min(kmin, __shfl_xor(kmin, off, 16));
+        kmax = max(kmax, __shfl_xor(kmax, off, 16));
+      }
+      if (kmin >= kmax) continue;
+      float u[4][4];
+      sh_rows<NL, SH, CL, BF>(sW, dx, dy, dz, lane, u);
+      float T = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
+      for (int k = kmin; k < kmax; ++k) {
+        const float a = fmaxf(t_a + (float)k * delta, lo);
+        const float b = fminf(t_a + (float)(k + 1) * delta, hi);
+        bool valid = live && k >= k0 && k < k1 && b > a;
+        const float tm = 0.5f * (a + b), D = b - a;
+        const float px = ox + tm * dx, py = oy + tm * dy, pz = oz + tm * dz;
+        if (valid && use_occ) valid = occ_lookup(F, px, py, pz);
+        if (__ballot(valid) == 0ull) continue;
+        float fe[LY::NF];
+        encode_group<NL, TabT>(F, table, px, py, pz, g, fe);
+        float sigma, rgb[3];
+        f4v raw;
+        mlp_tile<NL, SH, CL, BF>(sW, fe, u, F.density_offset, lane, sigma, rgb, raw);
+        const float alpha = valid ? -expm1f(-sigma * D) : 0.0f;
+        const float w = T * alpha;
+        acc0 += w * rgb[0];
+        acc1 += w * rgb[1];
+        acc2 += w * rgb[2];
+        T *= 1.0f - alpha;
+        if (g == 0 && valid) ++nsamp;
+      }
+      if (live && g == 0) {
+        const float tr = q.tr[r], tg = q.tg[r], tb = q.tb[r];
+        q.lr[r] += tr * acc0;
+        q.lg[r] += tg * acc1;
+        q.lb[r] += tb * acc2;
+        q.tr[r] = tr * T;
+        q.tg[r] = tg * T;
+        q.tb[r] = tb * T;
+      }
     }
-    acc0 = sum16(acc0);
-    acc1 = sum16(acc1);
-    acc2 = sum16(acc2);
-    if (lane == 0) {
-      const float tr = q.tr[r], tg = q.tg[r], tb = q.tb[r];
-      q.lr[r] += tr * acc0;
-      q.lg[r] += tg * acc1;
-      q.lb[r] += tb * acc2;
-      q.tr[r] = tr * Tseg;
-      q.tg[r] = tg * Tseg;
-      q.tb[r] = tb * Tseg;
+  } else {
+    WorkQueue wq(work, cnt, P.chunk, P.batch);
+    for (int base = wq.next(lane); base >= 0; base = wq.next(lane))
+    for (int bi = 0; bi < wq.batch; ++bi) {
+      const int r = wq.map(base + bi);
+      if (r >= cnt) break;
+      const float ox = q.ox[r], oy = q.oy[r], oz = q.oz[r];
+      const float dx = q.dx[r], dy = q.dy[r], dz = q.dz[r];
+      const int seg = q.depth[r] & 0xFFFF;
+      const float t_a = seg == 0 ? P.t_near : 0.0f;
+      float box0, box1;
+      if (!slab_box(F, ox, oy, oz, dx, dy, dz, box0, box1)) continue;
+      const float lo = fmaxf(t_a, box0);
+      const float hi = fminf(fminf(t_a + P.span, q.hit_t[r]), box1);
+      if (!(hi > lo)) continue;
+      const int k0 = max(0, (int)floorf((lo - t_a) / delta) - 1);
+      const int k1 = min(P.n_samples, (int)ceilf((hi - t_a) / delta) + 1);
+      float u[4][4];
+      sh_rows<NL, SH, CL, BF>(sW, dx, dy, dz, lane, u);
+      float Tseg = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
+      for (int kb = k0; kb < k1; kb += 16) {
+        const int k = kb + j;
+        const float a = fmaxf(t_a + (float)k * delta, lo);
+        const float b = fminf(t_a + (float)(k + 1) * delta, hi);
+        bool valid = k < k1 && b > a;
+        const float tm = 0.5f * (a + b), D = b - a;
+        const float px = ox + tm * dx, py = oy + tm * dy, pz = oz + tm * dz;
+        if (valid && use_occ) valid = occ_lookup(F, px, py, pz);
+        if (__ballot(valid) == 0ull) continue;
+        float fe[LY::NF];
+        encode_group<NL, TabT>(F, table, px, py, pz, g, fe);
+        float sigma, rgb[3];
+        f4v raw;
+        mlp_tile<NL, SH, CL, BF>(sW, fe, u, F.density_offset, lane, sigma, rgb, raw);
+        const float alpha = valid ? -expm1f(-sigma * D) : 0.0f;
+        const float incl = scan16_mul(1.0f - alpha, j);
+        float excl = __shfl_up(incl, 1, 16);
+        if (j == 0) excl = 1.0f;
+        const float w = Tseg * excl * alpha;
+        acc0 += w * rgb[0];
+        acc1 += w * rgb[1];
+        acc2 += w * rgb[2];
+        Tseg *= __shfl(incl, 15, 16);
+        if (g == 0 && valid) ++nsamp;
+      }
+      acc0 = sum16(acc0);
+      acc1 = sum16(acc1);
+      acc2 = sum16(acc2);
+      if (lane == 0) {
+        const float tr = q.tr[r], tg = q.tg[r], tb = q.tb[r];
+        q.lr[r] += tr * acc0;
+        q.lg[r] += tg * acc1;
+        q.lb[r] += tb * acc2;
+        q.tr[r] = tr * Tseg;
+        q.tg[r] = tg * Tseg;
+        q.tb[r] = tb * Tseg;
+      }
     }
   }
   if (stats) {
@@ -187,10 +264,15 @@ __global__ __launch_bounds__(256) void k_query_mfma(FieldView F, const TabT* __r
 
 template <int NL, int SH, int CL, typename TabT, bool BF>
 mr_status launch_march_mfma(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
-                            unsigned long long* stats, int blocks, hipStream_t st) {
+                            bool packets, unsigned long long* stats, int blocks, hipStream_t st) {
   const uint32_t* fr = BF ? f->frag_bf16_dev : f->frag_f32_dev;
-  hipLaunchKernelGGL((k_march_mfma<NL, SH, CL, TabT, BF>), dim3(blocks), dim3(256), 0, st, q, count, work, f->view,
-                     reinterpret_cast<const TabT*>(f->table_dev), fr, P, stats);
+  const TabT* tab = reinterpret_cast<const TabT*>(f->table_dev);
+  if (packets)
+    hipLaunchKernelGGL((k_march_mfma<NL, SH, CL, TabT, BF, true>), dim3(blocks), dim3(256), 0, st, q, count, work,
+                       f->view, tab, fr, P, stats);
+  else
+    hipLaunchKernelGGL((k_march_mfma<NL, SH, CL, TabT, BF, false>), dim3(blocks), dim3(256), 0, st, q, count, work,
+                       f->view, tab, fr, P, stats);
   MR_HIP(hipGetLastError());
   return MR_OK;
 }
@@ -269,15 +351,15 @@ std::vector<uint32_t> build_fragments(const mr_field_desc& d, const float* mlp, 
 }
 
 mr_status dispatch_march_mfma(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
-                              unsigned long long* stats, int blocks, hipStream_t st) {
+                              bool packets, unsigned long long* stats, int blocks, hipStream_t st) {
   const auto& v = f->view;
   const bool h = v.table_dtype == MR_F16, bf = v.mlp_dtype == MR_BF16;
 #define M(NL, SH, CL)                                                                                              \
   if (v.n_levels == NL && v.sh == SH && v.c_layers == CL) {                                                         \
-    if (bf) return h ? launch_march_mfma<NL, SH, CL, __half, true>(f, q, count, work, P, stats, blocks, st)         \
-                     : launch_march_mfma<NL, SH, CL, float, true>(f, q, count, work, P, stats, blocks, st);         \
-    return h ? launch_march_mfma<NL, SH, CL, __half, false>(f, q, count, work, P, stats, blocks, st)                \
-             : launch_march_mfma<NL, SH, CL, float, false>(f, q, count, work, P, stats, blocks, st);                \
+    if (bf) return h ? launch_march_mfma<NL, SH, CL, __half, true>(f, q, count, work, P, packets, stats, blocks, st)         \
+                     : launch_march_mfma<NL, SH, CL, float, true>(f, q, count, work, P, packets, stats, blocks, st);         \
+    return h ? launch_march_mfma<NL, SH, CL, __half, false>(f, q, count, work, P, packets, stats, blocks, st)                \
+             : launch_march_mfma<NL, SH, CL, float, false>(f, q, count, work, P, packets, stats, blocks, st);                \
   }
   M(8, 4, 1)
   M(16, 16, 2)

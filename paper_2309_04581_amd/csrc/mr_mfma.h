@@ -204,9 +204,10 @@ __device__ __forceinline__ void mlp_tile(const uint32_t* __restrict__ W, const f
 }
 
 // SH contribution to colour layer 1 for hidden rows mt*16 + 4g + v: the
-// product Wc1[:, 16:16+SH] x SH(d), the same for every sample of a ray, as
-// FP32 MFMAs whose B operand is the SH vector in every column (lane group g
-// supplies component 4 ks + g), so the result lands in the C layout.
+// product Wc1[:, 16:16+SH] x SH(d_j), where d_j is the direction lane (g, j)
+// passes for column j (one ray for all columns, or one ray per column), as
+// FP32 MFMAs whose B operand column j is SH(d_j) (lane group g supplies
+// component 4 ks + g), so the result lands in the C layout.
 template <int NL, int SH, int CL, bool BF>
 __device__ __forceinline__ void sh_rows(const uint32_t* __restrict__ W, float dx, float dy, float dz, int lane,
                                         float (&u)[4][4]) {

@@ -82,8 +82,9 @@ RayQueue queue_at(void* base, int64_t cap);
 int device_cus();
 
 // matrix-core march (march_mfma.hip)
+// packets: 16 consecutive queue rays per wave in step (else one ray per wave)
 mr_status dispatch_march_mfma(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
-                              unsigned long long* stats, int blocks, hipStream_t st);
+                              bool packets, unsigned long long* stats, int blocks, hipStream_t st);
 
 // proposal-sampled march (defined with the proposal kernels)
 mr_status dispatch_march_proposal(const mr_field* f, const mr_field* prop, RayQueue q, const int* count, int* work,

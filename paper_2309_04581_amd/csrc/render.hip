@@ -399,6 +399,7 @@ mr_status validate_render(const mr_field* field, const mr_mesh* mesh, int64_t n,
     return fail(MR_ERR_INVALID_ARG, "stage_tile must be a multiple of 128 (or 0)");
   if (opts->march_chunk < 0) return fail(MR_ERR_INVALID_ARG, "march_chunk must be >= 0");
   if (opts->march_batch < 0 || opts->march_batch > 64) return fail(MR_ERR_INVALID_ARG, "march_batch must be in 0..64");
+  if (opts->march_packets < -1) return fail(MR_ERR_INVALID_ARG, "march_packets must be >= -1");
   if (opts->use_occupancy && field && !field->occ_dev)
     return fail(MR_ERR_STATE, "use_occupancy set but the field has no occupancy grid");
   return MR_OK;
@@ -476,6 +477,7 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
   const int trace_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + tile - 1) / tile, (int64_t)cus * sbpc));
   // at least kXcds blocks so that every die has a home partition served
   const int march_blocks = (int)std::max<int64_t>(kXcds, std::min<int64_t>((n + 3) / 4, (int64_t)cus * mbpc));
+  const int packet_segments = opts->march_packets == 0 ? 1 : std::max(0, opts->march_packets);
   for (int b = 0; b <= max_bounces; ++b) {
     RayQueue& qi = Q[b & 1];
     RayQueue& qo = Q[(b + 1) & 1];
@@ -491,7 +493,8 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
         s = dispatch_march_proposal(field, opts->proposal, qi, counts + b, work + kXcds * b, P, opts->n_proposal,
                                     opts->n_fine, stats, march_blocks, st);
       else
-        s = dispatch_march_mfma(field, qi, counts + b, work + kXcds * b, P, stats, march_blocks, st);
+        s = dispatch_march_mfma(field, qi, counts + b, work + kXcds * b, P, b < packet_segments, stats, march_blocks,
+                                st);
       if (s != MR_OK) return s;
     }
     {
@@ -666,6 +669,7 @@ extern "C" mr_status mr_autotune_render(const mr_field* field, const mr_mesh* me
     o.stage_tile = host_cands[c].stage_tile;
     o.march_chunk = host_cands[c].march_chunk;
     o.march_batch = host_cands[c].march_batch;
+    o.march_packets = host_cands[c].march_packets;
     s = mr_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, host_lights, n_lights, &o, out,
                   workspace, workspace_bytes, stream);
     if (s != MR_OK) break;

@@ -64,12 +64,14 @@ class RenderOpts(C.Structure):
                 ("n_fine", C.c_int32), ("use_occupancy", C.c_int32), ("rr_after", C.c_int32),
                 ("t_min_throughput", C.c_float), ("seed", C.c_uint32),
                 ("march_blocks_per_cu", C.c_int32), ("stage_blocks_per_cu", C.c_int32),
-                ("stage_tile", C.c_int32), ("march_chunk", C.c_int32), ("march_batch", C.c_int32)]
+                ("stage_tile", C.c_int32), ("march_chunk", C.c_int32), ("march_batch", C.c_int32),
+                ("march_packets", C.c_int32)]
 
 
 class LaunchCfg(C.Structure):
     _fields_ = [("march_blocks_per_cu", C.c_int32), ("stage_blocks_per_cu", C.c_int32),
-                ("stage_tile", C.c_int32), ("march_chunk", C.c_int32), ("march_batch", C.c_int32)]
+                ("stage_tile", C.c_int32), ("march_chunk", C.c_int32), ("march_batch", C.c_int32),
+                ("march_packets", C.c_int32)]
 
 
 class Adam(C.Structure):
@@ -451,12 +453,12 @@ def mr_graph_destroy(graph):
 def mr_autotune_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, lights, opts, out,
                        workspace, workspace_bytes, candidates, reps=2, stream=None):
     """candidates: sequence of (march_blocks_per_cu, stage_blocks_per_cu, stage_tile, march_chunk,
-    march_batch)."""
+    march_batch, march_packets)."""
     arr, nl = _lights_arr(lights)
     cands = (LaunchCfg * len(candidates))()
     for i, c in enumerate(candidates):
         (cands[i].march_blocks_per_cu, cands[i].stage_blocks_per_cu, cands[i].stage_tile,
-         cands[i].march_chunk, cands[i].march_batch) = c
+         cands[i].march_chunk, cands[i].march_batch, cands[i].march_packets) = c
     best = C.c_int32()
     ms = C.c_float()
     _check(lib().mr_autotune_render(field, mesh, C.c_int64(n), _ptr(origins), _ptr(dirs), C.c_int32(max_bounces),

@@ -4,6 +4,7 @@ Tolerances: hit triangle ids, bounce counts and occupancy bits are compared
 bit-exactly on rays (cells) the oracle does not flag as ties; radiance and
 throughput per channel within |a - b| <= 1e-4 |b| + 1e-7 (FP32 arithmetic
 against FP64); field values with the bounds derived at each test."""
+import functools
 import math
 
 import numpy as np
@@ -68,7 +69,7 @@ def oracle_camera_rays(scene):
 
 
 def gpu_render(scene, o, d, field=None, mesh=None, table_dtype=0, mlp_dtype=0, use_occupancy=False,
-               occ_res=0, max_bounces=None, per_ray=None):
+               occ_res=0, max_bounces=None, per_ray=None, packets=0):
     M = mr()
     fld = field if field is not None else (M.Field(scene.field, table_dtype, mlp_dtype) if scene.field is not None else None)
     msh = mesh if mesh is not None else (M.Mesh(scene.mesh) if scene.mesh is not None else None)
@@ -77,6 +78,7 @@ def gpu_render(scene, o, d, field=None, mesh=None, table_dtype=0, mlp_dtype=0, u
     mb = scene.max_bounces if max_bounces is None else max_bounces
     R = M.Renderer(len(o), mb)
     opts = M.make_opts(scene, use_occupancy=use_occupancy)
+    opts.march_packets = packets
     R.render(fld, msh, dev(o), dev(d), scene.lights, opts,
              per_ray_max_bounces=None if per_ray is None else dev(per_ray, torch.int32))
     torch.cuda.synchronize()
@@ -271,13 +273,24 @@ def test_camera_rays_match_oracle():
 # whole paths
 # ---------------------------------------------------------------------------
 
-def test_render_tiny_scene_matches_oracle():
-    """The 64x64 camera, 8-level field, mirror cube, 64 samples, 4 bounces."""
-    sc = sg.tiny_scene()
+# march_packets settings: default (camera segment as 16-ray packets), none,
+# every segment
+PACKETS = [0, -1, 99]
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_image(name):
+    sc = sg.tiny_scene() if name == "tiny" else sg.mid_scene(width=48, height=40)
     o, d = oracle_camera_rays(sc)
-    r = orc.render(sc, o, d)
-    g = gpu_render(sc, o, d)
-    ties = compare_render(g, r, "tiny")
+    return sc, o, d, orc.render(sc, o, d)
+
+
+@pytest.mark.parametrize("packets", PACKETS)
+def test_render_tiny_scene_matches_oracle(packets):
+    """The 64x64 camera, 8-level field, mirror cube, 64 samples, 4 bounces."""
+    sc, o, d, r = _oracle_image("tiny")
+    g = gpu_render(sc, o, d, packets=packets)
+    ties = compare_render(g, r, f"tiny packets={packets}")
     assert ties < 40
     assert g["bounces"].max() == 1 and (g["hit_ids"][:, 0] >= 0).sum() > 100
 
@@ -294,14 +307,14 @@ def test_render_tiny_high_amplitude_field():
     compare_render(g, r, "tiny high amplitude", rtol=1e-3, atol=1e-6)
 
 
-def test_render_mid_scene_small_image_matches_oracle():
+@pytest.mark.parametrize("packets", PACKETS)
+def test_render_mid_scene_small_image_matches_oracle(packets):
     """Glass icosphere, mirror cube, lit diffuse floor, 16-level field,
-    256 samples, 8 bounces, on a 48x40 image of the same camera."""
-    sc = sg.mid_scene(width=48, height=40)
-    o, d = oracle_camera_rays(sc)
-    r = orc.render(sc, o, d)
-    g = gpu_render(sc, o, d)
-    compare_render(g, r, "mid 48x40")
+    256 samples, 8 bounces, on a 48x40 image of the same camera (the image
+    width is not a multiple of 16, so packets straddle rows)."""
+    sc, o, d, r = _oracle_image("mid")
+    g = gpu_render(sc, o, d, packets=packets)
+    compare_render(g, r, f"mid 48x40 packets={packets}")
     assert g["bounces"].max() >= 3
     assert (g["hit_ids"] >= 0).sum() > 500
 

@@ -91,7 +91,7 @@ def test_autotuner_picks_a_candidate_and_results_do_not_depend_on_launch_shape()
     R = M.Renderer(o.shape[0], sc.max_bounces)
     R.render(F, G, o, d, sc.lights, opts)
     ref = _outputs(R)
-    cands = [(2, 4, 128, 0, 1), (8, 16, 1024, 0, 4), (8, 16, 128, 64, 8), (4, 8, 256, 4096, 2)]
+    cands = [(2, 4, 128, 0, 1, 0), (8, 16, 1024, 0, 4, -1), (8, 16, 128, 64, 8, 3), (4, 8, 256, 4096, 2, 0)]
     best, ms = M.mr_autotune_render(F.handle, G.handle, o.shape[0], o, d, sc.max_bounces, None, sc.lights, opts,
                                     R.out, R.workspace, R.ws_bytes, cands, reps=2)
     assert best in cands and ms > 0
