@@ -87,8 +87,9 @@ mr_status dispatch_march_mfma(const mr_field* f, RayQueue q, const int* count, i
                               bool packets, unsigned long long* stats, int blocks, hipStream_t st);
 
 // proposal-sampled march (defined with the proposal kernels)
+// packets: 16 consecutive queue rays per wave when n_prop = 32 and n_fine <= 32
 mr_status dispatch_march_proposal(const mr_field* f, const mr_field* prop, RayQueue q, const int* count, int* work,
-                                  const MarchParams& P, int n_prop, int n_fine, unsigned long long* stats, int blocks,
-                                  hipStream_t st);
+                                  const MarchParams& P, int n_prop, int n_fine, bool packets,
+                                  unsigned long long* stats, int blocks, hipStream_t st);
 
 }  // namespace mr

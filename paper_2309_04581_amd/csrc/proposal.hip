@@ -253,6 +253,177 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 }
 
 // ---------------------------------------------------------------------------
+// proposal-sampled march, 16-ray packets (n_prop = 32, n_fine <= 32): a wave
+// takes 16 consecutive queue rays; lane (g, j) evaluates proposal intervals
+// 8g .. 8g+7 of ray j, the transmittance and CDF over the 32 intervals are a
+// local scan plus a scan over the four lane groups, the ray's CDF goes to a
+// per-wave LDS area where the lanes invert it for the fine edges, and the
+// fine samples of the 16 rays are stepped together as with the plain packets
+// ---------------------------------------------------------------------------
+constexpr int kPkBins = 32;
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int NL, int SH, int CL, typename TabT, bool BF, typename PTabT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_march_prop_pk(
+    RayQueue q, const int* __restrict__ count, int* __restrict__ work, FieldView F, const TabT* __restrict__ table,
+    const uint32_t* __restrict__ frags, FieldView Pf, const PTabT* __restrict__ ptable, MarchParams P, int n_fine,
+    unsigned long long* __restrict__ stats) {
+  using LY = FragLayout<NL, SH, CL, BF>;
+  __shared__ __align__(16) uint32_t sW[LY::TOTAL];
+  __shared__ float sP[kPropMlp];
+  __shared__ float sCdf[4][16][kPkBins], sBin[4][16][kPkBins], sEdge[4][16][kPkBins + 1];
+  for (int i = threadIdx.x; i < LY::TOTAL; i += blockDim.x) sW[i] = frags[i];
+  for (int i = threadIdx.x; i < kPropMlp; i += blockDim.x) sP[i] = Pf.mlp[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15, wv = threadIdx.x >> 6;
+  const int cnt = *count;
+  const bool use_occ = P.use_occupancy && F.occ;
+  constexpr float kInvBins = 1.0f / (float)kPkBins;
+  unsigned long long nsamp = 0;
+  WorkQueue wq(work, cnt, P.chunk, 16);
+  for (int base = wq.next(lane); base >= 0; base = wq.next(lane)) {
+    const int r = wq.map(base + j);
+    bool live = r < cnt;
+    float ox = 0.0f, oy = 0.0f, oz = 0.0f, dx = 0.0f, dy = 0.0f, dz = 1.0f, lo = 0.0f, hi = 0.0f;
+    if (live) {
+      ox = q.ox[r]; oy = q.oy[r]; oz = q.oz[r];
+      dx = q.dx[r]; dy = q.dy[r]; dz = q.dz[r];
+      const float t_a = (q.depth[r] & 0xFFFF) == 0 ? P.t_near : 0.0f;
+      float box0, box1;
+      live = seg_box(F, ox, oy, oz, dx, dy, dz, box0, box1);
+      if (live) {
+        lo = fmaxf(t_a, box0);
+        hi = fminf(fminf(t_a + P.span, q.hit_t[r]), box1);
+        live = hi > lo;
+      }
+    }
+    if (__ballot(live) == 0ull) continue;
+    // proposal opacities of this lane's 8 intervals
+    const float Dp = (hi - lo) / (float)kPkBins;
+    float al[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      al[p] = 0.0f;
+      if (live) {
+        const float tm = lo + ((float)(8 * g + p) + 0.5f) * Dp;
+        al[p] = -expm1f(-prop_sigma<PTabT>(Pf, ptable, sP, ox + tm * dx, oy + tm * dy, oz + tm * dz) * Dp);
+      }
+    }
+    // weights T_i alpha_i: local exclusive products times the product of the
+    // lower lane groups' totals
+    float w[8], run = 1.0f;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      w[p] = run * al[p];
+      run *= 1.0f - al[p];
+    }
+    float below = 1.0f;
+#pragma unroll
+    for (int gg = 0; gg < 3; ++gg) {
+      const float t = __shfl(run, gg * 16 + j, 64);
+      if (gg < g) below *= t;
+    }
+#pragma unroll
+    for (int p = 0; p < 8; ++p) w[p] *= below;
+    // dilate over adjacent intervals, mix half and half with a uniform density
+    float wl = __shfl(w[7], ((g + 3) & 3) * 16 + j, 64), wr = __shfl(w[0], ((g + 1) & 3) * 16 + j, 64);
+    if (g == 0) wl = 0.0f;
+    if (g == 3) wr = 0.0f;
+    float wd[8], part = 0.0f;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const float a = p > 0 ? w[p - 1] : wl, b = p < 7 ? w[p + 1] : wr;
+      wd[p] = fmaxf(w[p], fmaxf(a, b));
+      part += wd[p];
+    }
+    float wsum_all = part + __shfl_xor(part, 16, 64);
+    wsum_all += __shfl_xor(wsum_all, 32, 64);
+    const float add = wsum_all * kInvBins + 1e-3f * kInvBins;
+    float csum = 0.0f;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      wd[p] += add;
+      csum += wd[p];
+    }
+    float off = 0.0f;
+#pragma unroll
+    for (int gg = 0; gg < 3; ++gg) {
+      const float t = __shfl(csum, gg * 16 + j, 64);
+      if (gg < g) off += t;
+    }
+    float c = off;
+    wave_lds_sync();
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      c += wd[p];
+      sCdf[wv][j][8 * g + p] = c;
+      sBin[wv][j][8 * g + p] = wd[p];
+    }
+    const float tot = __shfl(c, 48 + j, 64);   // the last CDF value of ray j
+    wave_lds_sync();
+    // fine edges by inverse CDF at u = e / n_fine (lane group g takes e = g mod 4)
+    for (int e = g; e <= n_fine; e += 4) {
+      const float u = (float)e / (float)n_fine * tot;
+      int blo = 0, bhi = kPkBins - 1;
+#pragma unroll
+      for (int it = 0; it < 5; ++it) {
+        const int mid = (blo + bhi) >> 1;
+        if (sCdf[wv][j][mid] < u) blo = mid + 1;
+        else bhi = mid;
+      }
+      const float prev = blo > 0 ? sCdf[wv][j][blo - 1] : 0.0f;
+      float edge = lo + ((float)blo + (u - prev) / sBin[wv][j][blo]) * Dp;
+      if (e == 0) edge = lo;
+      if (e >= n_fine) edge = hi;
+      sEdge[wv][j][e] = edge;
+    }
+    wave_lds_sync();
+    float u_sh[4][4];
+    sh_rows<NL, SH, CL, BF>(sW, dx, dy, dz, lane, u_sh);
+    float T = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
+    for (int k = 0; k < n_fine; ++k) {
+      const float a = sEdge[wv][j][k], b = sEdge[wv][j][k + 1];
+      bool valid = live && b > a;
+      const float tm = 0.5f * (a + b), D = b - a;
+      const float px = ox + tm * dx, py = oy + tm * dy, pz = oz + tm * dz;
+      if (valid && use_occ) valid = occ_bit(F, px, py, pz);
+      if (__ballot(valid) == 0ull) continue;
+      float fe[LY::NF];
+      encode_group<NL, TabT>(F, table, px, py, pz, g, fe);
+      float sigma, rgb[3];
+      f4v raw;
+      mlp_tile<NL, SH, CL, BF>(sW, fe, u_sh, F.density_offset, lane, sigma, rgb, raw);
+      const float alpha = valid ? -expm1f(-sigma * D) : 0.0f;
+      const float wt = T * alpha;
+      acc0 += wt * rgb[0];
+      acc1 += wt * rgb[1];
+      acc2 += wt * rgb[2];
+      T *= 1.0f - alpha;
+      if (g == 0 && valid) ++nsamp;
+    }
+    if (live && g == 0) {
+      const float tr = q.tr[r], tg = q.tg[r], tb = q.tb[r];
+      q.lr[r] += tr * acc0;
+      q.lg[r] += tg * acc1;
+      q.lb[r] += tb * acc2;
+      q.tr[r] = tr * T;
+      q.tg[r] = tg * T;
+      q.tb[r] = tb * T;
+    }
+    wave_lds_sync();
+  }
+  if (stats) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nsamp += __shfl_xor(nsamp, off, 64);
+    if (lane == 0 && nsamp) atomicAdd(stats + 0, nsamp);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // training targets: the plain marcher's weights of the camera segment,
 // histogrammed over n_bins equal bins of [lo, hi] by interval overlap
 // ---------------------------------------------------------------------------
@@ -440,9 +611,16 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 
 template <int NL, int SH, int CL, typename TabT, bool BF, typename PTabT>
 mr_status launch_prop(const mr_field* f, const mr_field* p, RayQueue q, const int* count, int* work,
-                      const MarchParams& P, int n_prop, int n_fine, unsigned long long* stats, int blocks,
-                      hipStream_t st) {
+                      const MarchParams& P, int n_prop, int n_fine, bool packets, unsigned long long* stats,
+                      int blocks, hipStream_t st) {
   const uint32_t* fr = BF ? f->frag_bf16_dev : f->frag_f32_dev;
+  if (packets && n_prop == kPkBins && n_fine <= kPkBins) {
+    hipLaunchKernelGGL((k_march_prop_pk<NL, SH, CL, TabT, BF, PTabT>), dim3(blocks), dim3(256), 0, st, q, count, work,
+                       f->view, reinterpret_cast<const TabT*>(f->table_dev), fr, p->view,
+                       reinterpret_cast<const PTabT*>(p->table_dev), P, n_fine, stats);
+    MR_HIP(hipGetLastError());
+    return MR_OK;
+  }
   hipLaunchKernelGGL((k_march_prop<NL, SH, CL, TabT, BF, PTabT>), dim3(blocks), dim3(256), 0, st, q, count, work,
                      f->view, reinterpret_cast<const TabT*>(f->table_dev), fr, p->view,
                      reinterpret_cast<const PTabT*>(p->table_dev), P, n_prop, n_fine, stats);
@@ -489,14 +667,14 @@ mr_status check_prop(const mr_field* p, int64_t n, const float* o, const float* 
 namespace mr {
 
 mr_status dispatch_march_proposal(const mr_field* f, const mr_field* prop, RayQueue q, const int* count, int* work,
-                                  const MarchParams& P, int n_prop, int n_fine, unsigned long long* stats, int blocks,
-                                  hipStream_t st) {
+                                  const MarchParams& P, int n_prop, int n_fine, bool packets,
+                                  unsigned long long* stats, int blocks, hipStream_t st) {
   const auto& v = f->view;
   const bool h = v.table_dtype == MR_F16, bf = v.mlp_dtype == MR_BF16;
   const bool ph = prop->view.table_dtype == MR_F16;
 #define PR(NL, SH, CL, TT, BFV)                                                                                      \
-  return ph ? launch_prop<NL, SH, CL, TT, BFV, __half>(f, prop, q, count, work, P, n_prop, n_fine, stats, blocks, st) \
-            : launch_prop<NL, SH, CL, TT, BFV, float>(f, prop, q, count, work, P, n_prop, n_fine, stats, blocks, st);
+  return ph ? launch_prop<NL, SH, CL, TT, BFV, __half>(f, prop, q, count, work, P, n_prop, n_fine, packets, stats, blocks, st) \
+            : launch_prop<NL, SH, CL, TT, BFV, float>(f, prop, q, count, work, P, n_prop, n_fine, packets, stats, blocks, st);
 #define M(NL, SH, CL)                                                        \
   if (v.n_levels == NL && v.sh == SH && v.c_layers == CL) {                   \
     if (bf) {                                                                 \

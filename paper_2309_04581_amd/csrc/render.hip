@@ -491,7 +491,7 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
       StageTimer tm(1, st);
       if (opts->sampler == MR_SAMPLER_PROPOSAL)
         s = dispatch_march_proposal(field, opts->proposal, qi, counts + b, work + kXcds * b, P, opts->n_proposal,
-                                    opts->n_fine, stats, march_blocks, st);
+                                    opts->n_fine, b < packet_segments, stats, march_blocks, st);
       else
         s = dispatch_march_mfma(field, qi, counts + b, work + kXcds * b, P, b < packet_segments, stats, march_blocks,
                                 st);

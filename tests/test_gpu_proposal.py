@@ -1,6 +1,7 @@
 """Learned proposal sampler on the GPU against the FP64 oracle: training
 targets, loss and gradient, proposal-sampled rendering, and what training
 gains over the untrained proposal and over uniform sampling at equal budget."""
+import functools
 import math
 
 import numpy as np
@@ -70,26 +71,37 @@ def test_proposal_gradient_matches_oracle():
     assert (np.abs(rgt) > 0).sum() > 1000
 
 
-@pytest.mark.parametrize("fieldkind", ["tiny", "shell"])
-def test_proposal_sampled_render_matches_oracle(fieldkind):
-    """32 proposal + 32 fine samples per segment, same proposal parameters on
-    both sides (FP32 table): hit ids/bounces exact, radiance within 1e-4 (1e-3
-    for the shell field, whose density varies within a cell)."""
-    M = mr()
+@functools.lru_cache(maxsize=None)
+def _proposal_oracle(fieldkind, n_fine):
     sc = sg.tiny_scene()
     if fieldkind == "shell":
         sc.field = sg.shell_field()
     prop = sg.make_proposal(table_amp=0.5)
     o, d = oracle_camera_rays(sc)
-    r = orc.render(sc, o, d, proposal=prop, n_prop=32, n_fine=32)
+    return sc, prop, o, d, orc.render(sc, o, d, proposal=prop, n_prop=32, n_fine=n_fine)
+
+
+# (field, fine samples, march_packets): the camera segment in 16-ray packets
+# (default), no packets, packets on every segment, and 24 fine samples per
+# segment in packets
+@pytest.mark.parametrize("fieldkind,n_fine,packets", [("tiny", 32, 0), ("shell", 32, 0), ("tiny", 32, -1),
+                                                      ("shell", 32, -1), ("shell", 32, 99), ("shell", 24, 0)])
+def test_proposal_sampled_render_matches_oracle(fieldkind, n_fine, packets):
+    """32 proposal + n_fine fine samples per segment, same proposal parameters
+    on both sides (FP32 table): hit ids/bounces exact, radiance within 1e-4
+    (1e-3 for the shell field, whose density varies within a cell)."""
+    M = mr()
+    sc, prop, o, d, r = _proposal_oracle(fieldkind, n_fine)
     F, G = M.Field(sc.field), M.Mesh(sc.mesh)
     P = M.Field(prop, table_dtype=M.MR_F32)
     R = M.Renderer(len(o), sc.max_bounces)
-    R.render(F, G, dev(o), dev(d), sc.lights, M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P))
+    opts = M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P, n_fine=n_fine)
+    opts.march_packets = packets
+    R.render(F, G, dev(o), dev(d), sc.lights, opts)
     g = dict(radiance=host(R.radiance), throughput=host(R.throughput), bounces=host(R.bounces),
              hit_ids=host(R.hit_ids))
     tol = 1e-4 if fieldkind == "tiny" else 1e-3
-    compare_render(g, r, f"proposal {fieldkind}", rtol=tol, atol=1e-6)
+    compare_render(g, r, f"proposal {fieldkind} n_fine={n_fine} packets={packets}", rtol=tol, atol=1e-6)
 
 
 def test_training_gains_over_untrained_and_uniform():
