@@ -177,9 +177,10 @@ typedef struct {
   float t_min_throughput;    /* terminate when max channel of T drops below (1e-4) */
   uint32_t seed;             /* Philox4x32-10 key */
   int32_t march_blocks_per_cu;  /* launch shape of the persistent march grid: blocks of
-                                   4 waves per compute unit (0 = default 8) */
+                                   4 waves per compute unit (0 = as many as are resident
+                                   at once, from the occupancy of the kernel launched) */
   int32_t stage_blocks_per_cu;  /* closest-hit and shade grids: blocks of 128 threads
-                                   per compute unit (0 = default 16) */
+                                   per compute unit (0 = as many as are resident at once) */
   int32_t stage_tile;           /* rays a block takes per work-queue grab in the
                                    closest-hit and shade stages, a multiple of 128
                                    (0 = default 128) */

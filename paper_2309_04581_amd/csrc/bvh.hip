@@ -15,7 +15,9 @@ using namespace mr;
 
 namespace {
 
-constexpr int kMaxDepth = 44;   // < kStack
+constexpr int kMaxDepth = 44;
+// a traversal holds at most one pending sibling per level of its current path
+static_assert(kMaxDepth < kStack, "BVH depth must stay below the traversal stack size");
 constexpr int kBins = 32;
 
 struct Box {
@@ -213,10 +215,11 @@ __global__ __launch_bounds__(kTraceBlock) void k_closest(BvhView B, int64_t n, c
                                                          const float* __restrict__ d, float tmax,
                                                          float* __restrict__ t_hit, int32_t* __restrict__ tri) {
   __shared__ int stack[kStack * kTraceBlock];
+  __shared__ float tstack[kStack * kTraceBlock];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const RayPre r = ray_pre(v3(o[3 * i], o[3 * i + 1], o[3 * i + 2]), v3(d[3 * i], d[3 * i + 1], d[3 * i + 2]));
     float t;
-    const int p = bvh_trace<false>(B, r, tmax, t, stack + threadIdx.x, kTraceBlock);
+    const int p = bvh_trace<false>(B, r, tmax, t, stack + threadIdx.x, tstack + threadIdx.x, kTraceBlock);
     t_hit[i] = p >= 0 ? t : INFINITY;
     tri[i] = p >= 0 ? __float_as_int(B.tris[3 * p].w) : -1;
   }

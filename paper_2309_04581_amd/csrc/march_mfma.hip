@@ -264,15 +264,18 @@ __global__ __launch_bounds__(256) void k_query_mfma(FieldView F, const TabT* __r
 
 template <int NL, int SH, int CL, typename TabT, bool BF>
 mr_status launch_march_mfma(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
-                            bool packets, unsigned long long* stats, int blocks, hipStream_t st) {
+                            bool packets, unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st) {
   const uint32_t* fr = BF ? f->frag_bf16_dev : f->frag_f32_dev;
   const TabT* tab = reinterpret_cast<const TabT*>(f->table_dev);
-  if (packets)
-    hipLaunchKernelGGL((k_march_mfma<NL, SH, CL, TabT, BF, true>), dim3(blocks), dim3(256), 0, st, q, count, work,
-                       f->view, tab, fr, P, stats);
-  else
-    hipLaunchKernelGGL((k_march_mfma<NL, SH, CL, TabT, BF, false>), dim3(blocks), dim3(256), 0, st, q, count, work,
-                       f->view, tab, fr, P, stats);
+  if (packets) {
+    auto* k = k_march_mfma<NL, SH, CL, TabT, BF, true>;
+    const int blocks = persistent_blocks(reinterpret_cast<const void*>(k), 256, blocks_per_cu, (n + 63) / 64);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, q, count, work, f->view, tab, fr, P, stats);
+  } else {
+    auto* k = k_march_mfma<NL, SH, CL, TabT, BF, false>;
+    const int blocks = persistent_blocks(reinterpret_cast<const void*>(k), 256, blocks_per_cu, (n + 3) / 4);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, q, count, work, f->view, tab, fr, P, stats);
+  }
   MR_HIP(hipGetLastError());
   return MR_OK;
 }
@@ -351,15 +354,15 @@ std::vector<uint32_t> build_fragments(const mr_field_desc& d, const float* mlp, 
 }
 
 mr_status dispatch_march_mfma(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
-                              bool packets, unsigned long long* stats, int blocks, hipStream_t st) {
+                              bool packets, unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st) {
   const auto& v = f->view;
   const bool h = v.table_dtype == MR_F16, bf = v.mlp_dtype == MR_BF16;
 #define M(NL, SH, CL)                                                                                              \
   if (v.n_levels == NL && v.sh == SH && v.c_layers == CL) {                                                         \
-    if (bf) return h ? launch_march_mfma<NL, SH, CL, __half, true>(f, q, count, work, P, packets, stats, blocks, st)         \
-                     : launch_march_mfma<NL, SH, CL, float, true>(f, q, count, work, P, packets, stats, blocks, st);         \
-    return h ? launch_march_mfma<NL, SH, CL, __half, false>(f, q, count, work, P, packets, stats, blocks, st)                \
-             : launch_march_mfma<NL, SH, CL, float, false>(f, q, count, work, P, packets, stats, blocks, st);                \
+    if (bf) return h ? launch_march_mfma<NL, SH, CL, __half, true>(f, q, count, work, P, packets, stats, blocks_per_cu, n, st)         \
+                     : launch_march_mfma<NL, SH, CL, float, true>(f, q, count, work, P, packets, stats, blocks_per_cu, n, st);         \
+    return h ? launch_march_mfma<NL, SH, CL, __half, false>(f, q, count, work, P, packets, stats, blocks_per_cu, n, st)                \
+             : launch_march_mfma<NL, SH, CL, float, false>(f, q, count, work, P, packets, stats, blocks_per_cu, n, st);                \
   }
   M(8, 4, 1)
   M(16, 16, 2)

@@ -14,7 +14,7 @@ namespace mr {
 constexpr int kMaxLevels = 16;
 constexpr int kMaxMaterials = 16;
 constexpr int kMaxLights = 8;
-constexpr int kStack = 64;          // BVH traversal stack depth (tree depth is capped below it)
+constexpr int kStack = 48;          // BVH traversal stack depth (tree depth is capped below it)
 constexpr int kLeafSize = 4;
 constexpr int kTraceBlock = 128;    // threads per block of the traversal kernels
 

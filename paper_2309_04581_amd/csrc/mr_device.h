@@ -243,10 +243,13 @@ __device__ __forceinline__ float box_hit(const RayPre& r, float lx, float ly, fl
 
 // Closest hit (ANY = false): lexicographic minimum of (t, original id) over
 // 0 < t <= tmax.  Any hit (ANY = true): returns >= 0 for the first hit with
-// 0 < t < tmax.  stack: this thread's LDS stack, entry k at stack[k * stride].
+// 0 < t < tmax.  stack: this thread's LDS stack, entry k at stack[k * stride];
+// tstack (closest hit only): the entry distance of each pending node, so that
+// a node whose box starts beyond the best hit found since it was pushed is
+// dropped without loading it (its children start no earlier than it does).
 template <bool ANY>
 __device__ __forceinline__ int bvh_trace(const BvhView& B, const RayPre& r, float tmax, float& t_best,
-                                         int* stack, int stride) {
+                                         int* stack, float* tstack, int stride) {
   int best = -1, best_id = 0x7fffffff;
   t_best = tmax;
   int sp = 0;
@@ -287,15 +290,28 @@ __device__ __forceinline__ int bvh_trace(const BvhView& B, const RayPre& r, floa
       const bool swap = tin[1] < tin[0];
       next = swap ? inner[1] : inner[0];
       stack[sp * stride] = swap ? inner[0] : inner[1];
+      if constexpr (!ANY) tstack[sp * stride] = swap ? tin[0] : tin[1];
       ++sp;
     } else if (ninner == 1) {
       next = inner[0];
     }
     if (next < 0) {
-      // pop, skipping nodes whose boxes are now beyond the best hit is left to the box test
-      if (sp == 0) break;
-      --sp;
-      next = stack[sp * stride];
+      if constexpr (ANY) {
+        if (sp == 0) break;
+        --sp;
+        next = stack[sp * stride];
+      } else {
+        // the box test accepts entry distances up to its limit times 1.0000003576
+        const float reach = t_best * 1.0000003576f;
+        while (sp > 0) {
+          --sp;
+          if (tstack[sp * stride] <= reach) {
+            next = stack[sp * stride];
+            break;
+          }
+        }
+        if (next < 0) break;
+      }
     }
     node = next;
   }

@@ -81,15 +81,22 @@ size_t queue_bytes(int64_t cap);
 RayQueue queue_at(void* base, int64_t cap);
 int device_cus();
 
+// Blocks of a persistent grid of `kernel` (blocks of `threads`): `per_cu`
+// per compute unit, or, for per_cu = 0, as many as are resident at once by
+// the occupancy calculator (queried once per kernel); at least kXcds and at
+// most `cap`.
+int persistent_blocks(const void* kernel, int threads, int per_cu, int64_t cap);
+
 // matrix-core march (march_mfma.hip)
-// packets: 16 consecutive queue rays per wave in step (else one ray per wave)
+// packets: 16 consecutive queue rays per wave in step (else one ray per wave);
+// blocks_per_cu: 0 = as many as fit; n: rays in the queue at most
 mr_status dispatch_march_mfma(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
-                              bool packets, unsigned long long* stats, int blocks, hipStream_t st);
+                              bool packets, unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st);
 
 // proposal-sampled march (defined with the proposal kernels)
 // packets: 16 consecutive queue rays per wave when n_prop = 32 and n_fine <= 32
 mr_status dispatch_march_proposal(const mr_field* f, const mr_field* prop, RayQueue q, const int* count, int* work,
                                   const MarchParams& P, int n_prop, int n_fine, bool packets,
-                                  unsigned long long* stats, int blocks, hipStream_t st);
+                                  unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st);
 
 }  // namespace mr

@@ -612,18 +612,21 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 template <int NL, int SH, int CL, typename TabT, bool BF, typename PTabT>
 mr_status launch_prop(const mr_field* f, const mr_field* p, RayQueue q, const int* count, int* work,
                       const MarchParams& P, int n_prop, int n_fine, bool packets, unsigned long long* stats,
-                      int blocks, hipStream_t st) {
+                      int blocks_per_cu, int64_t n, hipStream_t st) {
   const uint32_t* fr = BF ? f->frag_bf16_dev : f->frag_f32_dev;
+  const TabT* tab = reinterpret_cast<const TabT*>(f->table_dev);
+  const PTabT* ptab = reinterpret_cast<const PTabT*>(p->table_dev);
   if (packets && n_prop == kPkBins && n_fine <= kPkBins) {
-    hipLaunchKernelGGL((k_march_prop_pk<NL, SH, CL, TabT, BF, PTabT>), dim3(blocks), dim3(256), 0, st, q, count, work,
-                       f->view, reinterpret_cast<const TabT*>(f->table_dev), fr, p->view,
-                       reinterpret_cast<const PTabT*>(p->table_dev), P, n_fine, stats);
-    MR_HIP(hipGetLastError());
-    return MR_OK;
+    auto* k = k_march_prop_pk<NL, SH, CL, TabT, BF, PTabT>;
+    const int blocks = persistent_blocks(reinterpret_cast<const void*>(k), 256, blocks_per_cu, (n + 63) / 64);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, q, count, work, f->view, tab, fr, p->view, ptab, P, n_fine,
+                       stats);
+  } else {
+    auto* k = k_march_prop<NL, SH, CL, TabT, BF, PTabT>;
+    const int blocks = persistent_blocks(reinterpret_cast<const void*>(k), 256, blocks_per_cu, (n + 3) / 4);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, q, count, work, f->view, tab, fr, p->view, ptab, P, n_prop,
+                       n_fine, stats);
   }
-  hipLaunchKernelGGL((k_march_prop<NL, SH, CL, TabT, BF, PTabT>), dim3(blocks), dim3(256), 0, st, q, count, work,
-                     f->view, reinterpret_cast<const TabT*>(f->table_dev), fr, p->view,
-                     reinterpret_cast<const PTabT*>(p->table_dev), P, n_prop, n_fine, stats);
   MR_HIP(hipGetLastError());
   return MR_OK;
 }
@@ -668,13 +671,13 @@ namespace mr {
 
 mr_status dispatch_march_proposal(const mr_field* f, const mr_field* prop, RayQueue q, const int* count, int* work,
                                   const MarchParams& P, int n_prop, int n_fine, bool packets,
-                                  unsigned long long* stats, int blocks, hipStream_t st) {
+                                  unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st) {
   const auto& v = f->view;
   const bool h = v.table_dtype == MR_F16, bf = v.mlp_dtype == MR_BF16;
   const bool ph = prop->view.table_dtype == MR_F16;
 #define PR(NL, SH, CL, TT, BFV)                                                                                      \
-  return ph ? launch_prop<NL, SH, CL, TT, BFV, __half>(f, prop, q, count, work, P, n_prop, n_fine, packets, stats, blocks, st) \
-            : launch_prop<NL, SH, CL, TT, BFV, float>(f, prop, q, count, work, P, n_prop, n_fine, packets, stats, blocks, st);
+  return ph ? launch_prop<NL, SH, CL, TT, BFV, __half>(f, prop, q, count, work, P, n_prop, n_fine, packets, stats, blocks_per_cu, n, st) \
+            : launch_prop<NL, SH, CL, TT, BFV, float>(f, prop, q, count, work, P, n_prop, n_fine, packets, stats, blocks_per_cu, n, st);
 #define M(NL, SH, CL)                                                        \
   if (v.n_levels == NL && v.sh == SH && v.c_layers == CL) {                   \
     if (bf) {                                                                 \

@@ -13,6 +13,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "mr_device.h"
@@ -112,6 +114,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(RayQueue q, const int* __
                                                        int tile, BvhView B, float t_far, float span,
                                                        int32_t* __restrict__ hit_ids, int hit_stride) {
   __shared__ int stack[kStack * kTraceBlock];
+  __shared__ float tstack[kStack * kTraceBlock];
   __shared__ int s_base;
   const int cnt = *count;
   while (true) {
@@ -125,7 +128,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(RayQueue q, const int* __
       const int seg = q.depth[i] & 0xFFFF;
       const RayPre r = ray_pre(v3(q.ox[i], q.oy[i], q.oz[i]), v3(q.dx[i], q.dy[i], q.dz[i]));
       float t = INFINITY;
-      const int p = B.n_prims ? bvh_trace<false>(B, r, seg == 0 ? t_far : span, t, stack + threadIdx.x, kTraceBlock) : -1;
+      const int p = B.n_prims ? bvh_trace<false>(B, r, seg == 0 ? t_far : span, t, stack + threadIdx.x,
+                                                            tstack + threadIdx.x, kTraceBlock) : -1;
       q.hit_t[i] = p >= 0 ? t : INFINITY;
       q.hit_p[i] = p;
       if (hit_ids && seg < hit_stride)
@@ -207,7 +211,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade(RayQueue qi, const int* _
             const RayPre sr = ray_pre(so, sd);
             float th;
             ++n_shadow;
-            if (bvh_trace<true>(M.bvh, sr, sdist, th, stack + threadIdx.x, kTraceBlock) >= 0) continue;
+            if (bvh_trace<true>(M.bvh, sr, sdist, th, stack + threadIdx.x, nullptr, kTraceBlock) >= 0) continue;
             const float g = cosl / d2 * (1.0f / 3.14159265358979323846f);
             lr += tr * mat.albedo[0] * S.lights[li][3] * g;
             lg += tg * mat.albedo[1] * S.lights[li][4] * g;
@@ -361,6 +365,22 @@ int device_cus() {
   return cus;
 }
 
+int persistent_blocks(const void* kernel, int threads, int per_cu, int64_t cap) {
+  if (per_cu <= 0) {
+    static std::mutex mu;
+    static std::unordered_map<const void*, int> fit;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = fit.find(kernel);
+    if (it == fit.end()) {
+      int b = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, threads, 0) != hipSuccess || b <= 0) b = 2;
+      it = fit.emplace(kernel, b).first;
+    }
+    per_cu = it->second;
+  }
+  return (int)std::max<int64_t>(kXcds, std::min<int64_t>(cap, (int64_t)device_cus() * per_cu));
+}
+
 mr_status validate_render(const mr_field* field, const mr_mesh* mesh, int64_t n, const float* origins,
                           const float* dirs, int32_t max_bounces, const mr_light* lights, int32_t n_lights,
                           const mr_render_opts* opts, const mr_render_out* out) {
@@ -470,13 +490,12 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
   ro.throughput = out->throughput;
   ro.bounces = out->bounces;
 
-  const int cus = device_cus();
   const int tile = opts->stage_tile > 0 ? opts->stage_tile : 128;
-  const int sbpc = opts->stage_blocks_per_cu > 0 ? opts->stage_blocks_per_cu : 16;
-  const int mbpc = opts->march_blocks_per_cu > 0 ? opts->march_blocks_per_cu : 8;
-  const int trace_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + tile - 1) / tile, (int64_t)cus * sbpc));
-  // at least kXcds blocks so that every die has a home partition served
-  const int march_blocks = (int)std::max<int64_t>(kXcds, std::min<int64_t>((n + 3) / 4, (int64_t)cus * mbpc));
+  const int64_t tiles = (n + tile - 1) / tile;
+  const int trace_blocks =
+      persistent_blocks(reinterpret_cast<const void*>(k_trace), kTraceBlock, opts->stage_blocks_per_cu, tiles);
+  const int shade_blocks =
+      persistent_blocks(reinterpret_cast<const void*>(k_shade), kTraceBlock, opts->stage_blocks_per_cu, tiles);
   const int packet_segments = opts->march_packets == 0 ? 1 : std::max(0, opts->march_packets);
   for (int b = 0; b <= max_bounces; ++b) {
     RayQueue& qi = Q[b & 1];
@@ -491,15 +510,15 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
       StageTimer tm(1, st);
       if (opts->sampler == MR_SAMPLER_PROPOSAL)
         s = dispatch_march_proposal(field, opts->proposal, qi, counts + b, work + kXcds * b, P, opts->n_proposal,
-                                    opts->n_fine, b < packet_segments, stats, march_blocks, st);
+                                    opts->n_fine, b < packet_segments, stats, opts->march_blocks_per_cu, n, st);
       else
-        s = dispatch_march_mfma(field, qi, counts + b, work + kXcds * b, P, b < packet_segments, stats, march_blocks,
-                                st);
+        s = dispatch_march_mfma(field, qi, counts + b, work + kXcds * b, P, b < packet_segments, stats,
+                                opts->march_blocks_per_cu, n, st);
       if (s != MR_OK) return s;
     }
     {
       StageTimer tm(2, st);
-      hipLaunchKernelGGL(k_shade, dim3(trace_blocks), dim3(kTraceBlock), 0, st, qi, counts + b, swork + b, tile, qo,
+      hipLaunchKernelGGL(k_shade, dim3(shade_blocks), dim3(kTraceBlock), 0, st, qi, counts + b, swork + b, tile, qo,
                          counts + b + 1, mv, S, ro, stats);
       MR_HIP(hipGetLastError());
     }
