@@ -70,144 +70,185 @@ __device__ __forceinline__ bool occ_lookup(const FieldView& F, float px, float p
   return (F.occ[c >> 5] >> (c & 31)) & 1u;
 }
 
+// One ray per wave: lane j takes sample kb + j of each 16-sample tile, and
+// transmittance is a 16-lane prefix product carried from tile to tile.
+template <int NL, int SH, int CL, typename TabT, bool BF>
+__device__ __forceinline__ void march_ray(const RayQueue& q, int r, const FieldView& F, const TabT* __restrict__ table,
+                                          const uint32_t* __restrict__ sW, const MarchParams& P, bool use_occ,
+                                          int lane, unsigned long long& nsamp) {
+  using LY = FragLayout<NL, SH, CL, BF>;
+  const int g = lane >> 4, j = lane & 15;
+  const float delta = P.delta;
+  const float ox = q.ox[r], oy = q.oy[r], oz = q.oz[r];
+  const float dx = q.dx[r], dy = q.dy[r], dz = q.dz[r];
+  const float t_a = (q.depth[r] & 0xFFFF) == 0 ? P.t_near : 0.0f;
+  float box0, box1;
+  if (!slab_box(F, ox, oy, oz, dx, dy, dz, box0, box1)) return;
+  const float lo = fmaxf(t_a, box0);
+  const float hi = fminf(fminf(t_a + P.span, q.hit_t[r]), box1);
+  if (!(hi > lo)) return;
+  const int k0 = max(0, (int)floorf((lo - t_a) / delta) - 1);
+  const int k1 = min(P.n_samples, (int)ceilf((hi - t_a) / delta) + 1);
+  float u[4][4];
+  sh_rows<NL, SH, CL, BF>(sW, dx, dy, dz, lane, u);
+  float Tseg = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
+  for (int kb = k0; kb < k1; kb += 16) {
+    const int k = kb + j;
+    const float a = fmaxf(t_a + (float)k * delta, lo);
+    const float b = fminf(t_a + (float)(k + 1) * delta, hi);
+    bool valid = k < k1 && b > a;
+    const float tm = 0.5f * (a + b), D = b - a;
+    const float px = ox + tm * dx, py = oy + tm * dy, pz = oz + tm * dz;
+    if (valid && use_occ) valid = occ_lookup(F, px, py, pz);
+    if (__ballot(valid) == 0ull) continue;
+    float fe[LY::NF];
+    encode_group<NL, TabT>(F, table, px, py, pz, g, fe);
+    float sigma, rgb[3];
+    f4v raw;
+    mlp_tile<NL, SH, CL, BF>(sW, fe, u, F.density_offset, lane, sigma, rgb, raw);
+    const float alpha = valid ? -expm1f(-sigma * D) : 0.0f;
+    const float incl = scan16_mul(1.0f - alpha, j);
+    float excl = __shfl_up(incl, 1, 16);
+    if (j == 0) excl = 1.0f;
+    const float w = Tseg * excl * alpha;
+    acc0 += w * rgb[0];
+    acc1 += w * rgb[1];
+    acc2 += w * rgb[2];
+    Tseg *= __shfl(incl, 15, 16);
+    if (g == 0 && valid) ++nsamp;
+  }
+  acc0 = sum16(acc0);
+  acc1 = sum16(acc1);
+  acc2 = sum16(acc2);
+  if (lane == 0) {
+    const float tr = q.tr[r], tg = q.tg[r], tb = q.tb[r];
+    q.lr[r] += tr * acc0;
+    q.lg[r] += tg * acc1;
+    q.lb[r] += tb * acc2;
+    q.tr[r] = tr * Tseg;
+    q.tg[r] = tg * Tseg;
+    q.tb[r] = tb * Tseg;
+  }
+}
+
+// Column j's ray of a 16-ray packet (every lane group holds the same 16).
+struct PacketRay {
+  float ox, oy, oz, dx, dy, dz;
+  int r;
+  bool live;   // a ray in the queue
+};
+
+__device__ __forceinline__ PacketRay packet_ray(const RayQueue& q, int r, int cnt) {
+  PacketRay R;
+  R.r = r;
+  R.live = r < cnt;
+  R.ox = R.oy = R.oz = R.dx = R.dy = 0.0f;
+  R.dz = 1.0f;
+  if (R.live) {
+    R.ox = q.ox[r]; R.oy = q.oy[r]; R.oz = q.oz[r];
+    R.dx = q.dx[r]; R.dy = q.dy[r]; R.dz = q.dz[r];
+  }
+  return R;
+}
+
+// A packet of 16 rays stepped through the same sample index together:
+// column j of every tile is ray j at sample k, composited by a running
+// product per column.
+template <int NL, int SH, int CL, typename TabT, bool BF>
+__device__ __forceinline__ void march_packet(const RayQueue& q, const PacketRay& R, const FieldView& F,
+                                             const TabT* __restrict__ table, const uint32_t* __restrict__ sW,
+                                             const MarchParams& P, bool use_occ, int lane,
+                                             unsigned long long& nsamp) {
+  using LY = FragLayout<NL, SH, CL, BF>;
+  const int g = lane >> 4;
+  const float delta = P.delta;
+  const float ox = R.ox, oy = R.oy, oz = R.oz, dx = R.dx, dy = R.dy, dz = R.dz;
+  const int r = R.r;
+  bool live = R.live;
+  float t_a = 0.0f, lo = 0.0f, hi = 0.0f;
+  int k0 = P.n_samples, k1 = 0;
+  if (live) {
+    t_a = (q.depth[r] & 0xFFFF) == 0 ? P.t_near : 0.0f;
+    float box0, box1;
+    live = slab_box(F, ox, oy, oz, dx, dy, dz, box0, box1);
+    if (live) {
+      lo = fmaxf(t_a, box0);
+      hi = fminf(fminf(t_a + P.span, q.hit_t[r]), box1);
+      live = hi > lo;
+    }
+    if (live) {
+      k0 = max(0, (int)floorf((lo - t_a) / delta) - 1);
+      k1 = min(P.n_samples, (int)ceilf((hi - t_a) / delta) + 1);
+    }
+  }
+  int kmin = k0, kmax = k1;
+#pragma unroll
+  for (int off = 1; off < 16; off <<= 1) {
+    kmin = min(kmin, __shfl_xor(kmin, off, 16));
+    kmax = max(kmax, __shfl_xor(kmax, off, 16));
+  }
+  if (kmin >= kmax) return;
+  float u[4][4];
+  sh_rows<NL, SH, CL, BF>(sW, dx, dy, dz, lane, u);
+  float T = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
+  for (int k = kmin; k < kmax; ++k) {
+    const float a = fmaxf(t_a + (float)k * delta, lo);
+    const float b = fminf(t_a + (float)(k + 1) * delta, hi);
+    bool valid = live && k >= k0 && k < k1 && b > a;
+    const float tm = 0.5f * (a + b), D = b - a;
+    const float px = ox + tm * dx, py = oy + tm * dy, pz = oz + tm * dz;
+    if (valid && use_occ) valid = occ_lookup(F, px, py, pz);
+    if (__ballot(valid) == 0ull) continue;
+    float fe[LY::NF];
+    encode_group<NL, TabT>(F, table, px, py, pz, g, fe);
+    float sigma, rgb[3];
+    f4v raw;
+    mlp_tile<NL, SH, CL, BF>(sW, fe, u, F.density_offset, lane, sigma, rgb, raw);
+    const float alpha = valid ? -expm1f(-sigma * D) : 0.0f;
+    const float w = T * alpha;
+    acc0 += w * rgb[0];
+    acc1 += w * rgb[1];
+    acc2 += w * rgb[2];
+    T *= 1.0f - alpha;
+    if (g == 0 && valid) ++nsamp;
+  }
+  if (live && g == 0) {
+    const float tr = q.tr[r], tg = q.tg[r], tb = q.tb[r];
+    q.lr[r] += tr * acc0;
+    q.lg[r] += tg * acc1;
+    q.lb[r] += tb * acc2;
+    q.tr[r] = tr * T;
+    q.tg[r] = tg * T;
+    q.tb[r] = tb * T;
+  }
+}
+
+// PK: 16-ray packets (march_packet), else one ray per wave (march_ray).
 template <int NL, int SH, int CL, typename TabT, bool BF, bool PK>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_march_mfma(RayQueue q, const int* __restrict__ count, int* __restrict__ work,
-                                                    FieldView F, const TabT* __restrict__ table,
-                                                    const uint32_t* __restrict__ frags, MarchParams P,
-                                                    unsigned long long* __restrict__ stats) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_march_mfma(
+    RayQueue q, const int* __restrict__ count, int* __restrict__ work, FieldView F, const TabT* __restrict__ table,
+    const uint32_t* __restrict__ frags, MarchParams P, unsigned long long* __restrict__ stats) {
   using LY = FragLayout<NL, SH, CL, BF>;
   __shared__ __align__(16) uint32_t sW[LY::TOTAL];
   for (int i = threadIdx.x; i < LY::TOTAL; i += blockDim.x) sW[i] = frags[i];
   __syncthreads();
-  const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+  const int lane = threadIdx.x & 63, j = lane & 15;
   const int cnt = *count;
   const bool use_occ = P.use_occupancy && F.occ;
-  const float delta = P.delta;
   unsigned long long nsamp = 0;
-  if constexpr (PK) {
-    // A wave marches a packet of 16 consecutive queue rays in step: column j of
-    // every tile is ray j of the packet at the same sample index k.
-    WorkQueue wq(work, cnt, P.chunk, 16);
-    for (int base = wq.next(lane); base >= 0; base = wq.next(lane)) {
-      const int r = wq.map(base + j);
-      bool live = r < cnt;
-      float ox = 0.0f, oy = 0.0f, oz = 0.0f, dx = 0.0f, dy = 0.0f, dz = 1.0f;
-      float t_a = 0.0f, lo = 0.0f, hi = 0.0f;
-      int k0 = P.n_samples, k1 = 0;
-      if (live) {
-        ox = q.ox[r]; oy = q.oy[r]; oz = q.oz[r];
-        dx = q.dx[r]; dy = q.dy[r]; dz = q.dz[r];
-        t_a = (q.depth[r] & 0xFFFF) == 0 ? P.t_near : 0.0f;
-        float box0, box1;
-        live = slab_box(F, ox, oy, oz, dx, dy, dz, box0, box1);
-        if (live) {
-          lo = fmaxf(t_a, box0);
-          hi = fminf(fminf(t_a + P.span, q.hit_t[r]), box1);
-          live = hi > lo;
-        }
-        if (live) {
-          k0 = max(0, (int)floorf((lo - t_a) / delta) - 1);
-          k1 = min(P.n_samples, (int)ceilf((hi - t_a) / delta) + 1);
-        }
-      }
-      int kmin = k0, kmax = k1;
-  #pragma unroll
-      for (int off = 1; off < 16; off <<= 1) {
-        kmin = min(kmin, __shfl_xor(kmin, off, 16));
-        kmax = max(kmax, __shfl_xor(kmax, off, 16));
-      }
-      if (kmin >= kmax) continue;
-      float u[4][4];
-      sh_rows<NL, SH, CL, BF>(sW, dx, dy, dz, lane, u);
-      float T = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
-      for (int k = kmin; k < kmax; ++k) {
-        const float a = fmaxf(t_a + (float)k * delta, lo);
-        const float b = fminf(t_a + (float)(k + 1) * delta, hi);
-        bool valid = live && k >= k0 && k < k1 && b > a;
-        const float tm = 0.5f * (a + b), D = b - a;
-        const float px = ox + tm * dx, py = oy + tm * dy, pz = oz + tm * dz;
-        if (valid && use_occ) valid = occ_lookup(F, px, py, pz);
-        if (__ballot(valid) == 0ull) continue;
-        float fe[LY::NF];
-        encode_group<NL, TabT>(F, table, px, py, pz, g, fe);
-        float sigma, rgb[3];
-        f4v raw;
-        mlp_tile<NL, SH, CL, BF>(sW, fe, u, F.density_offset, lane, sigma, rgb, raw);
-        const float alpha = valid ? -expm1f(-sigma * D) : 0.0f;
-        const float w = T * alpha;
-        acc0 += w * rgb[0];
-        acc1 += w * rgb[1];
-        acc2 += w * rgb[2];
-        T *= 1.0f - alpha;
-        if (g == 0 && valid) ++nsamp;
-      }
-      if (live && g == 0) {
-        const float tr = q.tr[r], tg = q.tg[r], tb = q.tb[r];
-        q.lr[r] += tr * acc0;
-        q.lg[r] += tg * acc1;
-        q.lb[r] += tb * acc2;
-        q.tr[r] = tr * T;
-        q.tg[r] = tg * T;
-        q.tb[r] = tb * T;
-      }
-    }
-  } else {
+  if constexpr (!PK) {
     WorkQueue wq(work, cnt, P.chunk, P.batch);
     for (int base = wq.next(lane); base >= 0; base = wq.next(lane))
-    for (int bi = 0; bi < wq.batch; ++bi) {
-      const int r = wq.map(base + bi);
-      if (r >= cnt) break;
-      const float ox = q.ox[r], oy = q.oy[r], oz = q.oz[r];
-      const float dx = q.dx[r], dy = q.dy[r], dz = q.dz[r];
-      const int seg = q.depth[r] & 0xFFFF;
-      const float t_a = seg == 0 ? P.t_near : 0.0f;
-      float box0, box1;
-      if (!slab_box(F, ox, oy, oz, dx, dy, dz, box0, box1)) continue;
-      const float lo = fmaxf(t_a, box0);
-      const float hi = fminf(fminf(t_a + P.span, q.hit_t[r]), box1);
-      if (!(hi > lo)) continue;
-      const int k0 = max(0, (int)floorf((lo - t_a) / delta) - 1);
-      const int k1 = min(P.n_samples, (int)ceilf((hi - t_a) / delta) + 1);
-      float u[4][4];
-      sh_rows<NL, SH, CL, BF>(sW, dx, dy, dz, lane, u);
-      float Tseg = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
-      for (int kb = k0; kb < k1; kb += 16) {
-        const int k = kb + j;
-        const float a = fmaxf(t_a + (float)k * delta, lo);
-        const float b = fminf(t_a + (float)(k + 1) * delta, hi);
-        bool valid = k < k1 && b > a;
-        const float tm = 0.5f * (a + b), D = b - a;
-        const float px = ox + tm * dx, py = oy + tm * dy, pz = oz + tm * dz;
-        if (valid && use_occ) valid = occ_lookup(F, px, py, pz);
-        if (__ballot(valid) == 0ull) continue;
-        float fe[LY::NF];
-        encode_group<NL, TabT>(F, table, px, py, pz, g, fe);
-        float sigma, rgb[3];
-        f4v raw;
-        mlp_tile<NL, SH, CL, BF>(sW, fe, u, F.density_offset, lane, sigma, rgb, raw);
-        const float alpha = valid ? -expm1f(-sigma * D) : 0.0f;
-        const float incl = scan16_mul(1.0f - alpha, j);
-        float excl = __shfl_up(incl, 1, 16);
-        if (j == 0) excl = 1.0f;
-        const float w = Tseg * excl * alpha;
-        acc0 += w * rgb[0];
-        acc1 += w * rgb[1];
-        acc2 += w * rgb[2];
-        Tseg *= __shfl(incl, 15, 16);
-        if (g == 0 && valid) ++nsamp;
+      for (int bi = 0; bi < wq.batch; ++bi) {
+        const int r = wq.map(base + bi);
+        if (r >= cnt) break;
+        march_ray<NL, SH, CL, TabT, BF>(q, r, F, table, sW, P, use_occ, lane, nsamp);
       }
-      acc0 = sum16(acc0);
-      acc1 = sum16(acc1);
-      acc2 = sum16(acc2);
-      if (lane == 0) {
-        const float tr = q.tr[r], tg = q.tg[r], tb = q.tb[r];
-        q.lr[r] += tr * acc0;
-        q.lg[r] += tg * acc1;
-        q.lb[r] += tb * acc2;
-        q.tr[r] = tr * Tseg;
-        q.tg[r] = tg * Tseg;
-        q.tb[r] = tb * Tseg;
-      }
+  } else {
+    WorkQueue wq(work, cnt, P.chunk, 16);
+    for (int base = wq.next(lane); base >= 0; base = wq.next(lane)) {
+      const PacketRay R = packet_ray(q, wq.map(base + j), cnt);
+      march_packet<NL, SH, CL, TabT, BF>(q, R, F, table, sW, P, use_occ, lane, nsamp);
     }
   }
   if (stats) {
@@ -262,22 +303,25 @@ __global__ __launch_bounds__(256) void k_query_mfma(FieldView F, const TabT* __r
   }
 }
 
+template <int NL, int SH, int CL, typename TabT, bool BF, bool PK>
+mr_status launch_march_mode(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
+                            unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st) {
+  const uint32_t* fr = BF ? f->frag_bf16_dev : f->frag_f32_dev;
+  const TabT* tab = reinterpret_cast<const TabT*>(f->table_dev);
+  auto* k = k_march_mfma<NL, SH, CL, TabT, BF, PK>;
+  const int64_t cap = PK ? (n + 63) / 64 : (n + 3) / 4;
+  const int blocks = persistent_blocks(reinterpret_cast<const void*>(k), 256, blocks_per_cu, cap);
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, q, count, work, f->view, tab, fr, P, stats);
+  MR_HIP(hipGetLastError());
+  return MR_OK;
+}
+
 template <int NL, int SH, int CL, typename TabT, bool BF>
 mr_status launch_march_mfma(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
                             bool packets, unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st) {
-  const uint32_t* fr = BF ? f->frag_bf16_dev : f->frag_f32_dev;
-  const TabT* tab = reinterpret_cast<const TabT*>(f->table_dev);
-  if (packets) {
-    auto* k = k_march_mfma<NL, SH, CL, TabT, BF, true>;
-    const int blocks = persistent_blocks(reinterpret_cast<const void*>(k), 256, blocks_per_cu, (n + 63) / 64);
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, q, count, work, f->view, tab, fr, P, stats);
-  } else {
-    auto* k = k_march_mfma<NL, SH, CL, TabT, BF, false>;
-    const int blocks = persistent_blocks(reinterpret_cast<const void*>(k), 256, blocks_per_cu, (n + 3) / 4);
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, q, count, work, f->view, tab, fr, P, stats);
-  }
-  MR_HIP(hipGetLastError());
-  return MR_OK;
+  if (packets)
+    return launch_march_mode<NL, SH, CL, TabT, BF, true>(f, q, count, work, P, stats, blocks_per_cu, n, st);
+  return launch_march_mode<NL, SH, CL, TabT, BF, false>(f, q, count, work, P, stats, blocks_per_cu, n, st);
 }
 
 template <int NL, int SH, int CL, typename TabT, bool BF>
