@@ -155,8 +155,10 @@ __device__ __forceinline__ void finalize(const RenderOut& out, int rid, float tr
 __global__ __launch_bounds__(kTraceBlock) void k_shade(RayQueue qi, const int* __restrict__ count_in,
                                                        int* __restrict__ work, int tile, RayQueue qo,
                                                        int* __restrict__ count_out, MeshView M, ShadeParams S,
-                                                       RenderOut out, unsigned long long* __restrict__ stats) {
+                                                       RenderOut out, float span, int32_t* __restrict__ hit_ids,
+                                                       int hit_stride, unsigned long long* __restrict__ stats) {
   __shared__ int stack[kStack * kTraceBlock];
+  __shared__ float tstack[kStack * kTraceBlock];
   __shared__ int s_base;
   const int cnt = *count_in;
   const int lane = threadIdx.x & 63;
@@ -297,6 +299,15 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade(RayQueue qi, const int* _
       qo.lr[slot] = lr; qo.lg[slot] = lg; qo.lb[slot] = lb;
       qo.rid[slot] = rid;
       qo.depth[slot] = ndepth;
+      // closest hit of the new segment, whose range starts at the spawn point
+      const RayPre nr = ray_pre(v3(nox, noy, noz), v3(ndx, ndy, ndz));
+      float th = INFINITY;
+      const int hp = bvh_trace<false>(M.bvh, nr, span, th, stack + threadIdx.x, tstack + threadIdx.x, kTraceBlock);
+      qo.hit_t[slot] = hp >= 0 ? th : INFINITY;
+      qo.hit_p[slot] = hp;
+      const int nseg = ndepth & 0xFFFF;
+      if (hit_ids && nseg < hit_stride)
+        hit_ids[(int64_t)rid * hit_stride + nseg] = hp >= 0 ? __float_as_int(M.bvh.tris[3 * hp].w) : -1;
     }
   }
   }
@@ -500,7 +511,8 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
   for (int b = 0; b <= max_bounces; ++b) {
     RayQueue& qi = Q[b & 1];
     RayQueue& qo = Q[(b + 1) & 1];
-    {
+    if (b == 0) {
+      // later segments are traced by the shade pass that spawns them
       StageTimer tm(0, st);
       hipLaunchKernelGGL(k_trace, dim3(trace_blocks), dim3(kTraceBlock), 0, st, qi, counts + b, twork + b, tile, mv.bvh,
                          opts->t_far, P.span, out->hit_ids, out->hit_ids ? out->hit_stride : 0);
@@ -519,7 +531,7 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
     {
       StageTimer tm(2, st);
       hipLaunchKernelGGL(k_shade, dim3(shade_blocks), dim3(kTraceBlock), 0, st, qi, counts + b, swork + b, tile, qo,
-                         counts + b + 1, mv, S, ro, stats);
+                         counts + b + 1, mv, S, ro, P.span, out->hit_ids, out->hit_ids ? out->hit_stride : 0, stats);
       MR_HIP(hipGetLastError());
     }
   }
