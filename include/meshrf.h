@@ -322,6 +322,18 @@ mr_status mr_proposal_train_step(mr_field* proposal, int64_t n, const float* ori
 mr_status mr_profile_enable(int32_t on);
 mr_status mr_profile_read(double* ms /*[4]*/, int64_t* launches /*[4]*/);
 
+/* Random-gather ceiling of the memory level that holds a field's hash table
+ * (a measurement helper, not part of the method).  Loads about n_loads (>= 8)
+ * table entries of f (8 B FP32 / 4 B FP16) at pseudo-random positions in a
+ * power-of-two prefix of its [L][T] entries, eight independent loads per lane
+ * and round, from a grid of 8 blocks of 256 lanes per compute unit; returns
+ * the kernel time in *ms_out (HIP events on `stream`) and the loads actually
+ * issued in *loads_out.  sink: one device uint32 the kernel may write.
+ * Synchronous (waits for the kernel); not for graph capture.  Fails with
+ * MR_ERR_UNSUPPORTED unless the field has 2 features per level. */
+mr_status mr_probe_gather(const mr_field* f, int64_t n_loads, uint32_t seed, uint32_t* sink, float* ms_out,
+                          int64_t* loads_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,13 +23,12 @@ MR_MIRROR, MR_GLASS, MR_DIFFUSE = 0, 1, 2
 MR_SAMPLER_UNIFORM, MR_SAMPLER_PROPOSAL = 0, 1
 
 EXPORTED = [
-    "mr_last_error", "mr_version", "mr_field_create", "mr_field_destroy", "mr_field_query",
-    "mr_field_build_occupancy", "mr_field_params", "mr_mesh_build_bvh", "mr_mesh_refit",
-    "mr_mesh_destroy", "mr_mesh_info", "mr_mesh_closest_hit", "mr_render_workspace_size",
-    "mr_render", "mr_rays_from_cameras", "mr_profile_enable", "mr_profile_read",
-    "mr_proposal_targets", "mr_proposal_grad", "mr_proposal_train_step",
-    "mr_render_graph_create", "mr_graph_launch", "mr_graph_destroy", "mr_autotune_render",
-    "mr_camera_bounce_limits",
+    "mr_autotune_render", "mr_camera_bounce_limits", "mr_field_build_occupancy", "mr_field_create",
+    "mr_field_destroy", "mr_field_params", "mr_field_query", "mr_graph_destroy", "mr_graph_launch",
+    "mr_last_error", "mr_mesh_build_bvh", "mr_mesh_closest_hit", "mr_mesh_destroy", "mr_mesh_info",
+    "mr_mesh_refit", "mr_probe_gather", "mr_profile_enable", "mr_profile_read", "mr_proposal_grad",
+    "mr_proposal_targets", "mr_proposal_train_step", "mr_rays_from_cameras", "mr_render",
+    "mr_render_graph_create", "mr_render_workspace_size", "mr_version",
 ]
 
 
@@ -362,6 +361,15 @@ def mr_profile_read():
     n = (C.c_int64 * 4)()
     _check(lib().mr_profile_read(ms, n))
     return list(ms), list(n)
+
+
+def mr_probe_gather(field, n_loads, seed, sink, stream=None):
+    """Random-gather ceiling of the field's table: returns (ms, loads issued)."""
+    ms = C.c_float()
+    loads = C.c_int64()
+    _check(lib().mr_probe_gather(field, C.c_int64(n_loads), C.c_uint32(seed), _ptr(sink), C.byref(ms),
+                                 C.byref(loads), _stream(stream)))
+    return ms.value, loads.value
 
 
 def mr_proposal_targets(fine, n, origins, dirs, t_near, t_far, n_samples, n_bins, lohi, targets, stream=None):

@@ -2,6 +2,9 @@
 matrix cores with FP32 accumulation, compositing, intersection and Fresnel
 in FP32.  Hit ids and bounce counts stay bit-exact against the FP64 oracle on
 non-tie rays; the radiance error is bounded (and reported by bench.py)."""
+import os
+import sys
+
 import numpy as np
 import pytest
 
@@ -9,6 +12,7 @@ from oracle import oracle as orc
 from paper_2309_04581_amd import scenegen as sg
 
 torch = pytest.importorskip("torch")
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 pytestmark = pytest.mark.gpu
 
 from test_gpu_parity import (assert_close_rel, compare_render, dev, gpu_render, host,  # noqa: E402
@@ -22,18 +26,10 @@ def _gpu():
     orc.build(force=False)
 
 
-def bf16_round(a):
-    """Round-to-nearest-even to bfloat16, returned as float32."""
-    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
-    return r.astype(np.uint32).view(np.float32)
-
-
 def rounded_field(f):
-    g = sg.Field(**{k: getattr(f, k) for k in f.__dataclass_fields__})
-    g.table = f.table.astype(np.float16).astype(np.float32)
-    g.mlp = bf16_round(f.mlp)
-    return g
+    """Parameters as the FP16-table / BF16-MLP engine holds them (bench.py)."""
+    import bench
+    return bench._rounded_field(sg, f)
 
 
 def test_fp16_table_is_round_to_nearest_with_subnormals():

@@ -97,3 +97,16 @@ def test_autotuner_picks_a_candidate_and_results_do_not_depend_on_launch_shape()
     assert best in cands and ms > 0
     for a, b in zip(_outputs(R), ref):
         np.testing.assert_array_equal(a, b)
+
+
+def test_gather_probe_runs_and_validates():
+    """The random-gather ceiling probe: the loads issued cover the request
+    (whole rounds of 8 per lane), time is positive, fewer than 8 loads is
+    refused before any launch."""
+    M = mr()
+    F = M.Field(sg.tiny_field())
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ms, loads = M.mr_probe_gather(F.handle, 1 << 22, 3, sink)
+    assert ms > 0 and (1 << 21) <= loads <= (1 << 23)
+    with pytest.raises(M.MrError):
+        M.mr_probe_gather(F.handle, 4, 3, sink)
