@@ -404,6 +404,24 @@ void orc_rays_from_camera(const float* cam, double* o, double* d) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* Placement: a world point p maps to the field's frame as R^T (p - c) and a */
+/* direction d as R^T d.  The map is rigid, so a ray keeps its parameter t.  */
+/* ------------------------------------------------------------------------- */
+static void world_to_field(const orc_field* f, const double p[3], const double d[3], double pf[3],
+                           double df[3]) {
+  if (!f->has_pose) {
+    for (int k = 0; k < 3; ++k) { pf[k] = p[k]; df[k] = d[k]; }
+    return;
+  }
+  const double* P = f->pose;   /* R[i][k] = P[4 i + k], c[i] = P[4 i + 3] */
+  const double q[3] = {p[0] - P[3], p[1] - P[7], p[2] - P[11]};
+  for (int k = 0; k < 3; ++k) {
+    pf[k] = P[k] * q[0] + P[4 + k] * q[1] + P[8 + k] * q[2];
+    df[k] = P[k] * d[0] + P[4 + k] * d[1] + P[8 + k] * d[2];
+  }
+}
+
+/* ------------------------------------------------------------------------- */
 /* Marching one ray segment (Eq. 10-11, and Eq. 8-9 for the quadrature).     */
 /* ------------------------------------------------------------------------- */
 static int slab(const orc_field* f, const double o[3], const double d[3], double* t0,
@@ -497,10 +515,13 @@ void orc_proposal_weights(const orc_field* p, const double o[3], const double d[
  * max(w_{j-1}, w_j, w_{j+1}), plus their mean (a half-and-half mixture with a
  * uniform density) plus 1e-3/n_prop; the n_fine + 1 edges are the inverse CDF
  * of that piecewise-constant density at u = k/n_fine. */
-static int64_t march(const orc_field* f, const orc_opts* opt, const double o[3],
-                     const double d[3], double t_a, double t_hit, double T[3], double L[3],
+static int64_t march(const orc_field* f, const orc_opts* opt, const double o_world[3],
+                     const double d_world[3], double t_a, double t_hit, double T[3], double L[3],
                      int* tie) {
   if (!f) return 0;
+  /* the segment in the field's frame (the proposal field shares that frame) */
+  double o[3], d[3];
+  world_to_field(f, o_world, d_world, o, d);
   double span = opt->t_far - opt->t_near;
   double box0, box1;
   if (!slab(f, o, d, &box0, &box1)) return 0;
@@ -769,10 +790,11 @@ static void* field_worker(void* arg) {
   fjob_t* J = (fjob_t*)arg;
   const orc_field* f = J->f;
   for (int64_t i = J->begin; i < J->end; ++i) {
-    double p[3], d[3] = {0, 0, 1}, xhat[3], rgb[3], raw[MAXW];
-    for (int k = 0; k < 3; ++k) p[k] = J->x[3 * i + k];
+    double pw[3], dw[3] = {0, 0, 1}, p[3], d[3], xhat[3], rgb[3], raw[MAXW];
+    for (int k = 0; k < 3; ++k) pw[k] = J->x[3 * i + k];
     if (J->d)
-      for (int k = 0; k < 3; ++k) d[k] = J->d[3 * i + k];
+      for (int k = 0; k < 3; ++k) dw[k] = J->d[3 * i + k];
+    world_to_field(f, pw, dw, p, d);
     orc_field_eval(f, p, d, &J->sigma[i], J->rgb ? rgb : NULL, raw);
     if (J->rgb)
       for (int c = 0; c < 3; ++c) J->rgb[3 * i + c] = rgb[c];

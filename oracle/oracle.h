@@ -27,6 +27,11 @@ typedef struct {
   const float* mlp;          /* flat weights, forward order, [out][in]       */
   double density_offset;
   double aabb_min[3], aabb_max[3];
+  /* placement of the field in the world (a moving NeRF object): a world point
+   * p is looked up at R^T (p - c), a direction d at R^T d.  pose = [R | c]
+   * row-major 3x4, R a rotation.  has_pose = 0: the field's frame is the world. */
+  int32_t has_pose;
+  double pose[12];
 } orc_field;
 
 typedef struct {

@@ -34,7 +34,8 @@ class _Field(C.Structure):
                 ("d_in", C.c_int32), ("d_hidden", C.c_int32), ("d_out", C.c_int32),
                 ("c_in", C.c_int32), ("c_hidden", C.c_int32), ("c_layers", C.c_int32),
                 ("sh", C.c_int32), ("mlp", C.c_void_p), ("density_offset", C.c_double),
-                ("aabb_min", C.c_double * 3), ("aabb_max", C.c_double * 3)]
+                ("aabb_min", C.c_double * 3), ("aabb_max", C.c_double * 3),
+                ("has_pose", C.c_int32), ("pose", C.c_double * 12)]
 
 
 class _Mesh(C.Structure):
@@ -100,6 +101,10 @@ class OField:
         s.density_offset = float(f.density_offset)
         s.aabb_min = (C.c_double * 3)(*f.aabb_min)
         s.aabb_max = (C.c_double * 3)(*f.aabb_max)
+        pose = getattr(f, "pose", None)
+        s.has_pose = int(pose is not None)
+        if pose is not None:
+            s.pose = (C.c_double * 12)(*np.asarray(pose, dtype=np.float64).reshape(12))
         self.s = s
 
     @property

@@ -67,6 +67,7 @@ class Field:
     density_offset: float = 1.0
     aabb_min: tuple = (-1.0, -1.0, -1.0)
     aabb_max: tuple = (1.0, 1.0, 1.0)
+    pose: object = None              # optional [R | c] 3x4 (field frame -> world), R a rotation
 
     @property
     def table_size(self) -> int:
@@ -477,6 +478,19 @@ def cloth_scene(frame=0, width=800, height=800) -> Scene:
     return Scene(name="cloth", field=tiny_field(1), mesh=cloth_mesh(frame),
                  lights=no_lights(), cameras=[front_camera(width, height, 8)],
                  t_near=0.05, t_far=4.0, n_samples=256, max_bounces=8)
+
+
+def rotation(axis, angle):
+    """Rotation matrix about a unit axis (Rodrigues), float64."""
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0.0, -a[2], a[1]], [a[2], 0.0, -a[0]], [-a[1], a[0], 0.0]])
+    return np.eye(3) + math.sin(angle) * K + (1.0 - math.cos(angle)) * (K @ K)
+
+
+def pose_matrix(R, c):
+    """[R | c] as a 3x4 float64 array."""
+    return np.concatenate([np.asarray(R, np.float64), np.asarray(c, np.float64).reshape(3, 1)], axis=1)
 
 
 def sample_points(n, seed, lo=-1.0, hi=1.0):
