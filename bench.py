@@ -219,6 +219,31 @@ def precision_report(M, sg):
     return out
 
 
+def moving_field(M, sg, sc, F, G, cams, n, steps):
+    """The mid workload with the field as a moving object: a different rigid
+    placement (turning about y, drifting along x) on every step, set with
+    mr_field_set_pose between renders."""
+    import torch
+    o = torch.empty(n, 3, device="cuda")
+    d = torch.empty(n, 3, device="cuda")
+    R = M.Renderer(n, sc.max_bounces, with_hits=False)
+    opts = M.make_opts(sc, use_occupancy=True)
+    poses = [sg.pose_matrix(sg.rotation((0.0, 1.0, 0.0), 0.05 * k), (0.02 * k, 0.0, 0.0)) for k in range(16)]
+    state = {"k": 0}
+
+    def step():
+        F.set_pose(poses[state["k"] % len(poses)])
+        state["k"] += 1
+        M.mr_rays_from_cameras(cams, o, d, None, n)
+        R.render(F, G, o, d, sc.lights, opts)
+    try:
+        ms = timed(step, steps, 1)
+    finally:
+        F.set_pose(None)
+    return {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms, 3),
+            "motion": "turn 0.05 rad about y and move 0.02 along x per step"}
+
+
 def multicam(M, sg, steps):
     """16 cameras of uneven size and bounce depth in one queue, replayed as a graph."""
     import numpy as np
@@ -437,6 +462,7 @@ def main():
         line["proposal_fp16"] = proposal_variant(M, sg, sc, F, G, cams, n, plain_img, args.steps, 1,
                                                  args.train_steps)
         line["precision_tiny_vs_fp64_oracle"] = precision_report(M, sg)
+        line["moving_field"] = moving_field(M, sg, sc, F, G, cams, n, args.steps)
         line["multicam_16_cameras"] = multicam(M, sg, 2)
         line["cloth_refit"] = cloth(M, sg, args.cloth_frames, args.train_steps)
     if not args.no_cpu_baseline:

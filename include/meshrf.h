@@ -100,10 +100,22 @@ mr_status mr_field_create(const mr_field_desc* desc, const float* host_table,
 mr_status mr_field_destroy(mr_field* f);
 
 /* Evaluate the field at n points (device arrays).
- * x, dirs: (n, 3); sigma: (n); rgb: (n, 3) or NULL; feat: (n, n_levels*feats)
+ * x, dirs: (n, 3) in world coordinates (mapped into the field's frame when it
+ * has a pose); sigma: (n); rgb: (n, 3) or NULL; feat: (n, n_levels*feats)
  * or NULL (interpolated hash features, FP32); raw: (n, density_out) or NULL. */
 mr_status mr_field_query(const mr_field* f, int64_t n, const float* x, const float* dirs,
                          float* sigma, float* rgb, float* feat, float* raw, void* stream);
+
+/* Placement of the field in the world, for a moving NeRF object: the field
+ * is looked up at R^T (p - c) for a world point p and at R^T d for a world
+ * direction d, with host_pose = [R | c] row-major 3x4 (field frame -> world)
+ * and R a rotation (R^T R = I within 1e-5, det R = +1; else
+ * MR_ERR_INVALID_ARG and the pose is unchanged).  NULL removes the pose.  It
+ * applies to renders and queries launched afterwards (a captured graph keeps
+ * the pose it was captured with).  The occupancy grid stays in the field's
+ * frame; a proposal field is evaluated in the frame of the field it samples
+ * for; the proposal training entry points take rays in the field's frame. */
+mr_status mr_field_set_pose(mr_field* f, const float* host_pose);
 
 /* Occupancy bit grid for empty-space skipping (attached to the field).
  * Cell (i, j, k) of a res^3 grid over the field box (x fastest) is occupied

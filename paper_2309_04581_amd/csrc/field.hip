@@ -268,6 +268,33 @@ extern "C" mr_status mr_field_params(mr_field* f, void** table, float** mlp, int
   return MR_OK;
 }
 
+extern "C" mr_status mr_field_set_pose(mr_field* f, const float* host_pose) {
+  if (!f) return fail(MR_ERR_INVALID_ARG, "null field");
+  if (!host_pose) {
+    f->view.has_pose = 0;
+    return MR_OK;
+  }
+  double R[3][3];
+  for (int i = 0; i < 3; ++i) {
+    for (int k = 0; k < 3; ++k) R[i][k] = host_pose[4 * i + k];
+    if (!std::isfinite(host_pose[4 * i + 3])) return fail(MR_ERR_INVALID_ARG, "pose translation not finite");
+  }
+  // R^T R = I within FP32 rounding, det R = +1
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double s = 0.0;
+      for (int i = 0; i < 3; ++i) s += R[i][a] * R[i][b];
+      if (!(std::fabs(s - (a == b ? 1.0 : 0.0)) <= 1e-5)) return fail(MR_ERR_INVALID_ARG, "pose rotation not orthonormal");
+    }
+  const double det = R[0][0] * (R[1][1] * R[2][2] - R[1][2] * R[2][1]) -
+                     R[0][1] * (R[1][0] * R[2][2] - R[1][2] * R[2][0]) +
+                     R[0][2] * (R[1][0] * R[2][1] - R[1][1] * R[2][0]);
+  if (!(det > 0.0)) return fail(MR_ERR_INVALID_ARG, "pose rotation has determinant -1");
+  for (int k = 0; k < 12; ++k) f->view.pose[k] = host_pose[k];
+  f->view.has_pose = 1;
+  return MR_OK;
+}
+
 extern "C" mr_status mr_field_query(const mr_field* f, int64_t n, const float* x, const float* dirs,
                                     float* sigma, float* rgb, float* feat, float* raw, void* stream) {
   if (!f) return fail(MR_ERR_INVALID_ARG, "null field");

@@ -79,8 +79,9 @@ __device__ __forceinline__ void march_ray(const RayQueue& q, int r, const FieldV
   using LY = FragLayout<NL, SH, CL, BF>;
   const int g = lane >> 4, j = lane & 15;
   const float delta = P.delta;
-  const float ox = q.ox[r], oy = q.oy[r], oz = q.oz[r];
-  const float dx = q.dx[r], dy = q.dy[r], dz = q.dz[r];
+  float ox = q.ox[r], oy = q.oy[r], oz = q.oz[r];
+  float dx = q.dx[r], dy = q.dy[r], dz = q.dz[r];
+  to_field_frame(F, ox, oy, oz, dx, dy, dz);
   const float t_a = (q.depth[r] & 0xFFFF) == 0 ? P.t_near : 0.0f;
   float box0, box1;
   if (!slab_box(F, ox, oy, oz, dx, dy, dz, box0, box1)) return;
@@ -138,7 +139,7 @@ struct PacketRay {
   bool live;   // a ray in the queue
 };
 
-__device__ __forceinline__ PacketRay packet_ray(const RayQueue& q, int r, int cnt) {
+__device__ __forceinline__ PacketRay packet_ray(const RayQueue& q, int r, int cnt, const FieldView& F) {
   PacketRay R;
   R.r = r;
   R.live = r < cnt;
@@ -147,6 +148,7 @@ __device__ __forceinline__ PacketRay packet_ray(const RayQueue& q, int r, int cn
   if (R.live) {
     R.ox = q.ox[r]; R.oy = q.oy[r]; R.oz = q.oz[r];
     R.dx = q.dx[r]; R.dy = q.dy[r]; R.dz = q.dz[r];
+    to_field_frame(F, R.ox, R.oy, R.oz, R.dx, R.dy, R.dz);
   }
   return R;
 }
@@ -247,7 +249,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   } else {
     WorkQueue wq(work, cnt, P.chunk, 16);
     for (int base = wq.next(lane); base >= 0; base = wq.next(lane)) {
-      const PacketRay R = packet_ray(q, wq.map(base + j), cnt);
+      const PacketRay R = packet_ray(q, wq.map(base + j), cnt, F);
       march_packet<NL, SH, CL, TabT, BF>(q, R, F, table, sW, P, use_occ, lane, nsamp);
     }
   }
@@ -275,9 +277,10 @@ __global__ __launch_bounds__(256) void k_query_mfma(FieldView F, const TabT* __r
     const int64_t p = t * 16 + j;
     const bool valid = p < n;
     const int64_t pc = valid ? p : n - 1;
-    const float px = x[3 * pc], py = x[3 * pc + 1], pz = x[3 * pc + 2];
+    float px = x[3 * pc], py = x[3 * pc + 1], pz = x[3 * pc + 2];
     float dx = 0.0f, dy = 0.0f, dz = 1.0f;
     if (dirs) { dx = dirs[3 * pc]; dy = dirs[3 * pc + 1]; dz = dirs[3 * pc + 2]; }
+    to_field_frame(F, px, py, pz, dx, dy, dz);
     float u[4][4];
     sh_rows<NL, SH, CL, BF>(sW, dx, dy, dz, lane, u);
     float fe[LY::NF];

@@ -49,6 +49,10 @@ struct FieldView {
   const uint32_t* occ;             // occupancy bits (x fastest) or null
   int occ_res;
   int table_dtype, mlp_dtype;
+  // placement in the world (mr_field_set_pose): a world point p is looked up
+  // at R^T (p - c), a direction d at R^T d; pose = [R | c] row-major 3x4
+  int has_pose;
+  float pose[12];
 };
 
 // ---------------------------------------------------------------------------

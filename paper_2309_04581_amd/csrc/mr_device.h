@@ -68,6 +68,22 @@ __device__ __forceinline__ void to_unit(const FieldView& F, float px, float py, 
   zh = fminf(fmaxf((pz - F.amin[2]) * F.inv_ext[2], 0.0f), 1.0f);
 }
 
+// A world-space point and direction in the field's own frame (rigid, so a
+// ray keeps its parameter t): p -> R^T (p - c), d -> R^T d.
+__device__ __forceinline__ void to_field_frame(const FieldView& F, float& px, float& py, float& pz, float& dx,
+                                               float& dy, float& dz) {
+  if (!F.has_pose) return;
+  const float* P = F.pose;
+  const float qx = px - P[3], qy = py - P[7], qz = pz - P[11];
+  px = P[0] * qx + P[4] * qy + P[8] * qz;
+  py = P[1] * qx + P[5] * qy + P[9] * qz;
+  pz = P[2] * qx + P[6] * qy + P[10] * qz;
+  const float ex = dx, ey = dy, ez = dz;
+  dx = P[0] * ex + P[4] * ey + P[8] * ez;
+  dy = P[1] * ex + P[5] * ey + P[9] * ez;
+  dz = P[2] * ex + P[6] * ey + P[10] * ez;
+}
+
 // Corner indices and trilinear weights of one level.
 __device__ __forceinline__ void level_corners(const FieldView& F, int l, float xh, float yh, float zh,
                                               uint32_t idx[8], float w[8]) {

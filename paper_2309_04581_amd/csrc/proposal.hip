@@ -155,8 +155,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   for (int bi = 0; bi < wq.batch; ++bi) {
     const int r = wq.map(base + bi);
     if (r >= cnt) break;
-    const float ox = q.ox[r], oy = q.oy[r], oz = q.oz[r];
-    const float dx = q.dx[r], dy = q.dy[r], dz = q.dz[r];
+    float ox = q.ox[r], oy = q.oy[r], oz = q.oz[r];
+    float dx = q.dx[r], dy = q.dy[r], dz = q.dz[r];
+    to_field_frame(F, ox, oy, oz, dx, dy, dz);   // the proposal shares the field's frame
     const int seg = q.depth[r] & 0xFFFF;
     const float t_a = seg == 0 ? P.t_near : 0.0f;
     float box0, box1;
@@ -292,6 +293,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     if (live) {
       ox = q.ox[r]; oy = q.oy[r]; oz = q.oz[r];
       dx = q.dx[r]; dy = q.dy[r]; dz = q.dz[r];
+      to_field_frame(F, ox, oy, oz, dx, dy, dz);   // the proposal shares the field's frame
       const float t_a = (q.depth[r] & 0xFFFF) == 0 ? P.t_near : 0.0f;
       float box0, box1;
       live = seg_box(F, ox, oy, oz, dx, dy, dz, box0, box1);

@@ -24,10 +24,10 @@ MR_SAMPLER_UNIFORM, MR_SAMPLER_PROPOSAL = 0, 1
 
 EXPORTED = [
     "mr_autotune_render", "mr_camera_bounce_limits", "mr_field_build_occupancy", "mr_field_create",
-    "mr_field_destroy", "mr_field_params", "mr_field_query", "mr_graph_destroy", "mr_graph_launch",
-    "mr_last_error", "mr_mesh_build_bvh", "mr_mesh_closest_hit", "mr_mesh_destroy", "mr_mesh_info",
-    "mr_mesh_refit", "mr_probe_gather", "mr_profile_enable", "mr_profile_read", "mr_proposal_grad",
-    "mr_proposal_targets", "mr_proposal_train_step", "mr_rays_from_cameras", "mr_render",
+    "mr_field_destroy", "mr_field_params", "mr_field_query", "mr_field_set_pose", "mr_graph_destroy",
+    "mr_graph_launch", "mr_last_error", "mr_mesh_build_bvh", "mr_mesh_closest_hit", "mr_mesh_destroy",
+    "mr_mesh_info", "mr_mesh_refit", "mr_probe_gather", "mr_profile_enable", "mr_profile_read",
+    "mr_proposal_grad", "mr_proposal_targets", "mr_proposal_train_step", "mr_rays_from_cameras", "mr_render",
     "mr_render_graph_create", "mr_render_workspace_size", "mr_version",
 ]
 
@@ -244,6 +244,8 @@ class Field:
         self.src = f
         self.handle = mr_field_create(d, np.ascontiguousarray(f.table, dtype=np.float32),
                                       np.ascontiguousarray(f.mlp, dtype=np.float32), stream)
+        if getattr(f, "pose", None) is not None:
+            self.set_pose(f.pose)
 
     def query(self, x, dirs=None, want_rgb=True, want_feat=False, want_raw=False):
         import torch
@@ -256,6 +258,14 @@ class Field:
         raw = torch.empty(n, 16, device=dev, dtype=torch.float32) if want_raw else None
         mr_field_query(self.handle, n, x, dirs, sigma, rgb, feat, raw)
         return dict(sigma=sigma, rgb=rgb, feat=feat, raw=raw)
+
+    def set_pose(self, pose):
+        """Rigid placement [R | c] (3x4, field frame -> world) or None."""
+        if pose is None:
+            _check(lib().mr_field_set_pose(self.handle, None))
+        else:
+            p = np.ascontiguousarray(np.asarray(pose, dtype=np.float32).reshape(12))
+            _check(lib().mr_field_set_pose(self.handle, p.ctypes.data_as(C.c_void_p)))
 
     def build_occupancy(self, res, thresh, export=False):
         import torch

@@ -465,3 +465,60 @@ def test_render_with_occupancy_matches_oracle():
     compare_render(g, r, "occupancy", rtol=1e-3, atol=1e-6)
     full = orc.render(sc, o, d)
     assert np.abs(full["radiance"] - r["radiance"]).max() > 1e-4   # skipping changed the image
+
+
+# ---------------------------------------------------------------------------
+# placement of the field (a moving NeRF object)
+# ---------------------------------------------------------------------------
+
+def _posed(f, R, c):
+    g = sg.Field(**{k: getattr(f, k) for k in f.__dataclass_fields__})
+    g.pose = sg.pose_matrix(R, c)
+    return g
+
+
+@pytest.mark.parametrize("amp,rtol", [(1e-4, RTOL), (1.0, 1e-3)])
+def test_render_with_field_pose_matches_oracle(amp, rtol):
+    """Tiny scene with the field turned 0.9 rad about (1, 2, -1) and moved by
+    (0.2, -0.1, 0.15): hit ids exact, radiance within 1e-4 relative (1e-3 for
+    the amplitude-1 table, where FP32 positions matter at the finest level)
+    plus 1e-6 absolute: the FP32 change of frame rounds the ray origin (|o| <=
+    2.6) by about 3e-7, which moves both ends of the box-clipped chord by that
+    much; with sigma = 1.31 and colour O(1) a ray that grazes an edge of the
+    turned box, chord ~1e-4, carries ~8e-7 absolute error at any chord
+    length."""
+    sc = sg.tiny_scene(table_amp=amp)
+    sc.field = _posed(sc.field, sg.rotation((1.0, 2.0, -1.0), 0.9), (0.2, -0.1, 0.15))
+    o, d = oracle_camera_rays(sc)
+    r = orc.render(sc, o, d)
+    g = gpu_render(sc, o, d)
+    compare_render(g, r, f"posed field amp={amp}", rtol=rtol, atol=1e-6)
+
+
+def test_field_query_under_exact_motion_is_bit_equal():
+    """A 90-degree turn about z and a dyadic shift are exact in FP32: the
+    posed field queried at moved points and directions returns the unposed
+    field's values bit for bit."""
+    M = mr()
+    f = sg.tiny_field(table_amp=1.0)
+    R = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    c = np.array([0.25, -0.5, 0.125])
+    rng = np.random.default_rng(35)
+    x = (rng.integers(-4000, 4000, size=(3000, 3)) / 4096.0).astype(np.float32)
+    d = sg.sample_points(3000, seed=36)[1]
+    a = M.Field(f).query(dev(x), dev(d), want_feat=True)
+    b = M.Field(_posed(f, R, c)).query(dev((x @ R.T + c).astype(np.float32)), dev((d @ R.T).astype(np.float32)),
+                                       want_feat=True)
+    for k in ("sigma", "rgb", "feat"):
+        np.testing.assert_array_equal(host(a[k]), host(b[k]))
+
+
+def test_set_pose_rejects_non_rotations():
+    M = mr()
+    F = M.Field(sg.tiny_field())
+    with pytest.raises(M.MrError):
+        F.set_pose(sg.pose_matrix(1.01 * np.eye(3), np.zeros(3)))            # scaled
+    with pytest.raises(M.MrError):
+        F.set_pose(sg.pose_matrix(np.diag([1.0, 1.0, -1.0]), np.zeros(3)))   # reflection
+    F.set_pose(sg.pose_matrix(sg.rotation((0, 0, 1), 0.3), (0.1, 0.0, 0.0)))
+    F.set_pose(None)

@@ -139,3 +139,23 @@ def test_training_gains_over_untrained_and_uniform():
     assert p_tr >= 40.0
     assert p_tr > p_un + 3.0
     assert p_tr > p_u64 + 3.0
+
+
+def test_proposal_render_with_field_pose_matches_oracle():
+    """The proposal is evaluated in the frame of the field it samples for:
+    shell field turned and moved, 32 + 32 samples, against the oracle."""
+    M = mr()
+    sc = sg.tiny_scene()
+    f = sg.shell_field()
+    f.pose = sg.pose_matrix(sg.rotation((0.3, 1.0, 0.2), 0.6), (0.1, 0.05, -0.1))
+    sc.field = f
+    prop = sg.make_proposal(table_amp=0.5)
+    o, d = oracle_camera_rays(sc)
+    r = orc.render(sc, o, d, proposal=prop, n_prop=32, n_fine=32)
+    F, G = M.Field(sc.field), M.Mesh(sc.mesh)
+    P = M.Field(prop, table_dtype=M.MR_F32)
+    R = M.Renderer(len(o), sc.max_bounces)
+    R.render(F, G, dev(o), dev(d), sc.lights, M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P))
+    g = dict(radiance=host(R.radiance), throughput=host(R.throughput), bounces=host(R.bounces),
+             hit_ids=host(R.hit_ids))
+    compare_render(g, r, "proposal posed shell", rtol=1e-3, atol=1e-6)
