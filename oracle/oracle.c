@@ -477,19 +477,47 @@ static int occupied(const orc_opts* opt, const orc_field* f, const double x[3], 
   return here;
 }
 
+/* What a sample's shadow mask needs: the meshes, the lights, the mask value
+ * and the segment in world coordinates (the field may be placed elsewhere). */
+typedef struct {
+  const orc_mesh* m;
+  const float* lights;       /* [n_lights][6]: position, intensity */
+  int32_t n_lights;
+  double mask;
+  const double* o_world;
+  const double* d_world;
+} shadow_ctx;
+
+/* Shadow mask m(p_t) of one sample: 1, times the mask value for every light
+ * that a mesh hides from the sample's world position. */
+static double sample_mask(const shadow_ctx* sh, const orc_opts* opt, double tm, int* tie) {
+  double m = 1.0, x[3];
+  for (int k = 0; k < 3; ++k) x[k] = sh->o_world[k] + tm * sh->d_world[k];
+  for (int li = 0; li < sh->n_lights; ++li) {
+    const float* lt = sh->lights + 6 * li;
+    double sd[3] = {lt[0] - x[0], lt[1] - x[1], lt[2] - x[2]};
+    double dist = sqrt(dot3(sd, sd));
+    for (int k = 0; k < 3; ++k) sd[k] /= dist;
+    if (any_hit(sh->m, x, sd, dist, opt->tie_eps, tie)) m *= sh->mask;
+  }
+  return m;
+}
+
 /* Composite one interval [a, b] at its midpoint: alpha = 1 - exp(-sigma D),
- * L += T alpha c, T *= (1 - alpha).  Returns the number of field samples. */
+ * L += T alpha m c with the sample's shadow mask m (1 without shadows),
+ * T *= (1 - alpha).  Returns the number of field samples. */
 static int composite_interval(const orc_field* f, const orc_opts* opt, const double o[3],
                               const double d[3], double a, double b, double T[3], double L[3],
-                              int* tie) {
+                              int* tie, const shadow_ctx* sh) {
   if (!(b > a)) return 0;
   double tm = 0.5 * (a + b), D = b - a, x[3], sigma, rgb[3];
   for (int k = 0; k < 3; ++k) x[k] = o[k] + tm * d[k];
   if (!occupied(opt, f, x, tie)) return 0;
   orc_field_eval(f, x, d, &sigma, rgb, NULL);
+  double m = sh ? sample_mask(sh, opt, tm, tie) : 1.0;
   double alpha = -expm1(-sigma * D);
   for (int c = 0; c < 3; ++c) {
-    L[c] += T[c] * alpha * rgb[c];
+    L[c] += T[c] * alpha * m * rgb[c];
     T[c] *= (1.0 - alpha);
   }
   return 1;
@@ -517,8 +545,16 @@ void orc_proposal_weights(const orc_field* p, const double o[3], const double d[
  * of that piecewise-constant density at u = k/n_fine. */
 static int64_t march(const orc_field* f, const orc_opts* opt, const double o_world[3],
                      const double d_world[3], double t_a, double t_hit, double T[3], double L[3],
-                     int* tie) {
+                     int* tie, const shadow_ctx* sh_in) {
   if (!f) return 0;
+  shadow_ctx shc;
+  const shadow_ctx* sh = NULL;
+  if (sh_in) {
+    shc = *sh_in;
+    shc.o_world = o_world;
+    shc.d_world = d_world;
+    sh = &shc;
+  }
   /* the segment in the field's frame (the proposal field shares that frame) */
   double o[3], d[3];
   world_to_field(f, o_world, d_world, o, d);
@@ -554,7 +590,7 @@ static int64_t march(const orc_field* f, const orc_opts* opt, const double o_wor
       double fr = (u - cdf[j]) / (cdf[j + 1] - cdf[j]);
       edges[k] = lo + (j + fr) * step;
     }
-    for (int k = 0; k < nf; ++k) ns += composite_interval(f, opt, o, d, edges[k], edges[k + 1], T, L, tie);
+    for (int k = 0; k < nf; ++k) ns += composite_interval(f, opt, o, d, edges[k], edges[k + 1], T, L, tie, sh);
     return ns;
   }
   double delta = span / opt->n_samples;
@@ -562,7 +598,7 @@ static int64_t march(const orc_field* f, const orc_opts* opt, const double o_wor
     double a = t_a + k * delta, b = t_a + (k + 1) * delta;
     if (b <= lo) continue;
     if (a >= hi) break;
-    ns += composite_interval(f, opt, o, d, fmax(a, lo), fmin(b, hi), T, L, tie);
+    ns += composite_interval(f, opt, o, d, fmax(a, lo), fmin(b, hi), T, L, tie, sh);
   }
   return ns;
 }
@@ -683,7 +719,9 @@ static void render_ray(const job_t* J, int64_t r) {
     int hit = m ? orc_closest_hit(m, o, d, t_max, opt->tie_eps, &t_hit, bary, &t_tie) : -1;
     tie |= t_tie;
     if (J->out->hit_ids) J->out->hit_ids[r * stride + s] = hit;
-    nsamp += march(J->f, opt, o, d, t_a, hit >= 0 ? t_hit : INFINITY, T, L, &tie);
+    shadow_ctx sh = {m, J->lights, J->n_lights, opt->shadow_mask, NULL, NULL};
+    nsamp += march(J->f, opt, o, d, t_a, hit >= 0 ? t_hit : INFINITY, T, L, &tie,
+                   opt->sample_shadows && m && J->n_lights > 0 ? &sh : NULL);
     ++segs;
     if (hit < 0) break;                  /* escaped the scene: background is 0 */
     if (s == mb) break;                  /* bounce limit: stop at the surface   */

@@ -59,6 +59,11 @@ typedef struct {
   const orc_field* proposal; /* density-only field (d_out = 1, c_layers = 0) */
   int32_t n_prop;            /* proposal intervals */
   int32_t n_fine;            /* fine samples drawn from the proposal */
+  /* optional shadow mask per field sample (Sec. 3.1 "Shadow rays"): a ray from
+   * the sample to each light; each light a mesh blocks multiplies the
+   * sample's emitted radiance by shadow_mask */
+  int32_t sample_shadows;
+  double shadow_mask;
 } orc_opts;
 
 typedef struct {

@@ -50,7 +50,8 @@ class _Opts(C.Structure):
                 ("t_min_throughput", C.c_double), ("seed", C.c_uint32),
                 ("tie_eps", C.c_double), ("tie_rel", C.c_double),
                 ("occ_res", C.c_int32), ("occ", C.c_void_p),
-                ("proposal", C.c_void_p), ("n_prop", C.c_int32), ("n_fine", C.c_int32)]
+                ("proposal", C.c_void_p), ("n_prop", C.c_int32), ("n_fine", C.c_int32),
+                ("sample_shadows", C.c_int32), ("shadow_mask", C.c_double)]
 
 
 class _Out(C.Structure):
@@ -212,8 +213,12 @@ def occupancy(field, res, thresh, n_threads=None):
 
 def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
            tie_eps=1e-5, tie_rel=1e-4, occupancy_bits=None, proposal=None, n_prop=32,
-           n_fine=32, field=..., mesh=...):
+           n_fine=32, field=..., mesh=..., shadow_mask=None):
     """Render FP32 input rays through the whole path in FP64.
+
+    shadow_mask: None = no per-sample shadows; else every field sample that a
+    mesh hides from a light has its emitted radiance multiplied by this value
+    once per such light (Sec. 3.1 "Shadow rays").
 
     Returns a dict with radiance, throughput, bounces, hit_ids (segments),
     tie flags, per-ray sample and segment counts.
@@ -245,6 +250,8 @@ def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
     if op is not None:
         opt.proposal = C.cast(C.pointer(op.s), C.c_void_p)
         opt.n_prop, opt.n_fine = int(n_prop), int(n_fine)
+    if shadow_mask is not None:
+        opt.sample_shadows, opt.shadow_mask = 1, float(shadow_mask)
     res = dict(radiance=np.zeros((n, 3)), throughput=np.zeros((n, 3)),
                bounces=np.zeros(n, dtype=np.int32),
                hit_ids=np.full((n, gmax + 1), -1, dtype=np.int32),

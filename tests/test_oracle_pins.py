@@ -811,3 +811,86 @@ def test_pose_field_queries_exact_under_exact_motion():
     b = orc.field_batch(_posed(f, R, c), (x @ R.T + c).astype(np.float32), (d @ R.T).astype(np.float32))
     for k in ("sigma", "rgb", "feat"):
         np.testing.assert_array_equal(a[k], b[k])
+
+
+# ---------------------------------------------------------------------------
+# shadow mask per field sample (Sec. 3.1 "Shadow rays"): a sample a mesh hides
+# from a light emits mask x its radiance
+# ---------------------------------------------------------------------------
+
+def _blocker_quad(y=1.5, half=0.5):
+    v = np.array([[-half, y, -half], [half, y, -half], [half, y, half], [-half, y, half]], np.float32)
+    f = np.array([[0, 1, 2], [0, 2, 3]], np.int32)
+    return sg.merge_meshes([(v, f, 0)], [[sg.DIFFUSE, 1.0, 0.7, 0.7, 0.7]])
+
+
+def test_sample_shadows_change_nothing_without_blockers_lights_or_strength():
+    sc = sg.tiny_scene(table_amp=1.0)
+    sc.lights = sg.seeded_light()
+    o, d = sg.random_rays(200, seed=41)
+    a = orc.render(sc, o, d)
+    np.testing.assert_array_equal(a["radiance"], orc.render(sc, o, d, shadow_mask=1.0)["radiance"])
+    no_mesh = orc.render(sc, o, d, mesh=None)
+    np.testing.assert_array_equal(no_mesh["radiance"], orc.render(sc, o, d, mesh=None, shadow_mask=0.2)["radiance"])
+    sc.lights = sg.no_lights()
+    np.testing.assert_array_equal(orc.render(sc, o, d)["radiance"], orc.render(sc, o, d, shadow_mask=0.2)["radiance"])
+
+
+def test_sample_shadow_closed_form_under_a_blocker():
+    """Constant medium (sigma = softplus(1), colour 1) crossed along x at y = 0,
+    z = 0; a quad at y = 1.5 over |x|, |z| < 0.5 and a light at (0, 5, 0): the
+    segment from (x, 0, 0) to the light crosses y = 1.5 at (0.7 x, 1.5, 0), so
+    exactly the samples with |x| < 0.5 / 0.7 are hidden.  L is the sum over the
+    fixed grid of T alpha m with m = 0.25 for hidden midpoints."""
+    f = _constant_field()
+    sigma = math.log1p(math.e)
+    light = np.array([[0.0, 5.0, 0.0, 10.0, 10.0, 10.0]], np.float32)
+    sc = _scene(f, _blocker_quad(), light)
+    o = np.array([[-2.5, 0.0, 0.0]], np.float32)
+    d = np.array([[1.0, 0.0, 0.0]], np.float32)
+    r = orc.render(sc, o, d, shadow_mask=0.25)
+    assert r["tie"][0] == 0 and r["hit_ids"][0, 0] == -1
+    delta = (sc.t_far - sc.t_near) / sc.n_samples
+    lo, hi = 1.5, 3.5                    # the box chord x in [-1, 1]
+    T, L = 1.0, 0.0
+    for k in range(sc.n_samples):
+        a, b = sc.t_near + k * delta, sc.t_near + (k + 1) * delta
+        a, b = max(a, lo), min(b, hi)
+        if not b > a:
+            continue
+        x = -2.5 + 0.5 * (a + b)
+        m = 0.25 if abs(0.7 * x) < 0.5 else 1.0
+        alpha = 1.0 - math.exp(-sigma * (b - a))
+        L += T * alpha * m
+        T *= 1.0 - alpha
+    np.testing.assert_allclose(r["radiance"][0], L, rtol=1e-12)
+    np.testing.assert_allclose(r["throughput"][0], T, rtol=1e-12)
+    plain = orc.render(sc, o, d)
+    assert plain["radiance"][0, 0] > r["radiance"][0, 0] * 1.2
+
+
+def test_sample_shadow_masks_multiply_over_lights():
+    """Lights at (0, 5, 0) and (0, 6, 0) over the quad: the first hides
+    |x| < 0.5 / 0.7, the second |x| < 0.5 / 0.75 (the segment crosses y = 1.5
+    at 0.7 x and 0.75 x), so with mask 0.5 the middle samples get 0.25, the
+    samples hidden from the first light only 0.5, the others 1."""
+    f = _constant_field()
+    sigma = math.log1p(math.e)
+    lights = np.array([[0.0, 5.0, 0.0, 1, 1, 1], [0.0, 6.0, 0.0, 1, 1, 1]], np.float32)
+    sc = _scene(f, _blocker_quad(), lights)
+    o = np.array([[-2.5, 0.0, 0.0]], np.float32)
+    d = np.array([[1.0, 0.0, 0.0]], np.float32)
+    r = orc.render(sc, o, d, shadow_mask=0.5)
+    assert r["tie"][0] == 0
+    delta = (sc.t_far - sc.t_near) / sc.n_samples
+    T, L = 1.0, 0.0
+    for k in range(sc.n_samples):
+        a, b = max(sc.t_near + k * delta, 1.5), min(sc.t_near + (k + 1) * delta, 3.5)
+        if not b > a:
+            continue
+        x = -2.5 + 0.5 * (a + b)
+        m = (0.5 if abs(0.7 * x) < 0.5 else 1.0) * (0.5 if abs(0.75 * x) < 0.5 else 1.0)
+        alpha = 1.0 - math.exp(-sigma * (b - a))
+        L += T * alpha * m
+        T *= 1.0 - alpha
+    np.testing.assert_allclose(r["radiance"][0], L, rtol=1e-12)
