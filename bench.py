@@ -244,6 +244,24 @@ def moving_field(M, sg, sc, F, G, cams, n, steps):
             "motion": "turn 0.05 rad about y and move 0.02 along x per step"}
 
 
+def sample_shadows(M, sg, sc, F, G, cams, n, steps, mask=0.2):
+    """The mid workload with the paper's per-sample shadow mask: every field
+    sample sends a ray to the light (one any-hit traversal per sample)."""
+    import torch
+    o = torch.empty(n, 3, device="cuda")
+    d = torch.empty(n, 3, device="cuda")
+    R = M.Renderer(n, sc.max_bounces, with_hits=False)
+    opts = M.make_opts(sc, use_occupancy=True, shadow_mask=mask)
+
+    def step():
+        M.mr_rays_from_cameras(cams, o, d, None, n)
+        R.render(F, G, o, d, sc.lights, opts)
+    ms = timed(step, steps, 1)
+    c = R.counters.cpu().numpy()
+    return {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms, 3),
+            "shadow_rays_per_s": round(int(c[0]) * len(sc.lights) / (ms / 1e3), 1), "mask": mask}
+
+
 def multicam(M, sg, steps):
     """16 cameras of uneven size and bounce depth in one queue, replayed as a graph."""
     import numpy as np
@@ -463,6 +481,7 @@ def main():
                                                  args.train_steps)
         line["precision_tiny_vs_fp64_oracle"] = precision_report(M, sg)
         line["moving_field"] = moving_field(M, sg, sc, F, G, cams, n, args.steps)
+        line["sample_shadows"] = sample_shadows(M, sg, sc, F, G, cams, n, args.steps)
         line["multicam_16_cameras"] = multicam(M, sg, 2)
         line["cloth_refit"] = cloth(M, sg, args.cloth_frames, args.train_steps)
     if not args.no_cpu_baseline:

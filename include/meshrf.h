@@ -209,6 +209,14 @@ typedef struct {
                                    the table; later segments march one ray per wave, 16
                                    samples per tile.  0 = default (1: the caller's rays),
                                    -1 = none, k > 0 = segments 0..k-1 */
+  int32_t sample_shadows;       /* 1: shadow mask per field sample (Sec. 3.1 "Shadow
+                                   rays"): a ray from each sample to each light, and
+                                   every light a mesh hides multiplies the sample's
+                                   emitted radiance by shadow_mask (transmittance is
+                                   unchanged); uniform sampler only (MR_ERR_UNSUPPORTED
+                                   with the proposal sampler) */
+  float shadow_mask;            /* mask value of a hidden sample, in [0, 1] (the paper's
+                                   1 - r_src, or a constant near 0) */
 } mr_render_opts;
 
 /* One launch shape (the launch fields of mr_render_opts). */

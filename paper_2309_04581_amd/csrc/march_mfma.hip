@@ -70,12 +70,32 @@ __device__ __forceinline__ bool occ_lookup(const FieldView& F, float px, float p
   return (F.occ[c >> 5] >> (c & 31)) & 1u;
 }
 
+// Shadow mask of the sample of column j (Sec. 3.1 "Shadow rays"): a lane of
+// group 0 sends a ray from the sample's world position to every light, and
+// each light a mesh hides multiplies the mask by P.shadow_mask; every lane
+// returns its column's mask.  stack: that lane's LDS stack, stride 16.
+__device__ __forceinline__ float sample_shadow(const FieldView& F, const BvhView& B, const MarchParams& P,
+                                               bool valid, float px, float py, float pz, int lane, int* stack) {
+  float m = 1.0f;
+  if (lane < 16 && valid) {
+    field_to_world(F, px, py, pz);
+    for (int li = 0; li < P.n_lights; ++li) {
+      const float sx = P.light_pos[li][0] - px, sy = P.light_pos[li][1] - py, sz = P.light_pos[li][2] - pz;
+      const float dist = sqrtf(sx * sx + sy * sy + sz * sz);
+      const RayPre sr = ray_pre(v3(px, py, pz), v3(sx / dist, sy / dist, sz / dist));
+      float th;
+      if (bvh_trace<true>(B, sr, dist, th, stack, nullptr, 16) >= 0) m *= P.shadow_mask;
+    }
+  }
+  return __shfl(m, lane & 15, 64);
+}
+
 // One ray per wave: lane j takes sample kb + j of each 16-sample tile, and
 // transmittance is a 16-lane prefix product carried from tile to tile.
 template <int NL, int SH, int CL, typename TabT, bool BF>
 __device__ __forceinline__ void march_ray(const RayQueue& q, int r, const FieldView& F, const TabT* __restrict__ table,
-                                          const uint32_t* __restrict__ sW, const MarchParams& P, bool use_occ,
-                                          int lane, unsigned long long& nsamp) {
+                                          const uint32_t* __restrict__ sW, const MarchParams& P, const BvhView& B,
+                                          int* sstack, bool use_occ, int lane, unsigned long long& nsamp) {
   using LY = FragLayout<NL, SH, CL, BF>;
   const int g = lane >> 4, j = lane & 15;
   const float delta = P.delta;
@@ -111,7 +131,8 @@ __device__ __forceinline__ void march_ray(const RayQueue& q, int r, const FieldV
     const float incl = scan16_mul(1.0f - alpha, j);
     float excl = __shfl_up(incl, 1, 16);
     if (j == 0) excl = 1.0f;
-    const float w = Tseg * excl * alpha;
+    const float msk = P.shadows ? sample_shadow(F, B, P, valid, px, py, pz, lane, sstack) : 1.0f;
+    const float w = Tseg * excl * alpha * msk;
     acc0 += w * rgb[0];
     acc1 += w * rgb[1];
     acc2 += w * rgb[2];
@@ -159,8 +180,8 @@ __device__ __forceinline__ PacketRay packet_ray(const RayQueue& q, int r, int cn
 template <int NL, int SH, int CL, typename TabT, bool BF>
 __device__ __forceinline__ void march_packet(const RayQueue& q, const PacketRay& R, const FieldView& F,
                                              const TabT* __restrict__ table, const uint32_t* __restrict__ sW,
-                                             const MarchParams& P, bool use_occ, int lane,
-                                             unsigned long long& nsamp) {
+                                             const MarchParams& P, const BvhView& B, int* sstack, bool use_occ,
+                                             int lane, unsigned long long& nsamp) {
   using LY = FragLayout<NL, SH, CL, BF>;
   const int g = lane >> 4;
   const float delta = P.delta;
@@ -207,7 +228,8 @@ __device__ __forceinline__ void march_packet(const RayQueue& q, const PacketRay&
     f4v raw;
     mlp_tile<NL, SH, CL, BF>(sW, fe, u, F.density_offset, lane, sigma, rgb, raw);
     const float alpha = valid ? -expm1f(-sigma * D) : 0.0f;
-    const float w = T * alpha;
+    const float msk = P.shadows ? sample_shadow(F, B, P, valid, px, py, pz, lane, sstack) : 1.0f;
+    const float w = T * alpha * msk;
     acc0 += w * rgb[0];
     acc1 += w * rgb[1];
     acc2 += w * rgb[2];
@@ -229,14 +251,16 @@ __device__ __forceinline__ void march_packet(const RayQueue& q, const PacketRay&
 template <int NL, int SH, int CL, typename TabT, bool BF, bool PK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_march_mfma(
     RayQueue q, const int* __restrict__ count, int* __restrict__ work, FieldView F, const TabT* __restrict__ table,
-    const uint32_t* __restrict__ frags, MarchParams P, unsigned long long* __restrict__ stats) {
+    const uint32_t* __restrict__ frags, MarchParams P, BvhView B, unsigned long long* __restrict__ stats) {
   using LY = FragLayout<NL, SH, CL, BF>;
   __shared__ __align__(16) uint32_t sW[LY::TOTAL];
+  __shared__ int sstack[4 * 16 * kStack];   // shadow-ray stacks: 16 lanes per wave
   for (int i = threadIdx.x; i < LY::TOTAL; i += blockDim.x) sW[i] = frags[i];
   __syncthreads();
   const int lane = threadIdx.x & 63, j = lane & 15;
   const int cnt = *count;
   const bool use_occ = P.use_occupancy && F.occ;
+  int* stack = sstack + (threadIdx.x >> 6) * 16 * kStack + j;
   unsigned long long nsamp = 0;
   if constexpr (!PK) {
     WorkQueue wq(work, cnt, P.chunk, P.batch);
@@ -244,13 +268,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       for (int bi = 0; bi < wq.batch; ++bi) {
         const int r = wq.map(base + bi);
         if (r >= cnt) break;
-        march_ray<NL, SH, CL, TabT, BF>(q, r, F, table, sW, P, use_occ, lane, nsamp);
+        march_ray<NL, SH, CL, TabT, BF>(q, r, F, table, sW, P, B, stack, use_occ, lane, nsamp);
       }
   } else {
     WorkQueue wq(work, cnt, P.chunk, 16);
     for (int base = wq.next(lane); base >= 0; base = wq.next(lane)) {
       const PacketRay R = packet_ray(q, wq.map(base + j), cnt, F);
-      march_packet<NL, SH, CL, TabT, BF>(q, R, F, table, sW, P, use_occ, lane, nsamp);
+      march_packet<NL, SH, CL, TabT, BF>(q, R, F, table, sW, P, B, stack, use_occ, lane, nsamp);
     }
   }
   if (stats) {
@@ -308,23 +332,24 @@ __global__ __launch_bounds__(256) void k_query_mfma(FieldView F, const TabT* __r
 
 template <int NL, int SH, int CL, typename TabT, bool BF, bool PK>
 mr_status launch_march_mode(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
-                            unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st) {
+                            const BvhView& B, unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st) {
   const uint32_t* fr = BF ? f->frag_bf16_dev : f->frag_f32_dev;
   const TabT* tab = reinterpret_cast<const TabT*>(f->table_dev);
   auto* k = k_march_mfma<NL, SH, CL, TabT, BF, PK>;
   const int64_t cap = PK ? (n + 63) / 64 : (n + 3) / 4;
   const int blocks = persistent_blocks(reinterpret_cast<const void*>(k), 256, blocks_per_cu, cap);
-  hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, q, count, work, f->view, tab, fr, P, stats);
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, q, count, work, f->view, tab, fr, P, B, stats);
   MR_HIP(hipGetLastError());
   return MR_OK;
 }
 
 template <int NL, int SH, int CL, typename TabT, bool BF>
 mr_status launch_march_mfma(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
-                            bool packets, unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st) {
+                            const BvhView& B, bool packets, unsigned long long* stats, int blocks_per_cu, int64_t n,
+                            hipStream_t st) {
   if (packets)
-    return launch_march_mode<NL, SH, CL, TabT, BF, true>(f, q, count, work, P, stats, blocks_per_cu, n, st);
-  return launch_march_mode<NL, SH, CL, TabT, BF, false>(f, q, count, work, P, stats, blocks_per_cu, n, st);
+    return launch_march_mode<NL, SH, CL, TabT, BF, true>(f, q, count, work, P, B, stats, blocks_per_cu, n, st);
+  return launch_march_mode<NL, SH, CL, TabT, BF, false>(f, q, count, work, P, B, stats, blocks_per_cu, n, st);
 }
 
 template <int NL, int SH, int CL, typename TabT, bool BF>
@@ -401,15 +426,16 @@ std::vector<uint32_t> build_fragments(const mr_field_desc& d, const float* mlp, 
 }
 
 mr_status dispatch_march_mfma(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
-                              bool packets, unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st) {
+                              const BvhView& B, bool packets, unsigned long long* stats, int blocks_per_cu, int64_t n,
+                              hipStream_t st) {
   const auto& v = f->view;
   const bool h = v.table_dtype == MR_F16, bf = v.mlp_dtype == MR_BF16;
 #define M(NL, SH, CL)                                                                                              \
   if (v.n_levels == NL && v.sh == SH && v.c_layers == CL) {                                                         \
-    if (bf) return h ? launch_march_mfma<NL, SH, CL, __half, true>(f, q, count, work, P, packets, stats, blocks_per_cu, n, st)         \
-                     : launch_march_mfma<NL, SH, CL, float, true>(f, q, count, work, P, packets, stats, blocks_per_cu, n, st);         \
-    return h ? launch_march_mfma<NL, SH, CL, __half, false>(f, q, count, work, P, packets, stats, blocks_per_cu, n, st)                \
-             : launch_march_mfma<NL, SH, CL, float, false>(f, q, count, work, P, packets, stats, blocks_per_cu, n, st);                \
+    if (bf) return h ? launch_march_mfma<NL, SH, CL, __half, true>(f, q, count, work, P, B, packets, stats, blocks_per_cu, n, st)         \
+                     : launch_march_mfma<NL, SH, CL, float, true>(f, q, count, work, P, B, packets, stats, blocks_per_cu, n, st);         \
+    return h ? launch_march_mfma<NL, SH, CL, __half, false>(f, q, count, work, P, B, packets, stats, blocks_per_cu, n, st)                \
+             : launch_march_mfma<NL, SH, CL, float, false>(f, q, count, work, P, B, packets, stats, blocks_per_cu, n, st);                \
   }
   M(8, 4, 1)
   M(16, 16, 2)

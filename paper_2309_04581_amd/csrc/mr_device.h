@@ -84,6 +84,16 @@ __device__ __forceinline__ void to_field_frame(const FieldView& F, float& px, fl
   dz = P[2] * ex + P[6] * ey + P[10] * ez;
 }
 
+// The inverse map for points: field frame -> world, p -> R p + c.
+__device__ __forceinline__ void field_to_world(const FieldView& F, float& px, float& py, float& pz) {
+  if (!F.has_pose) return;
+  const float* P = F.pose;
+  const float x = px, y = py, z = pz;
+  px = P[0] * x + P[1] * y + P[2] * z + P[3];
+  py = P[4] * x + P[5] * y + P[6] * z + P[7];
+  pz = P[8] * x + P[9] * y + P[10] * z + P[11];
+}
+
 // Corner indices and trilinear weights of one level.
 __device__ __forceinline__ void level_corners(const FieldView& F, int l, float xh, float yh, float zh,
                                               uint32_t idx[8], float w[8]) {

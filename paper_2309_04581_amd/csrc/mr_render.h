@@ -26,6 +26,12 @@ struct MarchParams {
   int use_occupancy;
   int chunk;          // rays per die chunk of the march queue (0 = one global queue)
   int batch;          // queue positions a wave takes per atomic
+  // shadow mask per field sample: each light a mesh hides from the sample
+  // multiplies its emitted radiance by shadow_mask
+  int shadows;
+  float shadow_mask;
+  int n_lights;
+  float light_pos[kMaxLights][3];
 };
 
 struct ShadeParams {
@@ -91,7 +97,8 @@ int persistent_blocks(const void* kernel, int threads, int per_cu, int64_t cap);
 // packets: 16 consecutive queue rays per wave in step (else one ray per wave);
 // blocks_per_cu: 0 = as many as fit; n: rays in the queue at most
 mr_status dispatch_march_mfma(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
-                              bool packets, unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st);
+                              const BvhView& B, bool packets, unsigned long long* stats, int blocks_per_cu, int64_t n,
+                              hipStream_t st);
 
 // proposal-sampled march (defined with the proposal kernels)
 // packets: 16 consecutive queue rays per wave when n_prop = 32 and n_fine <= 32

@@ -431,6 +431,10 @@ mr_status validate_render(const mr_field* field, const mr_mesh* mesh, int64_t n,
   if (opts->march_chunk < 0) return fail(MR_ERR_INVALID_ARG, "march_chunk must be >= 0");
   if (opts->march_batch < 0 || opts->march_batch > 64) return fail(MR_ERR_INVALID_ARG, "march_batch must be in 0..64");
   if (opts->march_packets < -1) return fail(MR_ERR_INVALID_ARG, "march_packets must be >= -1");
+  if (opts->sample_shadows && !(opts->shadow_mask >= 0.0f && opts->shadow_mask <= 1.0f))
+    return fail(MR_ERR_INVALID_ARG, "shadow_mask must be in [0, 1]");
+  if (opts->sample_shadows && opts->sampler == MR_SAMPLER_PROPOSAL)
+    return fail(MR_ERR_UNSUPPORTED, "sample shadows are built for the uniform sampler only");
   if (opts->use_occupancy && field && !field->occ_dev)
     return fail(MR_ERR_STATE, "use_occupancy set but the field has no occupancy grid");
   return MR_OK;
@@ -483,6 +487,11 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
   P.use_occupancy = opts->use_occupancy;
   P.chunk = opts->march_chunk;
   P.batch = opts->march_batch > 0 ? opts->march_batch : 1;
+  P.shadows = opts->sample_shadows && mesh && n_lights > 0;
+  P.shadow_mask = opts->shadow_mask;
+  P.n_lights = n_lights;
+  for (int i = 0; i < n_lights; ++i)
+    for (int k = 0; k < 3; ++k) P.light_pos[i][k] = host_lights[i].pos[k];
 
   ShadeParams S;
   std::memset(&S, 0, sizeof(S));
@@ -524,7 +533,7 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
         s = dispatch_march_proposal(field, opts->proposal, qi, counts + b, work + kXcds * b, P, opts->n_proposal,
                                     opts->n_fine, b < packet_segments, stats, opts->march_blocks_per_cu, n, st);
       else
-        s = dispatch_march_mfma(field, qi, counts + b, work + kXcds * b, P, b < packet_segments, stats,
+        s = dispatch_march_mfma(field, qi, counts + b, work + kXcds * b, P, mv.bvh, b < packet_segments, stats,
                                 opts->march_blocks_per_cu, n, st);
       if (s != MR_OK) return s;
     }

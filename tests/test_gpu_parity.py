@@ -522,3 +522,71 @@ def test_set_pose_rejects_non_rotations():
         F.set_pose(sg.pose_matrix(np.diag([1.0, 1.0, -1.0]), np.zeros(3)))   # reflection
     F.set_pose(sg.pose_matrix(sg.rotation((0, 0, 1), 0.3), (0.1, 0.0, 0.0)))
     F.set_pose(None)
+
+
+# ---------------------------------------------------------------------------
+# shadow mask per field sample (Sec. 3.1 "Shadow rays")
+# ---------------------------------------------------------------------------
+
+def _shadow_render(sc, o, d, mask, packets=0):
+    M = mr()
+    F, G = M.Field(sc.field), M.Mesh(sc.mesh)
+    R = M.Renderer(len(o), sc.max_bounces)
+    opts = M.make_opts(sc, shadow_mask=mask)
+    opts.march_packets = packets
+    R.render(F, G, dev(o), dev(d), sc.lights, opts)
+    torch.cuda.synchronize()
+    return dict(radiance=host(R.radiance), throughput=host(R.throughput), bounces=host(R.bounces),
+                hit_ids=host(R.hit_ids))
+
+
+@pytest.mark.parametrize("packets", PACKETS)
+def test_sample_shadows_tiny_match_oracle(packets):
+    """Tiny scene with a light above the mirror cube: samples the cube hides
+    from the light emit 0.2 of their radiance."""
+    sc = sg.tiny_scene(table_amp=1.0)
+    sc.lights = np.array([[0.1, 1.6, -0.2, 10.0, 10.0, 10.0]], np.float32)
+    o, d = oracle_camera_rays(sc)
+    r = orc.render(sc, o, d, shadow_mask=0.2)
+    plain = orc.render(sc, o, d)
+    assert (np.abs(r["radiance"] - plain["radiance"]) > 1e-3 * plain["radiance"]).any(axis=1).mean() > 0.05
+    g = _shadow_render(sc, o, d, 0.2, packets)
+    compare_render(g, r, f"tiny sample shadows packets={packets}", rtol=1e-3, atol=1e-6)
+
+
+def test_sample_shadows_mid_small_image_match_oracle():
+    """Glass sphere, mirror cube and floor under the mid scene's light, 32x24.
+    Every sample's shadow ray is a geometric decision that can sit within the
+    tie margin of one of the sphere's 30 000 small-triangle edges, so more
+    rays are ties here (about 4%, cap 15%); non-tie rays must match."""
+    sc = sg.mid_scene(width=32, height=24)
+    o, d = oracle_camera_rays(sc)
+    r = orc.render(sc, o, d, shadow_mask=0.1)
+    g = _shadow_render(sc, o, d, 0.1)
+    compare_render(g, r, "mid 32x24 sample shadows", max_tie_frac=0.15)
+
+
+def test_sample_shadows_with_field_pose_match_oracle():
+    """Shadow rays start at the samples' world positions when the field is
+    placed elsewhere."""
+    sc = sg.tiny_scene(table_amp=1.0)
+    sc.lights = np.array([[0.1, 1.6, -0.2, 10.0, 10.0, 10.0]], np.float32)
+    sc.field = _posed(sc.field, sg.rotation((0.0, 1.0, 0.3), 0.5), (0.1, 0.2, 0.0))
+    o, d = oracle_camera_rays(sc)
+    r = orc.render(sc, o, d, shadow_mask=0.2)
+    compare_render(_shadow_render(sc, o, d, 0.2), r, "posed sample shadows", rtol=1e-3, atol=1e-6)
+
+
+def test_sample_shadow_options_validated():
+    M = mr()
+    sc = sg.tiny_scene()
+    sc.lights = np.array([[0.1, 1.6, -0.2, 1.0, 1.0, 1.0]], np.float32)
+    o, d = oracle_camera_rays(sc)
+    F, G = M.Field(sc.field), M.Mesh(sc.mesh)
+    R = M.Renderer(len(o), sc.max_bounces)
+    with pytest.raises(M.MrError):
+        R.render(F, G, dev(o), dev(d), sc.lights, M.make_opts(sc, shadow_mask=1.5))
+    P = M.Field(sg.make_proposal(), table_dtype=M.MR_F32)
+    with pytest.raises(M.MrError):
+        R.render(F, G, dev(o), dev(d), sc.lights,
+                 M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P, shadow_mask=0.2))
