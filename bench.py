@@ -262,6 +262,46 @@ def sample_shadows(M, sg, sc, F, G, cams, n, steps, mask=0.2):
             "shadow_rays_per_s": round(int(c[0]) * len(sc.lights) / (ms / 1e3), 1), "mask": mask}
 
 
+def scaling(M, sg, steps):
+    """After the paper's App. A: rays/s and frame time with 1 .. 10^4 inserted
+    spheres (80 triangles each) at 900x450 over the mid field, and with the
+    image size swept at 100 spheres; the host BVH build time and the device
+    bytes of BVH, triangles and render workspace per configuration."""
+    import torch
+    sc0 = sg.balls_scene(1)
+    F = M.Field(sc0.field)
+    F.build_occupancy(sc0.occupancy_res, sc0.occupancy_thresh)
+
+    def run(sc):
+        cams = sg.cameras_array(sc.cameras)
+        n = sc.n_rays
+        t0 = time.perf_counter()
+        G = M.Mesh(sc.mesh)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        o = torch.empty(n, 3, device="cuda")
+        d = torch.empty(n, 3, device="cuda")
+        R = M.Renderer(n, sc.max_bounces, with_hits=False)
+        opts = M.make_opts(sc, use_occupancy=True)
+
+        def step():
+            M.mr_rays_from_cameras(cams, o, d, None, n)
+            R.render(F, G, o, d, sc.lights, opts)
+        ms = timed(step, steps, 1)
+        info = G.info()
+        nodes = info["n_nodes"]
+        tris = len(sc.mesh.indices)
+        return {"rays": n, "triangles": tris, "bvh_depth": info["depth"], "ms_per_frame": round(ms, 3),
+                "rays_per_s": round(n / (ms / 1e3), 1), "bvh_build_s": round(build_s, 3),
+                "device_mib": round((nodes * 64 + tris * 48 + R.ws_bytes) / 2 ** 20, 1)}
+    out = {"spheres_900x450": {}, "pixels_at_100_spheres": {}}
+    for nb in (1, 10, 100, 1000, 10000):
+        out["spheres_900x450"][str(nb)] = run(sg.balls_scene(nb))
+    for w, h in ((225, 112), (450, 225), (900, 450), (1800, 900)):
+        out["pixels_at_100_spheres"][f"{w}x{h}"] = run(sg.balls_scene(100, w, h))
+    return out
+
+
 def multicam(M, sg, steps):
     """16 cameras of uneven size and bounce depth in one queue, replayed as a graph."""
     import numpy as np
@@ -483,6 +523,7 @@ def main():
         line["moving_field"] = moving_field(M, sg, sc, F, G, cams, n, args.steps)
         line["sample_shadows"] = sample_shadows(M, sg, sc, F, G, cams, n, args.steps)
         line["multicam_16_cameras"] = multicam(M, sg, 2)
+        line["scaling_spheres"] = scaling(M, sg, 3)
         line["cloth_refit"] = cloth(M, sg, args.cloth_frames, args.train_steps)
     if not args.no_cpu_baseline:
         oh = o.cpu().numpy()

@@ -468,6 +468,33 @@ def mid_scene(width=800, height=800, table_amp=1e-4, n_samples=256,
                  occupancy_res=occupancy_res, occupancy_thresh=0.01)
 
 
+def balls_mesh(n_balls, seed=66, radius=0.03, level=1):
+    """n seeded icospheres (level 1: 80 triangles) of one radius with centres
+    uniform in [-0.9, 0.9]^3, materials cycling glass, mirror, diffuse, over
+    the mid scene's diffuse floor (ball i has triangle ids 80 i .. 80 i + 79,
+    the floor comes last)."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(-0.9, 0.9, size=(n_balls, 3))
+    bv, bf = icosphere(level, radius=1.0)
+    V = (bv[None].astype(np.float64) * radius + centres[:, None, :]).reshape(-1, 3)
+    F = (bf[None] + (np.arange(n_balls) * len(bv))[:, None, None]).reshape(-1, 3)
+    M = np.repeat(np.arange(n_balls) % 3, len(bf))
+    pv, pf = floor_plane(-0.6)
+    mats = [[GLASS, 1.5, 1.0, 1.0, 1.0], [MIRROR, 1.0, 1.0, 1.0, 1.0], [DIFFUSE, 1.0, 0.7, 0.7, 0.7]]
+    return Mesh(vertices=np.concatenate([V, pv]).astype(np.float32),
+                indices=np.concatenate([F, pf + len(V)]).astype(np.int32),
+                mat_ids=np.concatenate([M, np.full(len(pf), 2)]).astype(np.int32),
+                materials=_materials(mats))
+
+
+def balls_scene(n_balls, width=900, height=450, seed=66) -> Scene:
+    """Scaling workload after the paper's App. A (1 .. 10^4 inserted balls at
+    900x450): the mid field and light with n_balls small spheres."""
+    return Scene(name=f"balls{n_balls}", field=mid_field(2), mesh=balls_mesh(n_balls, seed),
+                 lights=seeded_light(22), cameras=[front_camera(width, height, 8)], t_near=0.05,
+                 t_far=4.0, n_samples=256, max_bounces=8, occupancy_res=128, occupancy_thresh=0.01)
+
+
 def multicam_scene(seed=44) -> Scene:
     return Scene(name="multicam", field=tiny_field(1), mesh=mirror_cube_mesh(),
                  lights=no_lights(), cameras=multicam_cameras(seed), t_near=0.05,

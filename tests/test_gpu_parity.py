@@ -590,3 +590,14 @@ def test_sample_shadow_options_validated():
     with pytest.raises(M.MrError):
         R.render(F, G, dev(o), dev(d), sc.lights,
                  M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P, shadow_mask=0.2))
+
+
+def test_scaling_workload_small_matches_oracle():
+    """The App. A-style workload (many small inserted spheres) at 200 spheres
+    and 40x20: 16 002 triangles, glass, mirror and diffuse, 8 bounces."""
+    sc = sg.balls_scene(200, width=40, height=20)
+    o, d = oracle_camera_rays(sc)
+    r = orc.render(sc, o, d)
+    g = gpu_render(sc, o, d)
+    compare_render(g, r, "200 spheres 40x20")
+    assert (g["hit_ids"][:, 0] >= 0).mean() > 0.1

@@ -41,3 +41,16 @@ def test_seeded_draws_are_reproducible():
     total = sum(c.width * c.height for c in cams)
     assert 5e6 < total < 2e7
     assert max(c.max_bounces for c in cams) == 16
+
+
+def test_balls_mesh_layout():
+    """n spheres of 80 triangles each, then the 2 floor triangles; centres in
+    [-0.9, 0.9]^3, radius 0.03; materials cycle glass, mirror, diffuse."""
+    m = sg.balls_mesh(7, seed=3)
+    assert m.indices.shape == (7 * 80 + 2, 3) and m.indices.max() == len(m.vertices) - 1
+    assert list(m.mat_ids[::80][:7]) == [0, 1, 2, 0, 1, 2, 0] and list(m.mat_ids[-2:]) == [2, 2]
+    for i in range(7):
+        v = m.vertices[m.indices[80 * i:80 * (i + 1)].ravel()].astype(np.float64)
+        c = v.mean(axis=0)
+        assert np.all(np.abs(c) <= 0.9 + 1e-6)
+        np.testing.assert_allclose(np.linalg.norm(v - c, axis=1), 0.03, rtol=1e-4)
