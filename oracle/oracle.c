@@ -724,6 +724,10 @@ static void render_ray(const job_t* J, int64_t r) {
                    opt->sample_shadows && m && J->n_lights > 0 ? &sh : NULL);
     ++segs;
     if (hit < 0) break;                  /* escaped the scene: background is 0 */
+    {                                    /* Eq. 12: emitted radiance, attenuated by the segment */
+      const float* em = m->materials + 8 * m->mat_ids[hit] + 5;
+      for (int c = 0; c < 3; ++c) L[c] += T[c] * (double)em[c];
+    }
     if (s == mb) break;                  /* bounce limit: stop at the surface   */
     double v[3][3], e1[3], e2[3], n[3], p[3], nd[3], side[3];
     tri_verts(m, hit, v);
@@ -736,7 +740,7 @@ static void render_ray(const job_t* J, int64_t r) {
     double dn = dot3(d, n);
     double nf[3];                        /* normal on the side the ray came from */
     for (int k = 0; k < 3; ++k) nf[k] = dn < 0.0 ? n[k] : -n[k];
-    const float* mat = m->materials + 5 * m->mat_ids[hit];
+    const float* mat = m->materials + 8 * m->mat_ids[hit];
     int kind = (int)mat[0];
     if (kind == 2) {                     /* Lambertian: shadow ray to every light */
       for (int li = 0; li < J->n_lights; ++li) {

@@ -40,7 +40,7 @@ typedef struct {
   const int32_t* indices;    /* [nf][3] */
   const int32_t* mat_ids;    /* [nf]    */
   int32_t n_mat;
-  const float* materials;    /* [n_mat][5]: kind, ior, albedo rgb */
+  const float* materials;    /* [n_mat][8]: kind, ior, albedo rgb, emitted radiance rgb */
 } orc_mesh;
 
 typedef struct {

@@ -103,7 +103,7 @@ class Mesh:
     vertices: np.ndarray             # float32 [V, 3]
     indices: np.ndarray              # int32 [F, 3]
     mat_ids: np.ndarray              # int32 [F]
-    materials: np.ndarray            # float32 [M, 5]: kind, ior, albedo r, g, b
+    materials: np.ndarray            # float32 [M, 8]: kind, ior, albedo rgb, emitted radiance rgb
 
 
 @dataclasses.dataclass
@@ -237,7 +237,10 @@ def make_proposal(seed=5, n_levels=5, feats=2, log2_table=17, n_min=16, n_max=25
 # ----------------------------------------------------------------------------
 
 def _materials(rows):
-    return np.array(rows, dtype=np.float32).reshape(-1, 5)
+    """Material rows: kind, ior, albedo rgb, and optionally emitted radiance
+    rgb (linear HDR; zero when left out)."""
+    rows = [list(r) + [0.0] * (8 - len(r)) for r in rows]
+    return np.array(rows, dtype=np.float32).reshape(-1, 8)
 
 
 def cube_triangles(center, side):

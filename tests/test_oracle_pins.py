@@ -894,3 +894,51 @@ def test_sample_shadow_masks_multiply_over_lights():
         L += T * alpha * m
         T *= 1.0 - alpha
     np.testing.assert_allclose(r["radiance"][0], L, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# emitted radiance of surfaces (Eq. 12, L_e, with the segment's attenuation)
+# ---------------------------------------------------------------------------
+
+def _emitter_quad(z=0.5, half=0.6, le=(4.0, 2.0, 1.0), kind=sg.DIFFUSE, albedo=0.0):
+    v = np.array([[-half, -half, z], [half, -half, z], [half, half, z], [-half, half, z]], np.float32)
+    f = np.array([[0, 1, 2], [0, 2, 3]], np.int32)
+    return v, f, [kind, 1.0, albedo, albedo, albedo, *le]
+
+
+def test_emitter_seen_directly_and_through_a_constant_medium():
+    """A black diffuse quad at z = 0.5 emitting (4, 2, 1): through empty
+    space the camera ray collects exactly L_e; through the constant medium
+    (sigma = softplus(1), colour 1) it collects (1 - T) + T L_e with T the
+    transmittance of the chord in front of the quad."""
+    v, f, mat = _emitter_quad()
+    mesh = sg.merge_meshes([(v, f, 0)], [mat])
+    o = np.array([[0.05, 0.02, -2.5]], np.float32)
+    d = np.array([[0.0, 0.0, 1.0]], np.float32)
+    empty = orc.render(_scene(None, mesh), o, d)
+    np.testing.assert_allclose(empty["radiance"][0], [4.0, 2.0, 1.0], rtol=1e-15)
+    assert empty["bounces"][0] == 1 and np.all(empty["throughput"][0] == 0)
+    f0 = _constant_field()
+    sigma = math.log1p(math.e)
+    fog = orc.render(_scene(f0, mesh), o, d)
+    T = math.exp(-sigma * 1.5)                     # the box from z = -1 to the quad at z = 0.5
+    np.testing.assert_allclose(fog["radiance"][0], (1 - T) + T * np.array([4.0, 2.0, 1.0]), rtol=1e-12)
+
+
+def test_emitter_seen_through_a_mirror_and_at_the_bounce_limit():
+    """A mirror turns the camera ray onto the emitter (weight 1): L = L_e;
+    with max_bounces = 0 a camera ray that stops on the emitter still
+    collects its L_e."""
+    v, f, mat = _emitter_quad(z=-1.5, le=(3.0, 3.0, 3.0))
+    mv = np.array([[-0.7, -0.7, 0.8], [0.7, -0.7, 0.8], [0.7, 0.7, 0.8], [-0.7, 0.7, 0.8]], np.float32)
+    mesh = sg.merge_meshes([(v, f, 0), (mv, f, 1)], [mat, [sg.MIRROR, 1.0, 1.0, 1.0, 1.0]])
+    o = np.array([[0.05, 0.02, -1.0]], np.float32)
+    d = np.array([[0.0, 0.0, 1.0]], np.float32)
+    r = orc.render(_scene(None, mesh), o, d)
+    np.testing.assert_allclose(r["radiance"][0], 3.0, rtol=1e-15)
+    assert r["bounces"][0] == 2
+    v2, f2, mat2 = _emitter_quad()
+    direct = orc.render(_scene(None, sg.merge_meshes([(v2, f2, 0)], [mat2]), max_bounces=0),
+                        np.array([[0.05, 0.02, -2.5]], np.float32), d)
+    np.testing.assert_allclose(direct["radiance"][0], [4.0, 2.0, 1.0], rtol=1e-15)
+    assert direct["bounces"][0] == 0
