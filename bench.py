@@ -302,6 +302,28 @@ def scaling(M, sg, steps):
     return out
 
 
+def emitters(M, sg, steps):
+    """The mid workload with an emitting ceiling panel (Eq. 12 L_e) next to the
+    point light: 800x800, 8 bounces, plain FP32."""
+    import torch
+    sc = sg.emitter_scene()
+    cams = sg.cameras_array(sc.cameras)
+    n = sc.n_rays
+    F, G = M.Field(sc.field), M.Mesh(sc.mesh)
+    F.build_occupancy(sc.occupancy_res, sc.occupancy_thresh)
+    o = torch.empty(n, 3, device="cuda")
+    d = torch.empty(n, 3, device="cuda")
+    R = M.Renderer(n, sc.max_bounces, with_hits=False)
+    opts = M.make_opts(sc, use_occupancy=True)
+
+    def step():
+        M.mr_rays_from_cameras(cams, o, d, None, n)
+        R.render(F, G, o, d, sc.lights, opts)
+    ms = timed(step, steps, 1)
+    return {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms, 3),
+            "mean_radiance": [round(float(x), 5) for x in R.radiance.mean(0).cpu().numpy()]}
+
+
 def multicam(M, sg, steps):
     """16 cameras of uneven size and bounce depth in one queue, replayed as a graph."""
     import numpy as np
@@ -522,6 +544,7 @@ def main():
         line["precision_tiny_vs_fp64_oracle"] = precision_report(M, sg)
         line["moving_field"] = moving_field(M, sg, sc, F, G, cams, n, args.steps)
         line["sample_shadows"] = sample_shadows(M, sg, sc, F, G, cams, n, args.steps)
+        line["emitters"] = emitters(M, sg, args.steps)
         line["multicam_16_cameras"] = multicam(M, sg, 2)
         line["scaling_spheres"] = scaling(M, sg, 3)
         line["cloth_refit"] = cloth(M, sg, args.cloth_frames, args.train_steps)

@@ -135,9 +135,12 @@ mr_status mr_field_params(mr_field* f, void** table, float** mlp, int64_t* n_tab
 /* of Sec. 3.1 "Surface Rendering Equation"; ray casting t(p, w), Eq. 3).   */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-  int32_t kind;    /* MR_MIRROR | MR_GLASS | MR_DIFFUSE */
-  float ior;       /* glass index of refraction (> 1) */
-  float albedo[3]; /* diffuse reflectance in [0, 1] */
+  int32_t kind;      /* MR_MIRROR | MR_GLASS | MR_DIFFUSE */
+  float ior;         /* glass index of refraction (> 1) */
+  float albedo[3];   /* diffuse reflectance in [0, 1] */
+  float emission[3]; /* emitted radiance L_e (linear HDR, >= 0; Eq. 12): every hit adds
+                        T L_e with the throughput attenuated by the segment, also when
+                        the ray stops there at its bounce limit */
 } mr_material;
 
 typedef struct mr_mesh mr_mesh;

@@ -243,6 +243,9 @@ extern "C" mr_status mr_mesh_build_bvh(const float* host_vertices, int32_t nv, c
       return fail(MR_ERR_INVALID_ARG, "glass ior must be finite and > 1");
     for (int c = 0; c < 3; ++c)
       if (!(mt.albedo[c] >= 0.0f && mt.albedo[c] <= 1.0f)) return fail(MR_ERR_INVALID_ARG, "albedo outside [0, 1]");
+    for (int c = 0; c < 3; ++c)
+      if (!(mt.emission[c] >= 0.0f && std::isfinite(mt.emission[c])))
+        return fail(MR_ERR_INVALID_ARG, "emission must be finite and >= 0");
   }
   for (int64_t i = 0; i < 3LL * nv; ++i)
     if (!std::isfinite(host_vertices[i])) return fail(MR_ERR_INVALID_ARG, "non-finite vertex");
@@ -366,10 +369,15 @@ extern "C" mr_status mr_mesh_build_bvh(const float* host_vertices, int32_t nv, c
   m->view.bvh.tris = m->tris_dev;
   m->view.bvh.n_prims = nf;
   m->view.n_mat = n_materials;
+  m->view.emissive = 0;
   for (int i = 0; i < n_materials; ++i) {
     m->view.mat[i].kind = host_materials[i].kind;
     m->view.mat[i].ior = host_materials[i].ior;
-    for (int c = 0; c < 3; ++c) m->view.mat[i].albedo[c] = host_materials[i].albedo[c];
+    for (int c = 0; c < 3; ++c) {
+      m->view.mat[i].albedo[c] = host_materials[i].albedo[c];
+      m->view.mat[i].emission[c] = host_materials[i].emission[c];
+      if (host_materials[i].emission[c] > 0.0f) m->view.emissive = 1;
+    }
   }
   *out = m;
   return MR_OK;

@@ -92,7 +92,7 @@ __device__ __forceinline__ float sample_shadow(const FieldView& F, const BvhView
 
 // One ray per wave: lane j takes sample kb + j of each 16-sample tile, and
 // transmittance is a 16-lane prefix product carried from tile to tile.
-template <int NL, int SH, int CL, typename TabT, bool BF>
+template <int NL, int SH, int CL, typename TabT, bool BF, bool SHADOW>
 __device__ __forceinline__ void march_ray(const RayQueue& q, int r, const FieldView& F, const TabT* __restrict__ table,
                                           const uint32_t* __restrict__ sW, const MarchParams& P, const BvhView& B,
                                           int* sstack, bool use_occ, int lane, unsigned long long& nsamp) {
@@ -131,7 +131,8 @@ __device__ __forceinline__ void march_ray(const RayQueue& q, int r, const FieldV
     const float incl = scan16_mul(1.0f - alpha, j);
     float excl = __shfl_up(incl, 1, 16);
     if (j == 0) excl = 1.0f;
-    const float msk = P.shadows ? sample_shadow(F, B, P, valid, px, py, pz, lane, sstack) : 1.0f;
+    float msk = 1.0f;
+    if constexpr (SHADOW) msk = sample_shadow(F, B, P, valid, px, py, pz, lane, sstack);
     const float w = Tseg * excl * alpha * msk;
     acc0 += w * rgb[0];
     acc1 += w * rgb[1];
@@ -177,7 +178,7 @@ __device__ __forceinline__ PacketRay packet_ray(const RayQueue& q, int r, int cn
 // A packet of 16 rays stepped through the same sample index together:
 // column j of every tile is ray j at sample k, composited by a running
 // product per column.
-template <int NL, int SH, int CL, typename TabT, bool BF>
+template <int NL, int SH, int CL, typename TabT, bool BF, bool SHADOW>
 __device__ __forceinline__ void march_packet(const RayQueue& q, const PacketRay& R, const FieldView& F,
                                              const TabT* __restrict__ table, const uint32_t* __restrict__ sW,
                                              const MarchParams& P, const BvhView& B, int* sstack, bool use_occ,
@@ -228,7 +229,8 @@ __device__ __forceinline__ void march_packet(const RayQueue& q, const PacketRay&
     f4v raw;
     mlp_tile<NL, SH, CL, BF>(sW, fe, u, F.density_offset, lane, sigma, rgb, raw);
     const float alpha = valid ? -expm1f(-sigma * D) : 0.0f;
-    const float msk = P.shadows ? sample_shadow(F, B, P, valid, px, py, pz, lane, sstack) : 1.0f;
+    float msk = 1.0f;
+    if constexpr (SHADOW) msk = sample_shadow(F, B, P, valid, px, py, pz, lane, sstack);
     const float w = T * alpha * msk;
     acc0 += w * rgb[0];
     acc1 += w * rgb[1];
@@ -248,7 +250,9 @@ __device__ __forceinline__ void march_packet(const RayQueue& q, const PacketRay&
 }
 
 // PK: 16-ray packets (march_packet), else one ray per wave (march_ray).
-template <int NL, int SH, int CL, typename TabT, bool BF, bool PK>
+// SHADOW: the shadow mask per field sample (instances without it carry none
+// of its code or registers).
+template <int NL, int SH, int CL, typename TabT, bool BF, bool PK, bool SHADOW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_march_mfma(
     RayQueue q, const int* __restrict__ count, int* __restrict__ work, FieldView F, const TabT* __restrict__ table,
     const uint32_t* __restrict__ frags, MarchParams P, BvhView B, unsigned long long* __restrict__ stats) {
@@ -268,13 +272,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       for (int bi = 0; bi < wq.batch; ++bi) {
         const int r = wq.map(base + bi);
         if (r >= cnt) break;
-        march_ray<NL, SH, CL, TabT, BF>(q, r, F, table, sW, P, B, stack, use_occ, lane, nsamp);
+        march_ray<NL, SH, CL, TabT, BF, SHADOW>(q, r, F, table, sW, P, B, stack, use_occ, lane, nsamp);
       }
   } else {
     WorkQueue wq(work, cnt, P.chunk, 16);
     for (int base = wq.next(lane); base >= 0; base = wq.next(lane)) {
       const PacketRay R = packet_ray(q, wq.map(base + j), cnt, F);
-      march_packet<NL, SH, CL, TabT, BF>(q, R, F, table, sW, P, B, stack, use_occ, lane, nsamp);
+      march_packet<NL, SH, CL, TabT, BF, SHADOW>(q, R, F, table, sW, P, B, stack, use_occ, lane, nsamp);
     }
   }
   if (stats) {
@@ -330,12 +334,12 @@ __global__ __launch_bounds__(256) void k_query_mfma(FieldView F, const TabT* __r
   }
 }
 
-template <int NL, int SH, int CL, typename TabT, bool BF, bool PK>
+template <int NL, int SH, int CL, typename TabT, bool BF, bool PK, bool SHADOW>
 mr_status launch_march_mode(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
                             const BvhView& B, unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st) {
   const uint32_t* fr = BF ? f->frag_bf16_dev : f->frag_f32_dev;
   const TabT* tab = reinterpret_cast<const TabT*>(f->table_dev);
-  auto* k = k_march_mfma<NL, SH, CL, TabT, BF, PK>;
+  auto* k = k_march_mfma<NL, SH, CL, TabT, BF, PK, SHADOW>;
   const int64_t cap = PK ? (n + 63) / 64 : (n + 3) / 4;
   const int blocks = persistent_blocks(reinterpret_cast<const void*>(k), 256, blocks_per_cu, cap);
   hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, q, count, work, f->view, tab, fr, P, B, stats);
@@ -347,9 +351,14 @@ template <int NL, int SH, int CL, typename TabT, bool BF>
 mr_status launch_march_mfma(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
                             const BvhView& B, bool packets, unsigned long long* stats, int blocks_per_cu, int64_t n,
                             hipStream_t st) {
+  if (P.shadows) {
+    if (packets)
+      return launch_march_mode<NL, SH, CL, TabT, BF, true, true>(f, q, count, work, P, B, stats, blocks_per_cu, n, st);
+    return launch_march_mode<NL, SH, CL, TabT, BF, false, true>(f, q, count, work, P, B, stats, blocks_per_cu, n, st);
+  }
   if (packets)
-    return launch_march_mode<NL, SH, CL, TabT, BF, true>(f, q, count, work, P, B, stats, blocks_per_cu, n, st);
-  return launch_march_mode<NL, SH, CL, TabT, BF, false>(f, q, count, work, P, B, stats, blocks_per_cu, n, st);
+    return launch_march_mode<NL, SH, CL, TabT, BF, true, false>(f, q, count, work, P, B, stats, blocks_per_cu, n, st);
+  return launch_march_mode<NL, SH, CL, TabT, BF, false, false>(f, q, count, work, P, B, stats, blocks_per_cu, n, st);
 }
 
 template <int NL, int SH, int CL, typename TabT, bool BF>

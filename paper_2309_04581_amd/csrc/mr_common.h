@@ -70,6 +70,7 @@ struct Material {
   int kind;
   float ior;
   float albedo[3];
+  float emission[3];
 };
 
 struct BvhView {
@@ -81,6 +82,7 @@ struct BvhView {
 struct MeshView {
   BvhView bvh;
   int n_mat;
+  int emissive;        // some material emits (hits then read their material even at the bounce limit)
   Material mat[kMaxMaterials];
 };
 

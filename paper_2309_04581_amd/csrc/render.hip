@@ -183,6 +183,13 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade(RayQueue qi, const int* _
       const int p = qi.hit_p[i];
       tr = qi.tr[i]; tg = qi.tg[i]; tb = qi.tb[i];
       lr = qi.lr[i]; lg = qi.lg[i]; lb = qi.lb[i];
+      if (p >= 0 && M.emissive) {
+        // Eq. 12: emitted radiance at the hit, attenuated by the marched segment
+        const Material& em = M.mat[__float_as_int(M.bvh.tris[3 * p + 1].w)];
+        lr += tr * em.emission[0];
+        lg += tg * em.emission[1];
+        lb += tb * em.emission[2];
+      }
       if (p < 0 || seg >= mb) {
         finalize(out, rid, tr, tg, tb, lr, lg, lb, seg);
       } else {

@@ -50,7 +50,8 @@ class FieldDesc(C.Structure):
 
 
 class Material(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("ior", C.c_float), ("albedo", C.c_float * 3)]
+    _fields_ = [("kind", C.c_int32), ("ior", C.c_float), ("albedo", C.c_float * 3),
+                ("emission", C.c_float * 3)]
 
 
 class Light(C.Structure):
@@ -168,6 +169,7 @@ def mr_mesh_build_bvh(vertices, indices, mat_ids, materials, stream=None):
         mats[i].kind = int(row[0])
         mats[i].ior = float(row[1])
         mats[i].albedo = (C.c_float * 3)(*[float(x) for x in row[2:5]])
+        mats[i].emission = (C.c_float * 3)(*[float(x) for x in (list(row[5:8]) + [0.0] * 3)[:3]])
     h = C.c_void_p()
     _check(lib().mr_mesh_build_bvh(_ptr(v), C.c_int32(len(v)), _ptr(f), C.c_int32(len(f)), _ptr(m),
                                    mats, C.c_int32(len(materials)), _stream(stream), C.byref(h)))

@@ -498,6 +498,28 @@ def balls_scene(n_balls, width=900, height=450, seed=66) -> Scene:
                  t_far=4.0, n_samples=256, max_bounces=8, occupancy_res=128, occupancy_thresh=0.01)
 
 
+def emitter_quad(y=0.95, half=0.4, radiance=(5.0, 5.0, 5.0)):
+    """A black diffuse quad facing down at height y that emits radiance (an
+    area light made of two triangles)."""
+    v = np.array([[-half, y, -half], [half, y, -half], [half, y, half], [-half, y, half]], dtype=np.float32)
+    f = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)
+    return v, f, [DIFFUSE, 1.0, 0.0, 0.0, 0.0, *radiance]
+
+
+def emitter_scene(width=800, height=800) -> Scene:
+    """The mid scene with an emitting ceiling panel (Eq. 12 L_e): glass
+    sphere, mirror cube and floor as in the mid scene, the panel last."""
+    sv, sf = icosphere(5, radius=0.35, center=(-0.4, -0.24, 0.0))
+    cv, cf = cube_triangles((0.45, -0.35, 0.1), 0.5)
+    pv, pf = floor_plane(-0.6)
+    ev, ef, em = emitter_quad()
+    mats = [[GLASS, 1.5, 1.0, 1.0, 1.0], [MIRROR, 1.0, 1.0, 1.0, 1.0], [DIFFUSE, 1.0, 0.7, 0.7, 0.7], em]
+    mesh = merge_meshes([(sv, sf, 0), (cv, cf, 1), (pv, pf, 2), (ev, ef, 3)], mats)
+    return Scene(name="emitter", field=mid_field(2), mesh=mesh, lights=seeded_light(22),
+                 cameras=[front_camera(width, height, 8)], t_near=0.05, t_far=4.0, n_samples=256,
+                 max_bounces=8, occupancy_res=128, occupancy_thresh=0.01)
+
+
 def multicam_scene(seed=44) -> Scene:
     return Scene(name="multicam", field=tiny_field(1), mesh=mirror_cube_mesh(),
                  lights=no_lights(), cameras=multicam_cameras(seed), t_near=0.05,

@@ -601,3 +601,31 @@ def test_scaling_workload_small_matches_oracle():
     g = gpu_render(sc, o, d)
     compare_render(g, r, "200 spheres 40x20")
     assert (g["hit_ids"][:, 0] >= 0).mean() > 0.1
+
+
+# ---------------------------------------------------------------------------
+# emitted radiance of surfaces (Eq. 12 L_e)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("packets", PACKETS)
+def test_emitters_match_oracle(packets):
+    """Tiny scene with an emitting quad behind the mirror cube (seen directly
+    and in the cube's faces): hit ids exact, radiance within 1e-4."""
+    sc = sg.tiny_scene()
+    v = np.array([[-0.9, -0.9, 0.9], [0.9, -0.9, 0.9], [0.9, 0.9, 0.9], [-0.9, 0.9, 0.9]], np.float32)
+    f = np.array([[0, 1, 2], [0, 2, 3]], np.int32)
+    cv, cf = sg.cube_triangles((0.0, 0.0, 0.0), 0.5)
+    sc.mesh = sg.merge_meshes([(cv, cf, 0), (v, f, 1)], [[sg.MIRROR, 1.0, 1.0, 1.0, 1.0],
+                                                          [sg.DIFFUSE, 1.0, 0.2, 0.2, 0.2, 3.0, 2.0, 1.0]])
+    o, d = oracle_camera_rays(sc)
+    r = orc.render(sc, o, d)
+    assert (r["radiance"][:, 0] > 1.0).mean() > 0.2
+    compare_render(gpu_render(sc, o, d, packets=packets), r, f"emitters packets={packets}")
+
+
+def test_emitter_scene_small_image_matches_oracle():
+    """The mid scene with its emitting ceiling panel at 32x24."""
+    sc = sg.emitter_scene(width=32, height=24)
+    o, d = oracle_camera_rays(sc)
+    r = orc.render(sc, o, d)
+    compare_render(gpu_render(sc, o, d), r, "emitter scene 32x24")
