@@ -46,7 +46,7 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 
 static double u01(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
 
-enum { RNG_GLASS = 0, RNG_DIFFUSE = 1, RNG_RR = 2 };
+enum { RNG_GLASS = 0, RNG_DIFFUSE = 1, RNG_RR = 2, RNG_EMITTER = 3 };
 
 static void draw(uint32_t seed, int64_t ray, int seg, int purpose, double u[4]) {
   uint32_t ctr[4] = {(uint32_t)ray, (uint32_t)seg, (uint32_t)purpose, 0u};
@@ -680,6 +680,71 @@ double orc_fresnel(double cos_i, double eta_i, double eta_t) {
   return fresnel(cos_i, eta_i, eta_t, &ct);
 }
 
+static int near_rel(double a, double b, double eps) {
+  return fabs(a - b) <= eps * fmax(fabs(b), 1e-30);
+}
+
+/* Light sampling toward emitting triangles (Eq. 12's L_e read as area
+ * lights; the paper estimates light sources but sets out no sampling rule).
+ * Reading: triangle k of the emitters (faces whose material emits, in face
+ * order) is chosen with probability p_k = w_k / W, w_k = sum of its emitted
+ * radiance over the three channels (not its power, so the choice does not
+ * change when a mesh deforms), by the first k with u0 W < w_0 + ... + w_k; on
+ * it the point x = (1 - s) v0 + s (1 - u2) v1 + s u2 v2, s = sqrt(u1), is
+ * uniform by area (pdf 1 / A_k).  The estimate of the light reflected by a
+ * Lambertian point p with normal nf is
+ *     (albedo / pi) L_e cos_p cos_x / |x - p|^2 * A_k / p_k,
+ * cos_p = nf . l, cos_x = |n_k . l| (emitters are two-sided, as the L_e term
+ * is added on either side), zero when either cosine is not positive or a
+ * mesh lies between: a ray from p + 1e-4 nf toward x finds a triangle before
+ * (1 - 1e-3) of the way.  As for the point lights, the shadow ray sees meshes
+ * only.  Returns the tie flag of the choice and the shadow ray in *tie. */
+static void emitter_sample(const orc_mesh* m, const double p[3], const double nf[3], const float* mat,
+                           const double u[4], double tie_eps, double tie_rel, double L_add[3], int* tie) {
+  for (int c = 0; c < 3; ++c) L_add[c] = 0.0;
+  double W = 0.0;
+  for (int i = 0; i < m->nf; ++i) {
+    const float* em = m->materials + 8 * m->mat_ids[i] + 5;
+    W += (double)em[0] + (double)em[1] + (double)em[2];
+  }
+  if (!(W > 0.0)) return;
+  double target = u[0] * W, cum = 0.0;
+  int k = -1;
+  double wk = 0.0;
+  for (int i = 0; i < m->nf; ++i) {
+    const float* em = m->materials + 8 * m->mat_ids[i] + 5;
+    double w = (double)em[0] + (double)em[1] + (double)em[2];
+    if (!(w > 0.0)) continue;
+    if (near_rel(target, cum, tie_rel) && cum > 0.0) *tie = 1;
+    cum += w;
+    if (k < 0 && target < cum) { k = i; wk = w; }
+    if (near_rel(target, cum, tie_rel) && cum < W) *tie = 1;
+  }
+  if (k < 0) return;                     /* u0 < 1 always finds one; kept for safety */
+  double v[3][3], e1[3], e2[3], nk[3], x[3], wi[3], l[3];
+  tri_verts(m, k, v);
+  double s = sqrt(u[1]);
+  for (int j = 0; j < 3; ++j) x[j] = (1.0 - s) * v[0][j] + s * (1.0 - u[2]) * v[1][j] + s * u[2] * v[2][j];
+  sub3(v[1], v[0], e1);
+  sub3(v[2], v[0], e2);
+  cross3(e1, e2, nk);
+  double a2 = sqrt(dot3(nk, nk));       /* twice the area */
+  sub3(x, p, wi);
+  double d2 = dot3(wi, wi), dist = sqrt(d2);
+  for (int j = 0; j < 3; ++j) l[j] = wi[j] / dist;
+  double cos_p = dot3(nf, l), cos_x = fabs(dot3(nk, l)) / a2;
+  if (!(cos_p > 0.0) || !(cos_x > 0.0)) return;
+  double so[3], sd[3];
+  for (int j = 0; j < 3; ++j) so[j] = p[j] + 1e-4 * nf[j];
+  sub3(x, so, sd);
+  double sdist = sqrt(dot3(sd, sd));
+  for (int j = 0; j < 3; ++j) sd[j] /= sdist;
+  if (any_hit(m, so, sd, (1.0 - 1e-3) * sdist, tie_eps, tie)) return;
+  const float* em = m->materials + 8 * m->mat_ids[k] + 5;
+  double g = cos_p * cos_x / d2 * (0.5 * a2) * (W / wk) / PI;
+  for (int c = 0; c < 3; ++c) L_add[c] = (double)mat[2 + c] * (double)em[c] * g;
+}
+
 typedef struct {
   const orc_field* f;
   const orc_mesh* m;
@@ -694,10 +759,6 @@ typedef struct {
   int64_t begin, end;
 } job_t;
 
-static int near_rel(double a, double b, double eps) {
-  return fabs(a - b) <= eps * fmax(fabs(b), 1e-30);
-}
-
 static void render_ray(const job_t* J, int64_t r) {
   const orc_opts* opt = J->opt;
   const orc_mesh* m = J->m;
@@ -705,7 +766,7 @@ static void render_ray(const job_t* J, int64_t r) {
   int64_t rid = J->ray_ids ? J->ray_ids[r] : r;
   double o[3], d[3], T[3] = {1, 1, 1}, L[3] = {0, 0, 0};
   for (int k = 0; k < 3; ++k) { o[k] = J->origins[3 * r + k]; d[k] = J->dirs[3 * r + k]; }
-  int nscat = 0, tie = 0, segs = 0;
+  int nscat = 0, tie = 0, segs = 0, after_diffuse = 0;
   int64_t nsamp = 0;
   int stride = opt->max_bounces + 1;
   if (J->out->hit_ids)
@@ -724,7 +785,7 @@ static void render_ray(const job_t* J, int64_t r) {
                    opt->sample_shadows && m && J->n_lights > 0 ? &sh : NULL);
     ++segs;
     if (hit < 0) break;                  /* escaped the scene: background is 0 */
-    {                                    /* Eq. 12: emitted radiance, attenuated by the segment */
+    if (!(opt->sample_emitters && after_diffuse)) {   /* Eq. 12: emitted radiance, attenuated by the segment */
       const float* em = m->materials + 8 * m->mat_ids[hit] + 5;
       for (int c = 0; c < 3; ++c) L[c] += T[c] * (double)em[c];
     }
@@ -760,7 +821,14 @@ static void render_ray(const job_t* J, int64_t r) {
         if (blocked) continue;
         for (int c = 0; c < 3; ++c) L[c] += T[c] * ((double)mat[2 + c] / PI) * lt[3 + c] * cosl / d2;
       }
+      if (opt->sample_emitters) {        /* one light sample on the emitting triangles */
+        double ue[4], Le[3];
+        draw(opt->seed, rid, s, RNG_EMITTER, ue);
+        emitter_sample(m, p, nf, mat, ue, opt->tie_eps, opt->tie_rel, Le, &tie);
+        for (int c = 0; c < 3; ++c) L[c] += T[c] * Le[c];
+      }
     }
+    after_diffuse = kind == 2;
     double u[4];
     draw(opt->seed, rid, s, kind == 1 ? RNG_GLASS : RNG_DIFFUSE, u);
     double wgt[3], R = -1.0;

@@ -64,6 +64,12 @@ typedef struct {
    * sample's emitted radiance by shadow_mask */
   int32_t sample_shadows;
   double shadow_mask;
+  /* optional light sampling toward emitting triangles (Eq. 12's L_e read as
+   * area lights): at every diffuse hit one point on one emitting triangle,
+   * chosen with probability proportional to its summed emitted radiance and
+   * uniformly by area on it; a path that reaches an emitter straight after a
+   * diffuse scatter then adds no L_e there (the light sample stands for it) */
+  int32_t sample_emitters;
 } orc_opts;
 
 typedef struct {

@@ -51,7 +51,8 @@ class _Opts(C.Structure):
                 ("tie_eps", C.c_double), ("tie_rel", C.c_double),
                 ("occ_res", C.c_int32), ("occ", C.c_void_p),
                 ("proposal", C.c_void_p), ("n_prop", C.c_int32), ("n_fine", C.c_int32),
-                ("sample_shadows", C.c_int32), ("shadow_mask", C.c_double)]
+                ("sample_shadows", C.c_int32), ("shadow_mask", C.c_double),
+                ("sample_emitters", C.c_int32)]
 
 
 class _Out(C.Structure):
@@ -213,12 +214,14 @@ def occupancy(field, res, thresh, n_threads=None):
 
 def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
            tie_eps=1e-5, tie_rel=1e-4, occupancy_bits=None, proposal=None, n_prop=32,
-           n_fine=32, field=..., mesh=..., shadow_mask=None):
+           n_fine=32, field=..., mesh=..., shadow_mask=None, sample_emitters=False):
     """Render FP32 input rays through the whole path in FP64.
 
     shadow_mask: None = no per-sample shadows; else every field sample that a
     mesh hides from a light has its emitted radiance multiplied by this value
     once per such light (Sec. 3.1 "Shadow rays").
+    sample_emitters: light sampling toward emitting triangles at diffuse hits
+    (Eq. 12's L_e as area lights).
 
     Returns a dict with radiance, throughput, bounces, hit_ids (segments),
     tie flags, per-ray sample and segment counts.
@@ -252,6 +255,7 @@ def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
         opt.n_prop, opt.n_fine = int(n_prop), int(n_fine)
     if shadow_mask is not None:
         opt.sample_shadows, opt.shadow_mask = 1, float(shadow_mask)
+    opt.sample_emitters = 1 if sample_emitters else 0
     res = dict(radiance=np.zeros((n, 3)), throughput=np.zeros((n, 3)),
                bounces=np.zeros(n, dtype=np.int32),
                hit_ids=np.full((n, gmax + 1), -1, dtype=np.int32),
