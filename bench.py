@@ -144,7 +144,16 @@ def proposal_variant(M, sg, sc, F_plain, G, cams, n, plain_img, steps, warmup, t
         R.render(F16, G, o, d, sc.lights, opts)
     ms = timed(step, steps, warmup)
     img = R.radiance.cpu().numpy()
+    # the same trained proposal with the per-sample shadow mask (0.2)
+    opts_sh = M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P, use_occupancy=True, shadow_mask=0.2)
+
+    def step_sh():
+        M.mr_rays_from_cameras(cams, o, d, None, n)
+        R.render(F16, G, o, d, sc.lights, opts_sh)
+    ms_sh = timed(step_sh, steps, 1)
     return {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms, 3),
+            "with_sample_shadows": {"value": round(n / (ms_sh / 1e3), 1), "unit": "rays/s",
+                                    "ms_per_step": round(ms_sh, 3), "mask": 0.2},
             "psnr_db_vs_plain_fp32": round(psnr_tonemapped(img, plain_img), 2),
             "samples": "32 proposal + 32 fine per segment", "table": "fp16", "mlp": "bf16 (MFMA, fp32 accumulate)",
             "train": {"steps": train_steps, "batch_segments": 1 << 14, "loss_first": float(hist[0]),
@@ -320,8 +329,18 @@ def emitters(M, sg, steps):
         M.mr_rays_from_cameras(cams, o, d, None, n)
         R.render(F, G, o, d, sc.lights, opts)
     ms = timed(step, steps, 1)
-    return {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms, 3),
-            "mean_radiance": [round(float(x), 5) for x in R.radiance.mean(0).cpu().numpy()]}
+    mean = [round(float(x), 5) for x in R.radiance.mean(0).cpu().numpy()]
+    # light sampling toward the panel's triangles at every diffuse hit
+    opts_ls = M.make_opts(sc, use_occupancy=True, sample_emitters=True)
+
+    def step_ls():
+        M.mr_rays_from_cameras(cams, o, d, None, n)
+        R.render(F, G, o, d, sc.lights, opts_ls)
+    ms_ls = timed(step_ls, steps, 1)
+    return {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms, 3), "mean_radiance": mean,
+            "with_light_sampling": {"value": round(n / (ms_ls / 1e3), 1), "unit": "rays/s",
+                                    "ms_per_step": round(ms_ls, 3),
+                                    "mean_radiance": [round(float(x), 5) for x in R.radiance.mean(0).cpu().numpy()]}}
 
 
 def multicam(M, sg, steps):

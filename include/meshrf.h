@@ -216,10 +216,18 @@ typedef struct {
                                    rays"): a ray from each sample to each light, and
                                    every light a mesh hides multiplies the sample's
                                    emitted radiance by shadow_mask (transmittance is
-                                   unchanged); uniform sampler only (MR_ERR_UNSUPPORTED
-                                   with the proposal sampler) */
+                                   unchanged); both samplers */
   float shadow_mask;            /* mask value of a hidden sample, in [0, 1] (the paper's
                                    1 - r_src, or a constant near 0) */
+  int32_t sample_emitters;      /* 1: light sampling toward emitting triangles (Eq. 12's
+                                   L_e as area lights): at each diffuse hit one point on one
+                                   emitting triangle, the triangle chosen with probability
+                                   proportional to its summed emitted radiance and the point
+                                   uniform by area; a mesh-only shadow ray to 0.999 of the
+                                   way; the estimate (albedo/pi) L_e cos_p cos_x / d^2 A / p
+                                   (emitters two-sided).  A path that reaches an emitter
+                                   straight after a diffuse scatter then adds no L_e there.
+                                   0: emission only where paths reach it */
 } mr_render_opts;
 
 /* One launch shape (the launch fields of mr_render_opts). */

@@ -363,8 +363,34 @@ extern "C" mr_status mr_mesh_build_bvh(const float* host_vertices, int32_t nv, c
   ok = ok && hipMemcpyAsync(m->prim_idx_dev, pidx.data(), pidx.size() * sizeof(int4), hipMemcpyHostToDevice, st) == hipSuccess;
   if (!refit.empty())
     ok = ok && hipMemcpyAsync(m->refit_nodes_dev, refit.data(), refit.size() * sizeof(int), hipMemcpyHostToDevice, st) == hipSuccess;
+  // emitting triangles in face order, chosen by summed emitted radiance
+  std::vector<int> leaf_of(std::max(nf, 1), -1);
+  for (int p = 0; p < nf; ++p) leaf_of[B.ids[p]] = p;
+  std::vector<float4> emit;
+  double wsum = 0.0;
+  for (int i = 0; i < nf; ++i) {
+    const float* e = host_materials[host_mat_ids[i]].emission;
+    wsum += (double)e[0] + (double)e[1] + (double)e[2];
+  }
+  if (wsum > 0.0) {
+    double cum = 0.0;
+    for (int i = 0; i < nf; ++i) {
+      const float* e = host_materials[host_mat_ids[i]].emission;
+      const double w = (double)e[0] + (double)e[1] + (double)e[2];
+      if (!(w > 0.0)) continue;
+      cum += w;
+      float leafbits;
+      std::memcpy(&leafbits, &leaf_of[i], 4);
+      emit.push_back(make_float4((float)(cum / wsum), (float)(w / wsum), leafbits, 0.0f));
+    }
+    emit.back().x = 1.0f;
+    if (hipMalloc(&m->emit_dev, emit.size() * sizeof(float4)) != hipSuccess) return cleanup(MR_ERR_OOM, "emitter alloc");
+    ok = ok && hipMemcpyAsync(m->emit_dev, emit.data(), emit.size() * sizeof(float4), hipMemcpyHostToDevice, st) == hipSuccess;
+  }
   ok = ok && hipStreamSynchronize(st) == hipSuccess;
   if (!ok) return cleanup(MR_ERR_DEVICE, "bvh upload");
+  m->view.emit = m->emit_dev;
+  m->view.n_emit = (int)emit.size();
   m->view.bvh.nodes = m->nodes_dev;
   m->view.bvh.tris = m->tris_dev;
   m->view.bvh.n_prims = nf;
@@ -407,6 +433,7 @@ extern "C" mr_status mr_mesh_destroy(mr_mesh* m) {
   if (m->nodes_dev) (void)hipFree(m->nodes_dev);
   if (m->tris_dev) (void)hipFree(m->tris_dev);
   if (m->prim_idx_dev) (void)hipFree(m->prim_idx_dev);
+  if (m->emit_dev) (void)hipFree(m->emit_dev);
   if (m->refit_nodes_dev) (void)hipFree(m->refit_nodes_dev);
   delete m->level_offsets;
   delete m;

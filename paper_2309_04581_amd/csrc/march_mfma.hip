@@ -70,26 +70,6 @@ __device__ __forceinline__ bool occ_lookup(const FieldView& F, float px, float p
   return (F.occ[c >> 5] >> (c & 31)) & 1u;
 }
 
-// Shadow mask of the sample of column j (Sec. 3.1 "Shadow rays"): a lane of
-// group 0 sends a ray from the sample's world position to every light, and
-// each light a mesh hides multiplies the mask by P.shadow_mask; every lane
-// returns its column's mask.  stack: that lane's LDS stack, stride 16.
-__device__ __forceinline__ float sample_shadow(const FieldView& F, const BvhView& B, const MarchParams& P,
-                                               bool valid, float px, float py, float pz, int lane, int* stack) {
-  float m = 1.0f;
-  if (lane < 16 && valid) {
-    field_to_world(F, px, py, pz);
-    for (int li = 0; li < P.n_lights; ++li) {
-      const float sx = P.light_pos[li][0] - px, sy = P.light_pos[li][1] - py, sz = P.light_pos[li][2] - pz;
-      const float dist = sqrtf(sx * sx + sy * sy + sz * sz);
-      const RayPre sr = ray_pre(v3(px, py, pz), v3(sx / dist, sy / dist, sz / dist));
-      float th;
-      if (bvh_trace<true>(B, sr, dist, th, stack, nullptr, 16) >= 0) m *= P.shadow_mask;
-    }
-  }
-  return __shfl(m, lane & 15, 64);
-}
-
 // One ray per wave: lane j takes sample kb + j of each 16-sample tile, and
 // transmittance is a 16-lane prefix product carried from tile to tile.
 template <int NL, int SH, int CL, typename TabT, bool BF, bool SHADOW>

@@ -79,11 +79,18 @@ struct BvhView {
   int n_prims;
 };
 
+// Emitting triangles for light sampling, in face order: x = cumulative
+// choice probability (the last is 1), y = the triangle's own probability,
+// z = its position in leaf order (int bits).  A triangle is chosen with
+// probability proportional to its summed emitted radiance; its area is read
+// from the current vertices, so a refit keeps the table valid.
 struct MeshView {
   BvhView bvh;
   int n_mat;
   int emissive;        // some material emits (hits then read their material even at the bounce limit)
   Material mat[kMaxMaterials];
+  const float4* emit;  // [n_emit]
+  int n_emit;
 };
 
 }  // namespace mr
@@ -110,6 +117,7 @@ struct mr_mesh {
   mr::BvhNode* nodes_dev = nullptr;
   float4* tris_dev = nullptr;
   int4* prim_idx_dev = nullptr;     // (i0, i1, i2, original id) per prim in leaf order
+  float4* emit_dev = nullptr;       // emitting triangles (MeshView::emit)
   int* refit_nodes_dev = nullptr;   // node ids, deepest level first
   int n_nodes = 0, depth = 0, n_leaves = 0, nv = 0, nf = 0;
   std::vector<int>* level_offsets = nullptr;   // host: offsets of each level in refit_nodes

@@ -10,7 +10,7 @@ namespace mr {
 // Philox4x32-10 (Salmon et al., SC'11), keyed by (seed, 0), counter
 // (ray id, segment, purpose, 0); u = (x >> 8) * 2^-24 is exact in FP32.
 // ---------------------------------------------------------------------------
-enum { kRngGlass = 0, kRngDiffuse = 1, kRngRoulette = 2 };
+enum { kRngGlass = 0, kRngDiffuse = 1, kRngRoulette = 2, kRngEmitter = 3 };
 
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll

@@ -1,6 +1,7 @@
 // Ray queues and launch parameters of the render path.
 #pragma once
 #include "mr_common.h"
+#include "mr_device.h"
 
 namespace mr {
 
@@ -34,13 +35,39 @@ struct MarchParams {
   float light_pos[kMaxLights][3];
 };
 
+// Shadow mask of the sample of column j (Sec. 3.1 "Shadow rays"): a lane of
+// group 0 sends a ray from the sample's world position to every light, and
+// each light a mesh hides multiplies the mask by P.shadow_mask; every lane
+// returns its column's mask.  stack: that lane's LDS stack, stride 16.
+__device__ __forceinline__ float sample_shadow(const FieldView& F, const BvhView& B, const MarchParams& P,
+                                               bool valid, float px, float py, float pz, int lane, int* stack) {
+  float m = 1.0f;
+  if (lane < 16 && valid) {
+    field_to_world(F, px, py, pz);
+    for (int li = 0; li < P.n_lights; ++li) {
+      const float sx = P.light_pos[li][0] - px, sy = P.light_pos[li][1] - py, sz = P.light_pos[li][2] - pz;
+      const float dist = sqrtf(sx * sx + sy * sy + sz * sz);
+      const RayPre sr = ray_pre(v3(px, py, pz), v3(sx / dist, sy / dist, sz / dist));
+      float th;
+      if (bvh_trace<true>(B, sr, dist, th, stack, nullptr, 16) >= 0) m *= P.shadow_mask;
+    }
+  }
+  return __shfl(m, lane & 15, 64);
+}
+
 struct ShadeParams {
   int n_lights;
   float lights[kMaxLights][6];
   uint32_t seed;
   int rr_after;
   float t_min;
+  int sample_emitters;   // light sampling toward the mesh's emitting triangles
 };
+
+// Ray queue depth word: bits 0-15 segment index (= scatter count so far),
+// bits 16-23 the ray's bounce limit, bit 24 set when the last scatter was
+// diffuse.
+constexpr int kDepthAfterDiffuse = 1 << 24;
 
 struct RenderOut {
   float* radiance;
@@ -103,7 +130,7 @@ mr_status dispatch_march_mfma(const mr_field* f, RayQueue q, const int* count, i
 // proposal-sampled march (defined with the proposal kernels)
 // packets: 16 consecutive queue rays per wave when n_prop = 32 and n_fine <= 32
 mr_status dispatch_march_proposal(const mr_field* f, const mr_field* prop, RayQueue q, const int* count, int* work,
-                                  const MarchParams& P, int n_prop, int n_fine, bool packets,
+                                  const MarchParams& P, const BvhView& B, int n_prop, int n_fine, bool packets,
                                   unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st);
 
 }  // namespace mr

@@ -134,15 +134,16 @@ __device__ __forceinline__ float prop_sigma(const FieldView& P, const TabT* __re
 // ---------------------------------------------------------------------------
 // proposal-sampled march (one wave per ray)
 // ---------------------------------------------------------------------------
-template <int NL, int SH, int CL, typename TabT, bool BF, typename PTabT>
+template <int NL, int SH, int CL, typename TabT, bool BF, typename PTabT, bool SHADOW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_march_prop(RayQueue q, const int* __restrict__ count, int* __restrict__ work,
                                                     FieldView F, const TabT* __restrict__ table,
                                                     const uint32_t* __restrict__ frags, FieldView Pf,
-                                                    const PTabT* __restrict__ ptable, MarchParams P, int n_prop,
-                                                    int n_fine, unsigned long long* __restrict__ stats) {
+                                                    const PTabT* __restrict__ ptable, MarchParams P, BvhView B,
+                                                    int n_prop, int n_fine, unsigned long long* __restrict__ stats) {
   using LY = FragLayout<NL, SH, CL, BF>;
   __shared__ __align__(16) uint32_t sW[LY::TOTAL];
   __shared__ float sP[kPropMlp];
+  __shared__ int sstack[4 * 16 * kStack];   // shadow-ray stacks: 16 lanes per wave
   for (int i = threadIdx.x; i < LY::TOTAL; i += blockDim.x) sW[i] = frags[i];
   for (int i = threadIdx.x; i < kPropMlp; i += blockDim.x) sP[i] = Pf.mlp[i];
   __syncthreads();
@@ -226,7 +227,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       const float incl = sc16_mul(1.0f - alpha, j);
       float excl = __shfl_up(incl, 1, 16);
       if (j == 0) excl = 1.0f;
-      const float w = Tseg * excl * alpha;
+      float msk = 1.0f;
+      if constexpr (SHADOW)
+        msk = sample_shadow(F, B, P, valid, px, py, pz, lane, sstack + (threadIdx.x >> 6) * 16 * kStack + j);
+      const float w = Tseg * excl * alpha * msk;
       acc0 += w * rgb[0];
       acc1 += w * rgb[1];
       acc2 += w * rgb[2];
@@ -268,14 +272,15 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <int NL, int SH, int CL, typename TabT, bool BF, typename PTabT>
+template <int NL, int SH, int CL, typename TabT, bool BF, typename PTabT, bool SHADOW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_march_prop_pk(
     RayQueue q, const int* __restrict__ count, int* __restrict__ work, FieldView F, const TabT* __restrict__ table,
-    const uint32_t* __restrict__ frags, FieldView Pf, const PTabT* __restrict__ ptable, MarchParams P, int n_fine,
-    unsigned long long* __restrict__ stats) {
+    const uint32_t* __restrict__ frags, FieldView Pf, const PTabT* __restrict__ ptable, MarchParams P, BvhView B,
+    int n_fine, unsigned long long* __restrict__ stats) {
   using LY = FragLayout<NL, SH, CL, BF>;
   __shared__ __align__(16) uint32_t sW[LY::TOTAL];
   __shared__ float sP[kPropMlp];
+  __shared__ int sstack[4 * 16 * kStack];   // shadow-ray stacks: 16 lanes per wave
   __shared__ float sCdf[4][16][kPkBins], sBin[4][16][kPkBins], sEdge[4][16][kPkBins + 1];
   for (int i = threadIdx.x; i < LY::TOTAL; i += blockDim.x) sW[i] = frags[i];
   for (int i = threadIdx.x; i < kPropMlp; i += blockDim.x) sP[i] = Pf.mlp[i];
@@ -400,7 +405,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       f4v raw;
       mlp_tile<NL, SH, CL, BF>(sW, fe, u_sh, F.density_offset, lane, sigma, rgb, raw);
       const float alpha = valid ? -expm1f(-sigma * D) : 0.0f;
-      const float wt = T * alpha;
+      float msk = 1.0f;
+      if constexpr (SHADOW) msk = sample_shadow(F, B, P, valid, px, py, pz, lane, sstack + wv * 16 * kStack + j);
+      const float wt = T * alpha * msk;
       acc0 += wt * rgb[0];
       acc1 += wt * rgb[1];
       acc2 += wt * rgb[2];
@@ -611,26 +618,37 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
   }
 }
 
-template <int NL, int SH, int CL, typename TabT, bool BF, typename PTabT>
-mr_status launch_prop(const mr_field* f, const mr_field* p, RayQueue q, const int* count, int* work,
-                      const MarchParams& P, int n_prop, int n_fine, bool packets, unsigned long long* stats,
-                      int blocks_per_cu, int64_t n, hipStream_t st) {
+template <int NL, int SH, int CL, typename TabT, bool BF, typename PTabT, bool SHADOW>
+mr_status launch_prop_mode(const mr_field* f, const mr_field* p, RayQueue q, const int* count, int* work,
+                           const MarchParams& P, const BvhView& B, int n_prop, int n_fine, bool packets,
+                           unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st) {
   const uint32_t* fr = BF ? f->frag_bf16_dev : f->frag_f32_dev;
   const TabT* tab = reinterpret_cast<const TabT*>(f->table_dev);
   const PTabT* ptab = reinterpret_cast<const PTabT*>(p->table_dev);
   if (packets && n_prop == kPkBins && n_fine <= kPkBins) {
-    auto* k = k_march_prop_pk<NL, SH, CL, TabT, BF, PTabT>;
+    auto* k = k_march_prop_pk<NL, SH, CL, TabT, BF, PTabT, SHADOW>;
     const int blocks = persistent_blocks(reinterpret_cast<const void*>(k), 256, blocks_per_cu, (n + 63) / 64);
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, q, count, work, f->view, tab, fr, p->view, ptab, P, n_fine,
-                       stats);
-  } else {
-    auto* k = k_march_prop<NL, SH, CL, TabT, BF, PTabT>;
-    const int blocks = persistent_blocks(reinterpret_cast<const void*>(k), 256, blocks_per_cu, (n + 3) / 4);
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, q, count, work, f->view, tab, fr, p->view, ptab, P, n_prop,
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, q, count, work, f->view, tab, fr, p->view, ptab, P, B,
                        n_fine, stats);
+  } else {
+    auto* k = k_march_prop<NL, SH, CL, TabT, BF, PTabT, SHADOW>;
+    const int blocks = persistent_blocks(reinterpret_cast<const void*>(k), 256, blocks_per_cu, (n + 3) / 4);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, q, count, work, f->view, tab, fr, p->view, ptab, P, B,
+                       n_prop, n_fine, stats);
   }
   MR_HIP(hipGetLastError());
   return MR_OK;
+}
+
+template <int NL, int SH, int CL, typename TabT, bool BF, typename PTabT>
+mr_status launch_prop(const mr_field* f, const mr_field* p, RayQueue q, const int* count, int* work,
+                      const MarchParams& P, const BvhView& B, int n_prop, int n_fine, bool packets,
+                      unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st) {
+  if (P.shadows)
+    return launch_prop_mode<NL, SH, CL, TabT, BF, PTabT, true>(f, p, q, count, work, P, B, n_prop, n_fine, packets,
+                                                               stats, blocks_per_cu, n, st);
+  return launch_prop_mode<NL, SH, CL, TabT, BF, PTabT, false>(f, p, q, count, work, P, B, n_prop, n_fine, packets,
+                                                              stats, blocks_per_cu, n, st);
 }
 
 template <int NL, int SH, int CL, typename TabT, bool BF>
@@ -672,14 +690,14 @@ mr_status check_prop(const mr_field* p, int64_t n, const float* o, const float* 
 namespace mr {
 
 mr_status dispatch_march_proposal(const mr_field* f, const mr_field* prop, RayQueue q, const int* count, int* work,
-                                  const MarchParams& P, int n_prop, int n_fine, bool packets,
+                                  const MarchParams& P, const BvhView& B, int n_prop, int n_fine, bool packets,
                                   unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st) {
   const auto& v = f->view;
   const bool h = v.table_dtype == MR_F16, bf = v.mlp_dtype == MR_BF16;
   const bool ph = prop->view.table_dtype == MR_F16;
 #define PR(NL, SH, CL, TT, BFV)                                                                                      \
-  return ph ? launch_prop<NL, SH, CL, TT, BFV, __half>(f, prop, q, count, work, P, n_prop, n_fine, packets, stats, blocks_per_cu, n, st) \
-            : launch_prop<NL, SH, CL, TT, BFV, float>(f, prop, q, count, work, P, n_prop, n_fine, packets, stats, blocks_per_cu, n, st);
+  return ph ? launch_prop<NL, SH, CL, TT, BFV, __half>(f, prop, q, count, work, P, B, n_prop, n_fine, packets, stats, blocks_per_cu, n, st) \
+            : launch_prop<NL, SH, CL, TT, BFV, float>(f, prop, q, count, work, P, B, n_prop, n_fine, packets, stats, blocks_per_cu, n, st);
 #define M(NL, SH, CL)                                                        \
   if (v.n_levels == NL && v.sh == SH && v.c_layers == CL) {                   \
     if (bf) {                                                                 \

@@ -179,11 +179,12 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade(RayQueue qi, const int* _
       ++n_seg;
       rid = qi.rid[i];
       const int depth = qi.depth[i];
-      const int seg = depth & 0xFFFF, mb = depth >> 16;
+      const int seg = depth & 0xFFFF, mb = (depth >> 16) & 0xFF;
       const int p = qi.hit_p[i];
       tr = qi.tr[i]; tg = qi.tg[i]; tb = qi.tb[i];
       lr = qi.lr[i]; lg = qi.lg[i]; lb = qi.lb[i];
-      if (p >= 0 && M.emissive) {
+      // with light sampling, the emission a diffuse bounce reaches was estimated at that bounce
+      if (p >= 0 && M.emissive && !(S.sample_emitters && (depth & kDepthAfterDiffuse))) {
         // Eq. 12: emitted radiance at the hit, attenuated by the marched segment
         const Material& em = M.mat[__float_as_int(M.bvh.tris[3 * p + 1].w)];
         lr += tr * em.emission[0];
@@ -225,6 +226,45 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade(RayQueue qi, const int* _
             lr += tr * mat.albedo[0] * S.lights[li][3] * g;
             lg += tg * mat.albedo[1] * S.lights[li][4] * g;
             lb += tb * mat.albedo[2] * S.lights[li][5] * g;
+          }
+          if (S.sample_emitters && M.n_emit > 0) {
+            // one point on one emitting triangle: the triangle by the cumulative
+            // probabilities, the point uniform by area (s = sqrt(u1))
+            const float4 ue = draw4(S.seed, (uint32_t)rid, (uint32_t)seg, kRngEmitter);
+            int lo = 0, hi = M.n_emit - 1;
+            while (lo < hi) {
+              const int mid = (lo + hi) >> 1;
+              if (ue.x < M.emit[mid].x) hi = mid;
+              else lo = mid + 1;
+            }
+            const float4 e = M.emit[lo];
+            const int ep = __float_as_int(e.z);
+            const float4 a0 = M.bvh.tris[3 * ep], a1 = M.bvh.tris[3 * ep + 1], a2 = M.bvh.tris[3 * ep + 2];
+            const V3 w0 = v3(a0.x, a0.y, a0.z), w1 = v3(a1.x, a1.y, a1.z), w2 = v3(a2.x, a2.y, a2.z);
+            const float sq = sqrtf(ue.y);
+            const V3 x = (1.0f - sq) * w0 + (sq * (1.0f - ue.z)) * w1 + (sq * ue.z) * w2;
+            const V3 en = cross(w1 - w0, w2 - w0);
+            const float a2x = sqrtf(dot(en, en));          // twice the area
+            const V3 wi = x - P;
+            const float d2 = dot(wi, wi), dist = sqrtf(d2);
+            const V3 l = v3(wi.x / dist, wi.y / dist, wi.z / dist);
+            const float cos_p = dot(nf, l), cos_x = fabsf(dot(en, l)) / a2x;
+            if (cos_p > 0.0f && cos_x > 0.0f) {
+              const V3 so = P + 1e-4f * nf;
+              V3 sd = x - so;
+              const float sdist = sqrtf(dot(sd, sd));
+              sd = v3(sd.x / sdist, sd.y / sdist, sd.z / sdist);
+              const RayPre sr = ray_pre(so, sd);
+              float th;
+              ++n_shadow;
+              if (bvh_trace<true>(M.bvh, sr, (1.0f - 1e-3f) * sdist, th, stack + threadIdx.x, nullptr, kTraceBlock) < 0) {
+                const Material& em = M.mat[__float_as_int(a1.w)];
+                const float g = cos_p * cos_x / d2 * (0.5f * a2x) / e.y * (1.0f / 3.14159265358979323846f);
+                lr += tr * mat.albedo[0] * em.emission[0] * g;
+                lg += tg * mat.albedo[1] * em.emission[1] * g;
+                lb += tb * mat.albedo[2] * em.emission[2] * g;
+              }
+            }
           }
         }
         const float4 u = draw4(S.seed, (uint32_t)rid, (uint32_t)seg, mat.kind == MR_GLASS ? kRngGlass : kRngDiffuse);
@@ -289,7 +329,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade(RayQueue qi, const int* _
           const V3 no = P + 1e-4f * side;
           nox = no.x; noy = no.y; noz = no.z;
           ndx = nd.x; ndy = nd.y; ndz = nd.z;
-          ndepth = (mb << 16) | nscat;
+          ndepth = (mb << 16) | nscat | (mat.kind == MR_DIFFUSE ? kDepthAfterDiffuse : 0);
         }
       }
     }
@@ -440,8 +480,6 @@ mr_status validate_render(const mr_field* field, const mr_mesh* mesh, int64_t n,
   if (opts->march_packets < -1) return fail(MR_ERR_INVALID_ARG, "march_packets must be >= -1");
   if (opts->sample_shadows && !(opts->shadow_mask >= 0.0f && opts->shadow_mask <= 1.0f))
     return fail(MR_ERR_INVALID_ARG, "shadow_mask must be in [0, 1]");
-  if (opts->sample_shadows && opts->sampler == MR_SAMPLER_PROPOSAL)
-    return fail(MR_ERR_UNSUPPORTED, "sample shadows are built for the uniform sampler only");
   if (opts->use_occupancy && field && !field->occ_dev)
     return fail(MR_ERR_STATE, "use_occupancy set but the field has no occupancy grid");
   return MR_OK;
@@ -511,6 +549,7 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
   S.seed = opts->seed;
   S.rr_after = opts->rr_after;
   S.t_min = opts->t_min_throughput;
+  S.sample_emitters = opts->sample_emitters ? 1 : 0;
 
   RenderOut ro;
   ro.radiance = out->radiance;
@@ -537,7 +576,7 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
     if (field) {
       StageTimer tm(1, st);
       if (opts->sampler == MR_SAMPLER_PROPOSAL)
-        s = dispatch_march_proposal(field, opts->proposal, qi, counts + b, work + kXcds * b, P, opts->n_proposal,
+        s = dispatch_march_proposal(field, opts->proposal, qi, counts + b, work + kXcds * b, P, mv.bvh, opts->n_proposal,
                                     opts->n_fine, b < packet_segments, stats, opts->march_blocks_per_cu, n, st);
       else
         s = dispatch_march_mfma(field, qi, counts + b, work + kXcds * b, P, mv.bvh, b < packet_segments, stats,

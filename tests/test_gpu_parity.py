@@ -4,6 +4,7 @@ Tolerances: hit triangle ids, bounce counts and occupancy bits are compared
 bit-exactly on rays (cells) the oracle does not flag as ties; radiance and
 throughput per channel within |a - b| <= 1e-4 |b| + 1e-7 (FP32 arithmetic
 against FP64); field values with the bounds derived at each test."""
+import copy
 import functools
 import math
 
@@ -69,7 +70,7 @@ def oracle_camera_rays(scene):
 
 
 def gpu_render(scene, o, d, field=None, mesh=None, table_dtype=0, mlp_dtype=0, use_occupancy=False,
-               occ_res=0, max_bounces=None, per_ray=None, packets=0):
+               occ_res=0, max_bounces=None, per_ray=None, packets=0, **opts_kw):
     M = mr()
     fld = field if field is not None else (M.Field(scene.field, table_dtype, mlp_dtype) if scene.field is not None else None)
     msh = mesh if mesh is not None else (M.Mesh(scene.mesh) if scene.mesh is not None else None)
@@ -77,7 +78,7 @@ def gpu_render(scene, o, d, field=None, mesh=None, table_dtype=0, mlp_dtype=0, u
         fld.build_occupancy(occ_res, scene.occupancy_thresh)
     mb = scene.max_bounces if max_bounces is None else max_bounces
     R = M.Renderer(len(o), mb)
-    opts = M.make_opts(scene, use_occupancy=use_occupancy)
+    opts = M.make_opts(scene, use_occupancy=use_occupancy, **opts_kw)
     opts.march_packets = packets
     R.render(fld, msh, dev(o), dev(d), scene.lights, opts,
              per_ray_max_bounces=None if per_ray is None else dev(per_ray, torch.int32))
@@ -586,10 +587,8 @@ def test_sample_shadow_options_validated():
     R = M.Renderer(len(o), sc.max_bounces)
     with pytest.raises(M.MrError):
         R.render(F, G, dev(o), dev(d), sc.lights, M.make_opts(sc, shadow_mask=1.5))
-    P = M.Field(sg.make_proposal(), table_dtype=M.MR_F32)
     with pytest.raises(M.MrError):
-        R.render(F, G, dev(o), dev(d), sc.lights,
-                 M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P, shadow_mask=0.2))
+        R.render(F, G, dev(o), dev(d), sc.lights, M.make_opts(sc, shadow_mask=-0.1))
 
 
 def test_scaling_workload_small_matches_oracle():
@@ -623,9 +622,63 @@ def test_emitters_match_oracle(packets):
     compare_render(gpu_render(sc, o, d, packets=packets), r, f"emitters packets={packets}")
 
 
-def test_emitter_scene_small_image_matches_oracle():
-    """The mid scene with its emitting ceiling panel at 32x24."""
+@pytest.mark.parametrize("sample_emitters", [False, True])
+def test_emitter_scene_small_image_matches_oracle(sample_emitters):
+    """The mid scene with its emitting ceiling panel at 32x24, with and
+    without light sampling toward the panel at the floor's diffuse hits."""
     sc = sg.emitter_scene(width=32, height=24)
     o, d = oracle_camera_rays(sc)
-    r = orc.render(sc, o, d)
-    compare_render(gpu_render(sc, o, d), r, "emitter scene 32x24")
+    r = orc.render(sc, o, d, sample_emitters=sample_emitters)
+    compare_render(gpu_render(sc, o, d, sample_emitters=sample_emitters), r,
+                   f"emitter scene 32x24 sample_emitters={sample_emitters}")
+
+
+# ---------------------------------------------------------------------------
+# light sampling toward emitting triangles (Eq. 12's L_e as area lights)
+# ---------------------------------------------------------------------------
+
+def _one_ray_many_paths(sc, o, d, n):
+    return np.repeat(o, n, 0), np.repeat(d, n, 0)
+
+
+@pytest.mark.parametrize("two,sample_emitters", [(False, True), (False, False), (True, True)])
+def test_emitter_sampling_paths_match_oracle(two, sample_emitters):
+    """20 000 paths of one camera ray onto a diffuse floor under one or two
+    emitting rectangles (ray i draws the Philox streams of id i on both
+    sides): every path's light sample or bounce matches the oracle's, and the
+    GPU mean is the closed-form albedo L_e F (5 standard errors)."""
+    from test_oracle_pins import _corner_form_factor, _floor_under_emitters
+    em = [(-0.5, 0.5, -0.5, 0.5, 1.0, (2.0, 1.0, 0.5))]
+    if two:
+        em.append((0.8, 1.4, -0.3, 0.3, 1.0, (1.0, 3.0, 1.0)))
+    sc, o1, d1 = _floor_under_emitters(em)
+    o, d = _one_ray_many_paths(sc, o1, d1, 20000)
+    r = orc.render(sc, o, d, sample_emitters=sample_emitters)
+    g = gpu_render(sc, o, d, sample_emitters=sample_emitters)
+    compare_render(g, r, f"emitter paths two={two} sample_emitters={sample_emitters}", rtol=1e-4, atol=1e-7,
+                   max_tie_frac=0.005)
+    want = 0.5 * np.array([2.0, 1.0, 0.5]) * 4 * _corner_form_factor(0.5, 0.5, 1.0)
+    if two:
+        want = want + 0.5 * np.array([1.0, 3.0, 1.0]) * 2 * (_corner_form_factor(1.4, 0.3, 1.0) -
+                                                              _corner_form_factor(0.8, 0.3, 1.0))
+    mean, err = g["radiance"].mean(0), g["radiance"].std(0) / math.sqrt(len(o))
+    assert np.all(np.abs(mean - want) < 5 * err), (mean, want, err)
+
+
+def test_emitter_sampling_after_refit_matches_oracle():
+    """The emitter table holds probabilities by radiance only and reads areas
+    from the current vertices: grow the emitter to 1.5 times its size with a
+    refit and compare against the oracle on the moved mesh."""
+    from test_oracle_pins import _floor_under_emitters
+    sc, o1, d1 = _floor_under_emitters([(-0.5, 0.5, -0.5, 0.5, 1.0, (2.0, 1.0, 0.5))])
+    o, d = _one_ray_many_paths(sc, o1, d1, 4000)
+    M = mr()
+    G = M.Mesh(sc.mesh)
+    moved = copy.deepcopy(sc.mesh)
+    moved.vertices[4:, [0, 2]] *= 1.5
+    G.refit(dev(moved.vertices))
+    sc2 = copy.copy(sc)
+    sc2.mesh = moved
+    r = orc.render(sc2, o, d, sample_emitters=True)
+    compare_render(gpu_render(sc2, o, d, mesh=G, sample_emitters=True), r, "emitter sampling after refit",
+                   rtol=1e-4, atol=1e-7, max_tie_frac=0.005)

@@ -159,3 +159,32 @@ def test_proposal_render_with_field_pose_matches_oracle():
     g = dict(radiance=host(R.radiance), throughput=host(R.throughput), bounces=host(R.bounces),
              hit_ids=host(R.hit_ids))
     compare_render(g, r, "proposal posed shell", rtol=1e-3, atol=1e-6)
+
+
+# (field, march_packets): the proposal march in packets on the camera segment
+# only (default), per ray on every segment, and in packets on every segment
+@pytest.mark.parametrize("fieldkind,packets", [("tiny", 0), ("tiny", -1), ("shell", 99)])
+def test_proposal_render_with_sample_shadows_matches_oracle(fieldkind, packets):
+    """Per-sample shadow mask (Sec. 3.1) with the proposal sampler: each fine
+    sample the mirror cube hides from the light above it emits 0.2 of its
+    radiance; 32 + 32 samples, against the oracle."""
+    M = mr()
+    sc = sg.tiny_scene(table_amp=1.0)
+    if fieldkind == "shell":
+        sc.field = sg.shell_field()
+    sc.lights = np.array([[0.1, 1.6, -0.2, 10.0, 10.0, 10.0]], np.float32)
+    prop = sg.make_proposal(table_amp=0.5)
+    o, d = oracle_camera_rays(sc)
+    r = orc.render(sc, o, d, proposal=prop, n_prop=32, n_fine=32, shadow_mask=0.2)
+    plain = orc.render(sc, o, d, proposal=prop, n_prop=32, n_fine=32)
+    assert (np.abs(r["radiance"] - plain["radiance"]) > 1e-3 * plain["radiance"]).any(axis=1).mean() > 0.05
+    F, G = M.Field(sc.field), M.Mesh(sc.mesh)
+    P = M.Field(prop, table_dtype=M.MR_F32)
+    R = M.Renderer(len(o), sc.max_bounces)
+    opts = M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P, shadow_mask=0.2)
+    opts.march_packets = packets
+    R.render(F, G, dev(o), dev(d), sc.lights, opts)
+    g = dict(radiance=host(R.radiance), throughput=host(R.throughput), bounces=host(R.bounces),
+             hit_ids=host(R.hit_ids))
+    tol = 1e-4 if fieldkind == "tiny" else 1e-3
+    compare_render(g, r, f"proposal {fieldkind} sample shadows packets={packets}", rtol=tol, atol=1e-6)
