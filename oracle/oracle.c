@@ -603,6 +603,88 @@ static int64_t march(const orc_field* f, const orc_opts* opt, const double o_wor
   return ns;
 }
 
+/* Several fields in one scene (each a NeRF object with its own placement):
+ * the medium's density is the sum of the fields' densities, each zero outside
+ * its own box, and its colour their density-weighted mean, the usual rule for
+ * overlapping emission-absorption media.  Every grid interval of the uniform
+ * march is cut at each box face the ray crosses inside it, so every piece lies
+ * wholly inside or outside each box, and each piece is composited at its
+ * midpoint as in the single-field march (with one field the two agree).
+ * A piece inside no box, or whose fields are all empty there by their
+ * occupancy grids, leaves L and T unchanged. */
+static int64_t march_fields(const orc_opts* opt, const double o_world[3], const double d_world[3],
+                            double t_a, double t_hit, double T[3], double L[3], int* tie,
+                            const shadow_ctx* sh_in) {
+  enum { MAXF = 16 };
+  int nf = opt->n_fields;
+  if (nf > MAXF) nf = MAXF;
+  double span = opt->t_far - opt->t_near;
+  double t_b = fmin(t_a + span, t_hit);
+  double of[MAXF][3], df[MAXF][3], in[MAXF], out[MAXF];
+  int valid[MAXF];
+  orc_opts fo[MAXF];
+  for (int k = 0; k < nf; ++k) {
+    world_to_field(opt->fields[k], o_world, d_world, of[k], df[k]);
+    double b0, b1;
+    valid[k] = slab(opt->fields[k], of[k], df[k], &b0, &b1);
+    in[k] = fmax(t_a, b0);
+    out[k] = fmin(t_b, b1);
+    if (!(out[k] > in[k])) valid[k] = 0;
+    fo[k] = *opt;
+    fo[k].occ = opt->field_occ ? opt->field_occ[k] : NULL;
+    fo[k].occ_res = opt->field_occ_res ? opt->field_occ_res[k] : 0;
+  }
+  shadow_ctx shc;
+  if (sh_in) {
+    shc = *sh_in;
+    shc.o_world = o_world;
+    shc.d_world = d_world;
+  }
+  int64_t ns = 0;
+  double delta = span / opt->n_samples;
+  for (int j = 0; j < opt->n_samples; ++j) {
+    double a = t_a + j * delta, b = fmin(t_a + (j + 1) * delta, t_b);
+    if (a >= t_b) break;
+    double cut[2 * MAXF + 2];
+    int nc = 0;
+    cut[nc++] = a;
+    for (int k = 0; k < nf; ++k) {
+      if (!valid[k]) continue;
+      if (in[k] > a && in[k] < b) cut[nc++] = in[k];
+      if (out[k] > a && out[k] < b) cut[nc++] = out[k];
+    }
+    cut[nc++] = b;
+    for (int x = 1; x < nc; ++x)        /* insertion sort of the cut points */
+      for (int y = x; y > 0 && cut[y] < cut[y - 1]; --y) { double t = cut[y]; cut[y] = cut[y - 1]; cut[y - 1] = t; }
+    for (int c = 0; c + 1 < nc; ++c) {
+      double lo = cut[c], hi = cut[c + 1];
+      if (!(hi > lo)) continue;
+      double tm = 0.5 * (lo + hi), D = hi - lo, sig = 0.0, sc[3] = {0, 0, 0};
+      int any = 0;
+      for (int k = 0; k < nf; ++k) {
+        if (!valid[k] || lo < in[k] || hi > out[k]) continue;
+        double x[3], sk, ck[3];
+        for (int i = 0; i < 3; ++i) x[i] = of[k][i] + tm * df[k][i];
+        if (!occupied(&fo[k], opt->fields[k], x, tie)) continue;
+        orc_field_eval(opt->fields[k], x, df[k], &sk, ck, NULL);
+        sig += sk;
+        for (int i = 0; i < 3; ++i) sc[i] += sk * ck[i];
+        ++any;
+      }
+      if (!any) continue;
+      ns += any;
+      double m = sh_in ? sample_mask(&shc, opt, tm, tie) : 1.0;
+      double alpha = -expm1(-sig * D);
+      for (int i = 0; i < 3; ++i) {
+        double ci = sig > 0.0 ? sc[i] / sig : 0.0;
+        L[i] += T[i] * alpha * m * ci;
+        T[i] *= (1.0 - alpha);
+      }
+    }
+  }
+  return ns;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Surface interaction (Eq. 12-13): perfect mirror, smooth dielectric with   */
 /* exact unpolarised Fresnel (reflect with probability R, else refract),     */
@@ -781,8 +863,12 @@ static void render_ray(const job_t* J, int64_t r) {
     tie |= t_tie;
     if (J->out->hit_ids) J->out->hit_ids[r * stride + s] = hit;
     shadow_ctx sh = {m, J->lights, J->n_lights, opt->shadow_mask, NULL, NULL};
-    nsamp += march(J->f, opt, o, d, t_a, hit >= 0 ? t_hit : INFINITY, T, L, &tie,
-                   opt->sample_shadows && m && J->n_lights > 0 ? &sh : NULL);
+    if (opt->n_fields > 0)
+      nsamp += march_fields(opt, o, d, t_a, hit >= 0 ? t_hit : INFINITY, T, L, &tie,
+                            opt->sample_shadows && m && J->n_lights > 0 ? &sh : NULL);
+    else
+      nsamp += march(J->f, opt, o, d, t_a, hit >= 0 ? t_hit : INFINITY, T, L, &tie,
+                     opt->sample_shadows && m && J->n_lights > 0 ? &sh : NULL);
     ++segs;
     if (hit < 0) break;                  /* escaped the scene: background is 0 */
     if (!(opt->sample_emitters && after_diffuse)) {   /* Eq. 12: emitted radiance, attenuated by the segment */

@@ -70,6 +70,14 @@ typedef struct {
    * uniformly by area on it; a path that reaches an emitter straight after a
    * diffuse scatter then adds no L_e there (the light sample stands for it) */
   int32_t sample_emitters;
+  /* optional several fields in one scene (uniform sampler only): when
+   * n_fields > 0 the field argument of orc_render is ignored and these are
+   * marched together; field_occ[k] (or NULL) is field k's occupancy grid of
+   * resolution field_occ_res[k] */
+  int32_t n_fields;
+  const orc_field* const* fields;
+  const uint8_t* const* field_occ;
+  const int32_t* field_occ_res;
 } orc_opts;
 
 typedef struct {

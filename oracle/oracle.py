@@ -52,7 +52,8 @@ class _Opts(C.Structure):
                 ("occ_res", C.c_int32), ("occ", C.c_void_p),
                 ("proposal", C.c_void_p), ("n_prop", C.c_int32), ("n_fine", C.c_int32),
                 ("sample_shadows", C.c_int32), ("shadow_mask", C.c_double),
-                ("sample_emitters", C.c_int32)]
+                ("sample_emitters", C.c_int32), ("n_fields", C.c_int32), ("fields", C.c_void_p),
+                ("field_occ", C.c_void_p), ("field_occ_res", C.c_void_p)]
 
 
 class _Out(C.Structure):
@@ -214,7 +215,8 @@ def occupancy(field, res, thresh, n_threads=None):
 
 def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
            tie_eps=1e-5, tie_rel=1e-4, occupancy_bits=None, proposal=None, n_prop=32,
-           n_fine=32, field=..., mesh=..., shadow_mask=None, sample_emitters=False):
+           n_fine=32, field=..., mesh=..., shadow_mask=None, sample_emitters=False, fields=None,
+           field_occupancy=None):
     """Render FP32 input rays through the whole path in FP64.
 
     shadow_mask: None = no per-sample shadows; else every field sample that a
@@ -222,6 +224,9 @@ def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
     once per such light (Sec. 3.1 "Shadow rays").
     sample_emitters: light sampling toward emitting triangles at diffuse hits
     (Eq. 12's L_e as area lights).
+    fields: several fields marched together (uniform sampler; the scene's own
+    field is then not used); field_occupancy: per field an occupancy bit
+    array or None.
 
     Returns a dict with radiance, throughput, bounces, hit_ids (segments),
     tie flags, per-ray sample and segment counts.
@@ -256,6 +261,27 @@ def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
     if shadow_mask is not None:
         opt.sample_shadows, opt.shadow_mask = 1, float(shadow_mask)
     opt.sample_emitters = 1 if sample_emitters else 0
+    keep = []
+    if fields is not None:
+        if proposal is not None:
+            raise ValueError("several fields are marched with the uniform sampler only")
+        ofs = [OField(f) for f in fields]
+        ptrs = (C.c_void_p * len(ofs))(*[C.cast(C.pointer(x.s), C.c_void_p) for x in ofs])
+        occs = (C.c_void_p * len(ofs))()
+        ress = (C.c_int32 * len(ofs))()
+        for k, bits in enumerate(field_occupancy or [None] * len(ofs)):
+            if bits is not None:
+                bits = np.ascontiguousarray(bits, dtype=np.uint8)
+                keep.append(bits)
+                occs[k] = bits.ctypes.data
+                ress[k] = int(round(len(bits) ** (1 / 3)))
+        keep += [ofs, ptrs, occs, ress]
+        opt.n_fields = len(ofs)
+        opt.fields = C.cast(ptrs, C.c_void_p)
+        opt.field_occ = C.cast(occs, C.c_void_p)
+        opt.field_occ_res = C.cast(ress, C.c_void_p)
+        if of is None and ofs:
+            of = ofs[0]
     res = dict(radiance=np.zeros((n, 3)), throughput=np.zeros((n, 3)),
                bounces=np.zeros(n, dtype=np.int32),
                hit_ids=np.full((n, gmax + 1), -1, dtype=np.int32),

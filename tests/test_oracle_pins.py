@@ -1049,3 +1049,98 @@ def test_light_sampling_without_emitters_changes_nothing():
     r = orc.render(_scene(None, mesh), np.array([[0.05, 0.02, -1.0]], np.float32),
                    np.array([[0.0, 0.0, 1.0]], np.float32), sample_emitters=True)
     np.testing.assert_allclose(r["radiance"][0], 3.0, rtol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# several fields in one scene (density sum, density-weighted colour)
+# ---------------------------------------------------------------------------
+
+Y00 = 0.28209479177387814
+
+
+def _tinted_field(sigma_offset, rgb, center=None):
+    """Zero table: sigma = softplus(sigma_offset) everywhere in the box and a
+    colour fixed by the weights from SH component Y00 (the colour MLP's
+    input column d_out) through hidden unit 0 to the output layer.  Returns
+    the field and its exact colour, exp(w Y00) of the stored FP32 weights."""
+    f = _constant_field(sigma_offset)
+    shapes = f.layer_shapes()
+    assert len(shapes) == 4
+    offs = np.cumsum([0] + [o * i for o, i in shapes])
+    W = f.mlp[offs[2]:offs[3]].reshape(shapes[2])
+    W[0, f.d_out] = 1.0
+    V = f.mlp[offs[3]:offs[4]].reshape(shapes[3])
+    V[:, 0] = np.log(np.asarray(rgb, np.float64)) / Y00
+    colour = np.exp(V[:, 0].astype(np.float64) * Y00)
+    if center is not None:
+        f.pose = sg.pose_matrix(np.eye(3), center)
+    return f, colour
+
+
+def _fields_render(fields, o, d, **kw):
+    sc = _scene(None, None, t_far=8.0, n_samples=64, max_bounces=0)
+    return orc.render(sc, o, d, fields=fields, **kw)
+
+
+def test_one_field_through_the_several_fields_march_is_the_single_field_march():
+    """The several-fields march with one (posed) field agrees with the
+    single-field march on the tiny scene's rays."""
+    sc = sg.tiny_scene(table_amp=1.0)
+    sc.field.pose = sg.pose_matrix(sg.rotation((0.2, 1.0, 0.1), 0.4), (0.1, -0.05, 0.0))
+    o, d = orc.rays_from_camera(sg.cameras_array(sc.cameras)[0])
+    o, d = o.astype(np.float32), d.astype(np.float32)
+    a = orc.render(sc, o, d)
+    b = orc.render(sc, o, d, fields=[sc.field])
+    np.testing.assert_allclose(b["radiance"], a["radiance"], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(b["throughput"], a["throughput"], rtol=1e-12, atol=1e-15)
+    np.testing.assert_array_equal(b["samples"], a["samples"])
+
+
+def test_two_disjoint_fields_composite_front_to_back():
+    """Field A in [-1, 1]^3 and field B moved to z in [1.5, 3.5], different
+    densities and colours, ray along +z: L = c_A (1 - T_A) + T_A c_B (1 - T_B)
+    with T = exp(-sigma * 2); the reverse ray sees B first."""
+    fa, ca = _tinted_field(1.0, (0.9, 0.3, 0.2))
+    fb, cb = _tinted_field(-0.5, (0.1, 0.6, 1.7), center=(0.0, 0.0, 2.5))
+    sa, sb = math.log1p(math.exp(1.0)), math.log1p(math.exp(-0.5))
+    Ta, Tb = math.exp(-2 * sa), math.exp(-2 * sb)
+    o = np.array([[0.05, 0.02, -2.5], [0.05, 0.02, 5.5]], np.float32)
+    d = np.array([[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]], np.float32)
+    r = _fields_render([fa, fb], o, d)
+    np.testing.assert_allclose(r["radiance"][0], ca * (1 - Ta) + Ta * cb * (1 - Tb), rtol=1e-12)
+    np.testing.assert_allclose(r["radiance"][1], cb * (1 - Tb) + Tb * ca * (1 - Ta), rtol=1e-12)
+    np.testing.assert_allclose(r["throughput"], Ta * Tb, rtol=1e-12)
+    r2 = _fields_render([fb, fa], o, d)                 # the list order does not matter
+    np.testing.assert_allclose(r2["radiance"], r["radiance"], rtol=1e-13)
+
+
+def test_overlapping_fields_add_density_and_mix_colour():
+    """Field B moved to z in [0.2, 2.2] overlaps A on [0.2, 1]: there the
+    density is sigma_A + sigma_B and the colour (sigma_A c_A + sigma_B c_B) /
+    (sigma_A + sigma_B); the three pieces composite in closed form, exactly,
+    because the grid is cut at the box faces."""
+    fa, ca = _tinted_field(1.0, (0.9, 0.3, 0.2))
+    fb, cb = _tinted_field(-0.5, (0.1, 0.6, 1.7), center=(0.0, 0.0, 1.2))
+    sa, sb = math.log1p(math.exp(1.0)), math.log1p(math.exp(-0.5))
+    o = np.array([[0.05, 0.02, -2.5]], np.float32)
+    d = np.array([[0.0, 0.0, 1.0]], np.float32)
+    r = _fields_render([fa, fb], o, d)
+    T1, T2, T3 = math.exp(-sa * 1.2), math.exp(-(sa + sb) * 0.8), math.exp(-sb * 1.2)
+    cmix = (sa * ca + sb * cb) / (sa + sb)
+    want = ca * (1 - T1) + T1 * cmix * (1 - T2) + T1 * T2 * cb * (1 - T3)
+    np.testing.assert_allclose(r["radiance"][0], want, rtol=1e-12)
+    np.testing.assert_allclose(r["throughput"][0], T1 * T2 * T3, rtol=1e-12)
+
+
+def test_field_outside_the_segment_changes_nothing():
+    """A second field beyond the first surface hit, or behind the camera,
+    leaves every output bit of the one-field render unchanged."""
+    fa, _ = _tinted_field(1.0, (0.9, 0.3, 0.2))
+    fb, _ = _tinted_field(0.0, (1.0, 1.0, 1.0), center=(0.0, 0.0, -6.0))
+    o = np.array([[0.05, 0.02, -2.5], [0.3, -0.2, -2.5]], np.float32)
+    d = np.array([[0.0, 0.0, 1.0], [0.1, 0.0, 0.995]], np.float32)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    a = _fields_render([fa], o, d)
+    b = _fields_render([fa, fb], o, d)
+    for k in ("radiance", "throughput", "samples"):
+        np.testing.assert_array_equal(a[k], b[k])
