@@ -343,6 +343,33 @@ def emitters(M, sg, steps):
                                     "mean_radiance": [round(float(x), 5) for x in R.radiance.mean(0).cpu().numpy()]}}
 
 
+def several_fields(M, sg, steps, n_fields=3):
+    """Several NeRF objects in one scene (mr_render_fields): three mid-layout
+    fields (64 MiB tables each), turned and side by side, over a floor with a
+    glass sphere and a mirror cube, 800x450, 8 bounces, plain FP32 with each
+    field's occupancy grid."""
+    import torch
+    sc = sg.fields_scene(n_fields)
+    cams = sg.cameras_array(sc.cameras)
+    n = sc.n_rays
+    Fs = [M.Field(f) for f in sc.fields]
+    for F in Fs:
+        F.build_occupancy(sc.occupancy_res, sc.occupancy_thresh)
+    G = M.Mesh(sc.mesh)
+    o = torch.empty(n, 3, device="cuda")
+    d = torch.empty(n, 3, device="cuda")
+    R = M.Renderer(n, sc.max_bounces, with_hits=False)
+    opts = M.make_opts(sc, use_occupancy=True)
+
+    def step():
+        M.mr_rays_from_cameras(cams, o, d, None, n)
+        R.render_fields(Fs, G, o, d, sc.lights, opts)
+    ms = timed(step, steps, 1)
+    c = R.counters.cpu().numpy()
+    return {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms, 3), "fields": n_fields,
+            "rays": n, "samples_per_step": int(c[0]), "samples_per_s": round(int(c[0]) / (ms / 1e3), 1)}
+
+
 def multicam(M, sg, steps):
     """16 cameras of uneven size and bounce depth in one queue, replayed as a graph."""
     import numpy as np
@@ -564,6 +591,7 @@ def main():
         line["moving_field"] = moving_field(M, sg, sc, F, G, cams, n, args.steps)
         line["sample_shadows"] = sample_shadows(M, sg, sc, F, G, cams, n, args.steps)
         line["emitters"] = emitters(M, sg, args.steps)
+        line["several_fields"] = several_fields(M, sg, args.steps)
         line["multicam_16_cameras"] = multicam(M, sg, 2)
         line["scaling_spheres"] = scaling(M, sg, 3)
         line["cloth_refit"] = cloth(M, sg, args.cloth_frames, args.train_steps)

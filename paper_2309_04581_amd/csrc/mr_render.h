@@ -9,6 +9,7 @@ constexpr int kQueueArrays = 16;       // 4-byte arrays per queue slot
 constexpr size_t kHeaderBytes = 4096;  // counters at the start of the workspace
 constexpr int kMaxBounces = 60;
 constexpr int kMaxCamsPerLaunch = 16;
+constexpr int kMaxFields = 8;          // fields marched together by mr_render_fields
 
 // Structure-of-arrays ray queue: one slot per live ray.
 struct RayQueue {

@@ -376,6 +376,86 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade(RayQueue qi, const int* _
 }
 
 // ---------------------------------------------------------------------------
+// several fields: each is marched in a pass of its own into a scratch copy of
+// the segment's throughput and radiance (starting at T = 1, L = 0); the
+// passes are then composited in the order the ray enters the fields' boxes.
+// With boxes that do not overlap, every sample lies in at most one field, so
+// this is the march of the summed medium.
+// ---------------------------------------------------------------------------
+struct FieldBoxes {
+  int n;
+  int has_pose[kMaxFields];
+  float pose[kMaxFields][12];
+  float amin[kMaxFields][3], amax[kMaxFields][3];
+};
+
+// scratch: per field six arrays of cap floats, T r g b then L r g b
+__global__ void k_fields_prep(const int* __restrict__ count, float* __restrict__ scratch, int n_fields, int64_t cap,
+                              int* __restrict__ ctr, int n_ctr) {
+  const int cnt = *count;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid < n_ctr) ctr[tid] = 0;
+  for (int64_t i = tid; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
+    for (int k = 0; k < n_fields; ++k) {
+      float* f = scratch + (int64_t)6 * k * cap;
+      f[i] = 1.0f; f[cap + i] = 1.0f; f[2 * cap + i] = 1.0f;
+      f[3 * cap + i] = 0.0f; f[4 * cap + i] = 0.0f; f[5 * cap + i] = 0.0f;
+    }
+}
+
+__global__ void k_fields_combine(RayQueue q, const int* __restrict__ count, const float* __restrict__ scratch,
+                                 int64_t cap, FieldBoxes fb) {
+  const int cnt = *count;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+    const float ox = q.ox[i], oy = q.oy[i], oz = q.oz[i], dx = q.dx[i], dy = q.dy[i], dz = q.dz[i];
+    float tin[kMaxFields];
+    int ord[kMaxFields];
+    for (int k = 0; k < fb.n; ++k) {
+      float p[3] = {ox, oy, oz}, d[3] = {dx, dy, dz};
+      if (fb.has_pose[k]) {
+        const float* P = fb.pose[k];
+        const float qx = ox - P[3], qy = oy - P[7], qz = oz - P[11];
+        for (int a = 0; a < 3; ++a) {
+          p[a] = P[a] * qx + P[4 + a] * qy + P[8 + a] * qz;
+          d[a] = P[a] * dx + P[4 + a] * dy + P[8 + a] * dz;
+        }
+      }
+      float lo = -INFINITY;
+      for (int a = 0; a < 3; ++a) {
+        const float inv = 1.0f / d[a];
+        const float t0 = (fb.amin[k][a] - p[a]) * inv, t1 = (fb.amax[k][a] - p[a]) * inv;
+        lo = fmaxf(lo, fminf(t0, t1));
+      }
+      // a field the ray misses carries T = 1, L = 0: its place in the order is immaterial
+      tin[k] = lo;
+      int j = k;
+      while (j > 0 && tin[ord[j - 1]] > lo) {
+        ord[j] = ord[j - 1];
+        --j;
+      }
+      ord[j] = k;
+    }
+    float tr = 1.0f, tg = 1.0f, tb = 1.0f, lr = 0.0f, lg = 0.0f, lb = 0.0f;
+    for (int j = 0; j < fb.n; ++j) {
+      const float* f = scratch + (int64_t)6 * ord[j] * cap;
+      lr += tr * f[3 * cap + i];
+      lg += tg * f[4 * cap + i];
+      lb += tb * f[5 * cap + i];
+      tr *= f[i];
+      tg *= f[cap + i];
+      tb *= f[2 * cap + i];
+    }
+    const float qr = q.tr[i], qg = q.tg[i], qb = q.tb[i];
+    q.lr[i] += qr * lr;
+    q.lg[i] += qg * lg;
+    q.lb[i] += qb * lb;
+    q.tr[i] = qr * tr;
+    q.tg[i] = qg * tg;
+    q.tb[i] = qb * tb;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // pinhole cameras
 // ---------------------------------------------------------------------------
 struct CamBatch {
@@ -492,15 +572,80 @@ extern "C" size_t mr_render_workspace_size(int64_t n) {
   return kHeaderBytes + 2 * queue_bytes(cap);
 }
 
-extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64_t n, const float* origins,
-                               const float* dirs, int32_t max_bounces, const int32_t* per_ray_max_bounces,
-                               const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
-                               mr_render_out* out, void* workspace, size_t workspace_bytes, void* stream) {
-  mr_status s = validate_render(field, mesh, n, origins, dirs, max_bounces, host_lights, n_lights, opts, out);
-  if (s != MR_OK) return s;
+// several fields: after the single-field workspace, 256 bytes of march
+// counters (kXcds per field) and the per-field scratch T and L arrays
+static constexpr size_t kFieldCtrBytes = 256;
+static_assert(kMaxFields * kXcds * sizeof(int) <= kFieldCtrBytes, "field counters");
+
+extern "C" size_t mr_render_fields_workspace_size(int64_t n, int32_t n_fields) {
+  const int64_t cap = ((std::max<int64_t>(n, 1) + 63) / 64) * 64;
+  if (n_fields <= 1) return mr_render_workspace_size(n);
+  return mr_render_workspace_size(n) + kFieldCtrBytes + (size_t)n_fields * 6 * sizeof(float) * (size_t)cap;
+}
+
+namespace {
+
+// Separating-axis test of two oriented boxes (centre, half extents, unit
+// axes as the columns of R): they overlap unless some face normal or edge
+// cross product separates their projections.  Touching boxes do not overlap.
+bool boxes_overlap(const double c1[3], const double h1[3], const double R1[3][3], const double c2[3],
+                   const double h2[3], const double R2[3][3]) {
+  double axes[15][3];
+  int na = 0;
+  for (int i = 0; i < 3; ++i) {
+    for (int k = 0; k < 3; ++k) axes[na][k] = R1[k][i];
+    ++na;
+    for (int k = 0; k < 3; ++k) axes[na][k] = R2[k][i];
+    ++na;
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const double a[3] = {R1[0][i], R1[1][i], R1[2][i]}, b[3] = {R2[0][j], R2[1][j], R2[2][j]};
+      axes[na][0] = a[1] * b[2] - a[2] * b[1];
+      axes[na][1] = a[2] * b[0] - a[0] * b[2];
+      axes[na][2] = a[0] * b[1] - a[1] * b[0];
+      ++na;
+    }
+  const double dc[3] = {c2[0] - c1[0], c2[1] - c1[1], c2[2] - c1[2]};
+  for (int a = 0; a < na; ++a) {
+    const double* L = axes[a];
+    const double l2 = L[0] * L[0] + L[1] * L[1] + L[2] * L[2];
+    if (l2 < 1e-12) continue;   // parallel edges: covered by the face normals
+    double r1 = 0.0, r2 = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      r1 += h1[i] * std::fabs(R1[0][i] * L[0] + R1[1][i] * L[1] + R1[2][i] * L[2]);
+      r2 += h2[i] * std::fabs(R2[0][i] * L[0] + R2[1][i] * L[1] + R2[2][i] * L[2]);
+    }
+    const double dist = std::fabs(dc[0] * L[0] + dc[1] * L[1] + dc[2] * L[2]);
+    if (dist >= (r1 + r2) * (1.0 - 1e-9)) return false;
+  }
+  return true;
+}
+
+void field_box(const mr_field* f, double c[3], double h[3], double R[3][3]) {
+  const FieldView& v = f->view;
+  double cf[3];
+  for (int k = 0; k < 3; ++k) {
+    cf[k] = 0.5 * ((double)v.amin[k] + (double)v.amax[k]);
+    h[k] = 0.5 * ((double)v.amax[k] - (double)v.amin[k]);
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) R[i][k] = v.has_pose ? (double)v.pose[4 * i + k] : (i == k ? 1.0 : 0.0);
+  for (int i = 0; i < 3; ++i)
+    c[i] = R[i][0] * cf[0] + R[i][1] * cf[1] + R[i][2] * cf[2] + (v.has_pose ? (double)v.pose[4 * i + 3] : 0.0);
+}
+
+mr_status render_impl(const mr_field* const* fields, int n_fields, const mr_mesh* mesh, int64_t n,
+                      const float* origins, const float* dirs, int32_t max_bounces,
+                      const int32_t* per_ray_max_bounces, const mr_light* host_lights, int32_t n_lights,
+                      const mr_render_opts* opts, mr_render_out* out, void* workspace, size_t workspace_bytes,
+                      void* stream) {
+  mr_status s = MR_OK;
+  const mr_field* field = n_fields == 1 ? fields[0] : nullptr;
   if (n == 0) return MR_OK;
-  if (!workspace || workspace_bytes < mr_render_workspace_size(n))
-    return fail(MR_ERR_INVALID_ARG, "workspace smaller than mr_render_workspace_size(n)");
+  if (!workspace || workspace_bytes < mr_render_fields_workspace_size(n, n_fields))
+    return fail(MR_ERR_INVALID_ARG, n_fields > 1 ? "workspace smaller than mr_render_fields_workspace_size(n, n_fields)"
+                                                 : "workspace smaller than mr_render_workspace_size(n)");
   if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(MR_ERR_INVALID_ARG, "workspace not 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;
   const int64_t cap = ((n + 63) / 64) * 64;
@@ -510,6 +655,20 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
   int* swork = twork + (kMaxBounces + 2);                   // shade tile queue heads
   int* work = swork + (kMaxBounces + 2);                    // march: kXcds ray queue heads per segment
   RayQueue Q[2] = {queue_at(ws + kHeaderBytes, cap), queue_at(ws + kHeaderBytes + queue_bytes(cap), cap)};
+  int* fctr = reinterpret_cast<int*>(ws + mr_render_workspace_size(n));     // several fields only
+  float* fscratch = reinterpret_cast<float*>(ws + mr_render_workspace_size(n) + kFieldCtrBytes);
+  FieldBoxes FB;
+  std::memset(&FB, 0, sizeof(FB));
+  FB.n = n_fields > 1 ? n_fields : 0;
+  for (int k = 0; k < FB.n; ++k) {
+    const FieldView& v = fields[k]->view;
+    FB.has_pose[k] = v.has_pose;
+    for (int j = 0; j < 12; ++j) FB.pose[k][j] = v.pose[j];
+    for (int j = 0; j < 3; ++j) {
+      FB.amin[k][j] = v.amin[j];
+      FB.amax[k][j] = v.amax[j];
+    }
+  }
   unsigned long long* stats = reinterpret_cast<unsigned long long*>(out->counters);
 
   const int init_blocks = (int)std::min<int64_t>((n + 255) / 256, 65535);
@@ -573,7 +732,24 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
                          opts->t_far, P.span, out->hit_ids, out->hit_ids ? out->hit_stride : 0);
       MR_HIP(hipGetLastError());
     }
-    if (field) {
+    if (n_fields > 1) {
+      StageTimer tm(1, st);
+      const int fblocks = (int)std::min<int64_t>((n + 255) / 256, 65535);
+      hipLaunchKernelGGL(k_fields_prep, dim3(fblocks), dim3(256), 0, st, counts + b, fscratch, n_fields, cap, fctr,
+                         n_fields * kXcds);
+      MR_HIP(hipGetLastError());
+      for (int k = 0; k < n_fields; ++k) {
+        RayQueue qk = qi;
+        float* f = fscratch + (int64_t)6 * k * cap;
+        qk.tr = f; qk.tg = f + cap; qk.tb = f + 2 * cap;
+        qk.lr = f + 3 * cap; qk.lg = f + 4 * cap; qk.lb = f + 5 * cap;
+        s = dispatch_march_mfma(fields[k], qk, counts + b, fctr + kXcds * k, P, mv.bvh, b < packet_segments, stats,
+                                opts->march_blocks_per_cu, n, st);
+        if (s != MR_OK) return s;
+      }
+      hipLaunchKernelGGL(k_fields_combine, dim3(fblocks), dim3(256), 0, st, qi, counts + b, fscratch, cap, FB);
+      MR_HIP(hipGetLastError());
+    } else if (field) {
       StageTimer tm(1, st);
       if (opts->sampler == MR_SAMPLER_PROPOSAL)
         s = dispatch_march_proposal(field, opts->proposal, qi, counts + b, work + kXcds * b, P, mv.bvh, opts->n_proposal,
@@ -591,6 +767,46 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
     }
   }
   return MR_OK;
+}
+
+}  // namespace
+
+extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64_t n, const float* origins,
+                               const float* dirs, int32_t max_bounces, const int32_t* per_ray_max_bounces,
+                               const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
+                               mr_render_out* out, void* workspace, size_t workspace_bytes, void* stream) {
+  mr_status s = validate_render(field, mesh, n, origins, dirs, max_bounces, host_lights, n_lights, opts, out);
+  if (s != MR_OK) return s;
+  return render_impl(&field, field ? 1 : 0, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, host_lights,
+                     n_lights, opts, out, workspace, workspace_bytes, stream);
+}
+
+extern "C" mr_status mr_render_fields(const mr_field* const* fields, int32_t n_fields, const mr_mesh* mesh, int64_t n,
+                                      const float* origins, const float* dirs, int32_t max_bounces,
+                                      const int32_t* per_ray_max_bounces, const mr_light* host_lights,
+                                      int32_t n_lights, const mr_render_opts* opts, mr_render_out* out,
+                                      void* workspace, size_t workspace_bytes, void* stream) {
+  if (n_fields < 1 || n_fields > kMaxFields) return fail(MR_ERR_INVALID_ARG, "n_fields must be in 1..8");
+  if (!fields) return fail(MR_ERR_INVALID_ARG, "null field list");
+  for (int k = 0; k < n_fields; ++k)
+    if (!fields[k]) return fail(MR_ERR_INVALID_ARG, "null field in the list");
+  for (int k = 0; k < n_fields; ++k) {
+    mr_status s = validate_render(fields[k], mesh, n, origins, dirs, max_bounces, host_lights, n_lights, opts, out);
+    if (s != MR_OK) return s;
+  }
+  if (n_fields > 1 && opts->sampler != MR_SAMPLER_UNIFORM)
+    return fail(MR_ERR_UNSUPPORTED, "several fields are marched with the uniform sampler only");
+  for (int a = 0; a < n_fields; ++a)
+    for (int b = a + 1; b < n_fields; ++b) {
+      double c1[3], h1[3], R1[3][3], c2[3], h2[3], R2[3][3];
+      field_box(fields[a], c1, h1, R1);
+      field_box(fields[b], c2, h2, R2);
+      if (boxes_overlap(c1, h1, R1, c2, h2, R2))
+        return fail(MR_ERR_INVALID_ARG, "the boxes of fields " + std::to_string(a) + " and " + std::to_string(b) +
+                                            " overlap in the world");
+    }
+  return render_impl(fields, n_fields, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, host_lights, n_lights,
+                     opts, out, workspace, workspace_bytes, stream);
 }
 
 extern "C" mr_status mr_profile_enable(int32_t on) {

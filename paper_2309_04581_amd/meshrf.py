@@ -28,7 +28,8 @@ EXPORTED = [
     "mr_graph_launch", "mr_last_error", "mr_mesh_build_bvh", "mr_mesh_closest_hit", "mr_mesh_destroy",
     "mr_mesh_info", "mr_mesh_refit", "mr_probe_gather", "mr_profile_enable", "mr_profile_read",
     "mr_proposal_grad", "mr_proposal_targets", "mr_proposal_train_step", "mr_rays_from_cameras", "mr_render",
-    "mr_render_graph_create", "mr_render_workspace_size", "mr_version",
+    "mr_render_fields", "mr_render_fields_workspace_size", "mr_render_graph_create", "mr_render_workspace_size",
+    "mr_version",
 ]
 
 
@@ -98,8 +99,11 @@ def lib():
         L.mr_version.restype = C.c_char_p
         L.mr_render_workspace_size.restype = C.c_size_t
         L.mr_render_workspace_size.argtypes = [C.c_int64]
+        L.mr_render_fields_workspace_size.restype = C.c_size_t
+        L.mr_render_fields_workspace_size.argtypes = [C.c_int64, C.c_int32]
         for name in EXPORTED:
-            if name not in ("mr_last_error", "mr_version", "mr_render_workspace_size"):
+            if name not in ("mr_last_error", "mr_version", "mr_render_workspace_size",
+                            "mr_render_fields_workspace_size"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -211,6 +215,24 @@ def mr_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, l
                            C.c_int32(max_bounces), _ptr(per_ray_max_bounces), arr, C.c_int32(nl),
                            C.byref(opts), C.byref(out), _ptr(workspace), C.c_size_t(workspace_bytes),
                            _stream(stream)))
+
+
+def mr_render_fields_workspace_size(n, n_fields):
+    return int(lib().mr_render_fields_workspace_size(C.c_int64(n), C.c_int32(n_fields)))
+
+
+def mr_render_fields(fields, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, lights, opts, out,
+                     workspace, workspace_bytes, stream=None):
+    nl = len(lights)
+    arr = (Light * max(nl, 1))()
+    for i, row in enumerate(lights):
+        arr[i].pos = (C.c_float * 3)(*[float(x) for x in row[:3]])
+        arr[i].intensity = (C.c_float * 3)(*[float(x) for x in row[3:6]])
+    hs = (C.c_void_p * max(len(fields), 1))(*fields)
+    _check(lib().mr_render_fields(hs, C.c_int32(len(fields)), mesh, C.c_int64(n), _ptr(origins), _ptr(dirs),
+                                  C.c_int32(max_bounces), _ptr(per_ray_max_bounces), arr, C.c_int32(nl),
+                                  C.byref(opts), C.byref(out), _ptr(workspace), C.c_size_t(workspace_bytes),
+                                  _stream(stream)))
 
 
 def mr_rays_from_cameras(host_cams, origins, dirs, cam_index=None, capacity=None, stream=None):
@@ -353,6 +375,19 @@ class Renderer:
                   mesh.handle if mesh is not None else None, self.n, origins, dirs,
                   self.max_bounces, per_ray_max_bounces, lights, opts, self.out, self.workspace,
                   self.ws_bytes, stream)
+        return self
+
+    def render_fields(self, fields, mesh, origins, dirs, lights, opts, per_ray_max_bounces=None, stream=None):
+        """Several fields in one scene (mr_render_fields); grows the
+        workspace to the size the field count needs."""
+        need = mr_render_fields_workspace_size(self.n, len(fields))
+        if need > self.ws_bytes:
+            import torch
+            self.workspace = torch.empty(need, dtype=torch.uint8, device=self.workspace.device)
+            self.ws_bytes = need
+        mr_render_fields([f.handle for f in fields], mesh.handle if mesh is not None else None, self.n,
+                         origins, dirs, self.max_bounces, per_ray_max_bounces, lights, opts, self.out,
+                         self.workspace, self.ws_bytes, stream)
         return self
 
 

@@ -520,6 +520,41 @@ def emitter_scene(width=800, height=800) -> Scene:
                  max_bounces=8, occupancy_res=128, occupancy_thresh=0.01)
 
 
+def fields_scene(n_fields=3, width=800, height=450, kind="mid", table_amp=1e-4, spacing=2.9, seed=77,
+                 n_samples=None) -> Scene:
+    """Several NeRF objects in one scene: n copies of the mid (or tiny) field
+    layout with seeds 2, 3, ... (tiny: 1, 2, ...), each turned about y by a
+    seeded angle in [-pi/4, pi/4] and set `spacing` apart along x (a box turned
+    about y spans at most 2 sqrt 2 in x, so the boxes stay disjoint), over a
+    wide diffuse floor with a glass sphere and a mirror cube in front of them;
+    camera 4.8 back.  The segment length covers the far boxes (t in [0.05,
+    8.0]) with about the interval length of the single-field workloads (mid:
+    516 samples, tiny: 128).  Scene.field is the first field; Scene.fields
+    all."""
+    rng = np.random.default_rng(seed)
+    fields = []
+    for k in range(n_fields):
+        f = (mid_field(2 + k, table_amp) if kind == "mid" else tiny_field(1 + k, table_amp))
+        x = (k - (n_fields - 1) / 2.0) * spacing
+        f.pose = pose_matrix(rotation((0.0, 1.0, 0.0), rng.uniform(-math.pi / 4, math.pi / 4)), (x, 0.0, 0.0))
+        fields.append(f)
+    sv, sf = icosphere(4, radius=0.35, center=(-1.45, -0.75, -2.0))
+    cv, cf = cube_triangles((1.45, -0.8, -2.0), 0.6)
+    pv, pf = floor_plane(-1.1, half=7.0)
+    mats = [[GLASS, 1.5, 1.0, 1.0, 1.0], [MIRROR, 1.0, 1.0, 1.0, 1.0], [DIFFUSE, 1.0, 0.7, 0.7, 0.7]]
+    mesh = merge_meshes([(sv, sf, 0), (cv, cf, 1), (pv, pf, 2)], mats)
+    cam = Camera(pos=(0.0, 0.4, -4.8), look_at=(0.0, 0.0, 0.0), fov_deg=60.0, width=width, height=height,
+                 max_bounces=8)
+    if n_samples is None:
+        n_samples = 516 if kind == "mid" else 128
+    sc = Scene(name=f"fields{n_fields}", field=fields[0], mesh=mesh,
+               lights=np.array([[0.0, 2.5, -1.0, 40.0, 40.0, 40.0]], np.float32), cameras=[cam],
+               t_near=0.05, t_far=8.0, n_samples=n_samples, max_bounces=8, occupancy_res=128,
+               occupancy_thresh=0.01)
+    sc.fields = fields
+    return sc
+
+
 def multicam_scene(seed=44) -> Scene:
     return Scene(name="multicam", field=tiny_field(1), mesh=mirror_cube_mesh(),
                  lights=no_lights(), cameras=multicam_cameras(seed), t_near=0.05,

@@ -682,3 +682,99 @@ def test_emitter_sampling_after_refit_matches_oracle():
     r = orc.render(sc2, o, d, sample_emitters=True)
     compare_render(gpu_render(sc2, o, d, mesh=G, sample_emitters=True), r, "emitter sampling after refit",
                    rtol=1e-4, atol=1e-7, max_tie_frac=0.005)
+
+
+# ---------------------------------------------------------------------------
+# several fields in one scene (mr_render_fields)
+# ---------------------------------------------------------------------------
+
+def _fields_gpu(sc, o, d, fields=None, packets=0, use_occupancy=False, occ_res=0, **kw):
+    M = mr()
+    Fs = [M.Field(f) for f in (fields if fields is not None else sc.fields)]
+    if use_occupancy:
+        for F in Fs:
+            F.build_occupancy(occ_res, sc.occupancy_thresh)
+    G = M.Mesh(sc.mesh)
+    R = M.Renderer(len(o), sc.max_bounces)
+    opts = M.make_opts(sc, use_occupancy=use_occupancy, **kw)
+    opts.march_packets = packets
+    R.render_fields(Fs, G, dev(o), dev(d), sc.lights, opts)
+    torch.cuda.synchronize()
+    return dict(radiance=host(R.radiance), throughput=host(R.throughput), bounces=host(R.bounces),
+                hit_ids=host(R.hit_ids), counters=host(R.counters))
+
+
+@pytest.mark.parametrize("n_fields,packets", [(2, 0), (3, 0), (3, -1), (3, 99)])
+def test_several_fields_match_oracle(n_fields, packets):
+    """Two or three amplitude-1 tiny fields, turned and set side by side over
+    a floor with a glass sphere and a mirror cube, 48x27: one march pass per
+    field composited in box order against the oracle's summed medium; the
+    field-sample count equals the oracle's."""
+    sc = sg.fields_scene(n_fields, 48, 27, kind="tiny", table_amp=1.0)
+    o, d = oracle_camera_rays(sc)
+    r = orc.render(sc, o, d, fields=sc.fields)
+    assert (r["samples"] > 0).mean() > 0.3
+    g = _fields_gpu(sc, o, d, packets=packets)
+    compare_render(g, r, f"{n_fields} fields packets={packets}", rtol=1e-3, atol=1e-6)
+    assert int(g["counters"][0]) == int(r["samples"].sum())
+
+
+def test_several_fields_with_occupancy_and_sample_shadows_match_oracle():
+    """Three copies of the sparse field (its occupancy threshold in a gap of
+    the cells' densities), each with its own grid, and the per-sample shadow
+    mask toward the scene's light."""
+    sc = sg.fields_scene(3, 48, 27, kind="tiny")
+    base = _sparse_field()
+    fields = []
+    for f in sc.fields:
+        g = copy.deepcopy(base)
+        g.pose = f.pose
+        fields.append(g)
+    sc.fields = fields
+    sc.occupancy_thresh = _unambiguous_threshold(base, 32)
+    bits, margin = orc.occupancy(base, 32, sc.occupancy_thresh)
+    assert np.abs(margin).min() > 5e-7
+    o, d = oracle_camera_rays(sc)
+    r = orc.render(sc, o, d, fields=fields, field_occupancy=[bits] * 3, shadow_mask=0.2)
+    g = _fields_gpu(sc, o, d, use_occupancy=True, occ_res=32, shadow_mask=0.2)
+    compare_render(g, r, "3 sparse fields, occupancy, sample shadows", rtol=1e-3, atol=1e-6)
+
+
+def test_one_field_list_is_mr_render():
+    """mr_render_fields with one field is mr_render, bit for bit."""
+    sc = sg.tiny_scene(table_amp=1.0)
+    o, d = oracle_camera_rays(sc)
+    a = gpu_render(sc, o, d)
+    b = _fields_gpu(sc, o, d, fields=[sc.field])
+    for k in ("radiance", "throughput", "bounces", "hit_ids"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_several_fields_validated():
+    """Overlapping boxes, the proposal sampler, more than 8 fields and a
+    missing occupancy grid are refused; boxes that touch are accepted."""
+    M = mr()
+    sc = sg.tiny_scene()
+    o, d = oracle_camera_rays(sc)
+    G = M.Mesh(sc.mesh)
+    R = M.Renderer(len(o), sc.max_bounces)
+
+    def placed(x, angle=0.0):
+        f = copy.deepcopy(sc.field)
+        f.pose = sg.pose_matrix(sg.rotation((0.0, 1.0, 0.0), angle), (x, 0.0, 0.0))
+        return M.Field(f)
+    opts = M.make_opts(sc)
+    R.render_fields([placed(0.0), placed(2.0)], G, dev(o), dev(d), sc.lights, opts)    # touching
+    with pytest.raises(M.MrError, match="overlap"):
+        R.render_fields([placed(0.0), placed(1.9)], G, dev(o), dev(d), sc.lights, opts)
+    with pytest.raises(M.MrError, match="overlap"):
+        R.render_fields([placed(0.0), placed(2.3, math.pi / 4)], G, dev(o), dev(d), sc.lights, opts)
+    R.render_fields([placed(0.0), placed(2.5, math.pi / 4)], G, dev(o), dev(d), sc.lights, opts)
+    P = M.Field(sg.make_proposal(), table_dtype=M.MR_F32)
+    with pytest.raises(M.MrError):
+        R.render_fields([placed(0.0), placed(3.0)], G, dev(o), dev(d), sc.lights,
+                        M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P))
+    with pytest.raises(M.MrError):
+        R.render_fields([placed(3.0 * k) for k in range(9)], G, dev(o), dev(d), sc.lights, opts)
+    with pytest.raises(M.MrError):
+        R.render_fields([placed(0.0), placed(3.0)], G, dev(o), dev(d), sc.lights, M.make_opts(sc, use_occupancy=True))
