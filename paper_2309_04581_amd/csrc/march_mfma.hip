@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) void k_query_mfma(FieldView F, const TabT* __r
     }
     if (feat_out)
 #pragma unroll
-      for (int k = 0; k < LY::NF; ++k) feat_out[p * 2 * NL + g * LY::NF + k] = fe[k];
+      for (int k = 0; k < LY::NF; ++k) feat_out[p * 2 * NL + frag_k(0, false, LY::NF, k, g, 0)] = fe[k];
     if (raw_out)
 #pragma unroll
       for (int v = 0; v < 4; ++v) raw_out[p * 16 + 4 * g + v] = raw[v];

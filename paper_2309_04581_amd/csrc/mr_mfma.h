@@ -38,7 +38,12 @@ struct FragLayout {
 // Layer kinds: 0 density layer 1 (features), 1 layers over 64 hidden units,
 // 2 colour layer 1 over the 16 raw outputs.
 __host__ __device__ inline int frag_k(int kind, bool bf, int nf, int ks, int g, int e) {
-  if (kind == 0) return bf ? g * nf + 4 * ks + e : g * nf + ks;
+  if (kind == 0) {
+    // lane group g holds levels g, g + 4, g + 8, ... (register r: level 4 (r / 2) + g, feature r % 2)
+    (void)nf;
+    const int r = bf ? 4 * ks + e : ks;
+    return 8 * (r >> 1) + 2 * g + (r & 1);
+  }
   if (kind == 1) return bf ? ks * 16 + 4 * g + e : (ks / 4) * 16 + 4 * g + (ks % 4);
   return bf ? 4 * g + e : 4 * g + ks;
 }
@@ -62,7 +67,17 @@ __device__ __forceinline__ uint2 pack_bf16(float a, float b, float c, float d) {
   return make_uint2(bf16_bits(a) | (bf16_bits(b) << 16), bf16_bits(c) | (bf16_bits(d) << 16));
 }
 
-// Hash features of the lane's level group for one point (2 per level).
+// ReLU on the bit pattern: positive floats order like positive integers and
+// every value with the sign bit set becomes +0, so max_i32(bits, 0) is max(x,
+// 0) in one instruction (fmaxf on a matrix-core result first quiets a
+// possible signalling NaN, a second instruction per value).
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
+// Hash features of the lane's levels for one point (2 per level).  Lane
+// group g takes levels g, g + 4, g + 8, ...: at each step ll the four
+// groups hold four consecutive levels, so the dense coarse levels fall
+// together and the dense-or-hashed choice is uniform across the wave at all
+// but one step (it is per lane).
 template <int NL, typename TabT>
 __device__ __forceinline__ void encode_group(const FieldView& F, const TabT* __restrict__ table, float px, float py,
                                              float pz, int g, float* fe) {
@@ -72,7 +87,7 @@ __device__ __forceinline__ void encode_group(const FieldView& F, const TabT* __r
   const size_t T = (size_t)F.table_mask + 1u;
 #pragma unroll
   for (int ll = 0; ll < LPG; ++ll) {
-    const int l = g * LPG + ll;
+    const int l = ll * 4 + g;
     uint32_t idx[8];
     float w[8];
     level_corners(F, l, xh, yh, zh, idx, w);
@@ -122,7 +137,7 @@ __device__ __forceinline__ void mlp_tile(const uint32_t* __restrict__ W, const f
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) h[mt][v] = fmaxf(h[mt][v], 0.0f);
+    for (int v = 0; v < 4; ++v) h[mt][v] = relu(h[mt][v]);
   // density layer 2: 16 raw outputs
   // four independent accumulator chains (one per hidden tile), summed at the end
   f4v rp[4] = {zero, zero, zero, zero};
@@ -161,7 +176,7 @@ __device__ __forceinline__ void mlp_tile(const uint32_t* __restrict__ W, const f
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) c[mt][v] = fmaxf(c[mt][v], 0.0f);
+    for (int v = 0; v < 4; ++v) c[mt][v] = relu(c[mt][v]);
   if constexpr (CL == 2) {
     f4v c2[4] = {zero, zero, zero, zero};
     if constexpr (!BF) {
@@ -182,7 +197,7 @@ __device__ __forceinline__ void mlp_tile(const uint32_t* __restrict__ W, const f
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) c[mt][v] = fmaxf(c2[mt][v], 0.0f);
+      for (int v = 0; v < 4; ++v) c[mt][v] = relu(c2[mt][v]);
   }
   // 3-wide output layer on the vector units, reduced over the four lane groups
   const float* Wo = reinterpret_cast<const float*>(W) + LY::OUT;
