@@ -320,20 +320,29 @@ def test_render_mid_scene_small_image_matches_oracle(packets):
     assert (g["hit_ids"] >= 0).sum() > 500
 
 
-def test_render_mid_scene_full_size_sampled():
-    """800x800 at full settings; 400 seeded rays re-rendered one by one by the oracle."""
+@pytest.mark.parametrize("use_occupancy", [False, True])
+def test_render_mid_scene_full_size_sampled(use_occupancy):
+    """800x800 at full settings, with the occupancy grid as the benchmark
+    times it (128^3, threshold 0.01, the oracle's own grid on its side: every
+    cell is occupied by a margin far above FP32 noise); 400 seeded rays
+    re-rendered one by one by the oracle."""
     sc = sg.mid_scene()
     M = mr()
     o, d, _ = M.camera_rays(sg.cameras_array(sc.cameras))
     F, G = M.Field(sc.field), M.Mesh(sc.mesh)
+    bits = None
+    if use_occupancy:
+        F.build_occupancy(sc.occupancy_res, sc.occupancy_thresh)
+        bits, margin = orc.occupancy(sc.field, sc.occupancy_res, sc.occupancy_thresh)
+        assert np.abs(margin).min() > 1e-3
     R = M.Renderer(o.shape[0], sc.max_bounces)
-    R.render(F, G, o, d, sc.lights, M.make_opts(sc))
+    R.render(F, G, o, d, sc.lights, M.make_opts(sc, use_occupancy=use_occupancy))
     g = dict(radiance=host(R.radiance), throughput=host(R.throughput), bounces=host(R.bounces),
              hit_ids=host(R.hit_ids))
     rng = np.random.default_rng(104)
     idx = np.sort(rng.choice(o.shape[0], 400, replace=False))
     oo, dd = host(o)[idx], host(d)[idx]
-    r = orc.render(sc, oo, dd, ray_ids=idx)
+    r = orc.render(sc, oo, dd, ray_ids=idx, occupancy_bits=bits)
     sub = {k: v[idx] for k, v in g.items()}
     compare_render(sub, r, "mid 800x800 sample")
     # whole-image properties

@@ -188,3 +188,39 @@ def test_proposal_render_with_sample_shadows_matches_oracle(fieldkind, packets):
              hit_ids=host(R.hit_ids))
     tol = 1e-4 if fieldkind == "tiny" else 1e-3
     compare_render(g, r, f"proposal {fieldkind} sample shadows packets={packets}", rtol=tol, atol=1e-6)
+
+
+def test_proposal_fp16_full_size_sampled():
+    """The benchmark's second configuration at full size: 800x800 mid scene,
+    FP16 table + BF16 MLPs, FP16 proposal table, 32 + 32 samples, occupancy
+    grid, default packets.  The oracle runs on the parameters as the GPU holds
+    them (table and proposal table rounded to FP16, BF16-held layers rounded)
+    with a seeded proposal (trained weights would come from the GPU); 400
+    seeded rays.  Hit ids and bounces exact off ties; radiance within 2e-3
+    relative (the BF16 rounding of layer inputs, measured at most 2e-3 on the
+    amplitude-1 field) and 1e-5 absolute."""
+    import bench
+    M = mr()
+    sc = sg.mid_scene()
+    prop = sg.make_proposal()
+    o, d, _ = M.camera_rays(sg.cameras_array(sc.cameras))
+    F = M.Field(sc.field, table_dtype=M.MR_F16, mlp_dtype=M.MR_BF16)
+    F.build_occupancy(sc.occupancy_res, sc.occupancy_thresh)
+    P = M.Field(prop, table_dtype=M.MR_F16)
+    G = M.Mesh(sc.mesh)
+    R = M.Renderer(o.shape[0], sc.max_bounces)
+    R.render(F, G, o, d, sc.lights, M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P, use_occupancy=True))
+    g = dict(radiance=host(R.radiance), throughput=host(R.throughput), bounces=host(R.bounces),
+             hit_ids=host(R.hit_ids))
+    scr = sg.mid_scene()
+    scr.field = bench._rounded_field(sg, sc.field)
+    propr = sg.make_proposal()
+    propr.table = prop.table.astype(np.float16).astype(np.float32)
+    bits, margin = orc.occupancy(scr.field, sc.occupancy_res, sc.occupancy_thresh)
+    assert np.abs(margin).min() > 1e-3
+    rng = np.random.default_rng(106)
+    idx = np.sort(rng.choice(o.shape[0], 400, replace=False))
+    r = orc.render(scr, host(o)[idx], host(d)[idx], ray_ids=idx, occupancy_bits=bits, proposal=propr,
+                   n_prop=32, n_fine=32)
+    compare_render({k: v[idx] for k, v in g.items()}, r, "proposal fp16 800x800 sample", rtol=2e-3, atol=1e-5)
+    assert np.all(g["throughput"] <= 1 + 1e-6) and np.all(g["radiance"] >= 0)
