@@ -52,10 +52,9 @@ __device__ __forceinline__ f4v mma(float a, float b, f4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 __device__ __forceinline__ f4v mma(uint2 a, uint2 b, f4v c) {
-  s4v av, bv;
-  av[0] = (short)(a.x & 0xFFFF); av[1] = (short)(a.x >> 16); av[2] = (short)(a.y & 0xFFFF); av[3] = (short)(a.y >> 16);
-  bv[0] = (short)(b.x & 0xFFFF); bv[1] = (short)(b.x >> 16); bv[2] = (short)(b.y & 0xFFFF); bv[3] = (short)(b.y >> 16);
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
+  // four bf16 values per operand, element 0 in the low half of .x
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4v, a), __builtin_bit_cast(s4v, b), c, 0, 0,
+                                                   0);
 }
 
 // round-to-nearest-even FP32 -> bf16 bits
@@ -63,8 +62,17 @@ __device__ __forceinline__ uint32_t bf16_bits(float f) {
   const uint32_t u = __float_as_uint(f);
   return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
 }
+// Two FP32 values to bf16 (round to nearest even), the first in the low half:
+// one v_cvt_pk_bf16_f32 on gfx950, which rounds every finite value as
+// bf16_bits does.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack2_bf16(float a, float b) {
+  const f32x2_t v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
 __device__ __forceinline__ uint2 pack_bf16(float a, float b, float c, float d) {
-  return make_uint2(bf16_bits(a) | (bf16_bits(b) << 16), bf16_bits(c) | (bf16_bits(d) << 16));
+  return make_uint2(pack2_bf16(a, b), pack2_bf16(c, d));
 }
 
 // ReLU on the bit pattern: positive floats order like positive integers and
