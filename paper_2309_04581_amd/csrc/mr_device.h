@@ -172,7 +172,20 @@ __device__ __forceinline__ void sh_eval(float x, float y, float z, float* o) {
   }
 }
 
-__device__ __forceinline__ float softplusf(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
+// e^x on the hardware base-2 exponential: 2^(x log2 e), about 1 ulp.
+__device__ __forceinline__ float exp_hw(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+
+// softplus(x) = max(x, 0) + log1p(e^-|x|) on the hardware exponential and
+// base-2 logarithm.  log1p(v) = log(w) v / (w - 1) with w = 1 + v rounded
+// (Goldberg, "What every computer scientist should know about
+// floating-point arithmetic", 1991): the ratio cancels the rounding of 1 + v,
+// so small densities keep their relative accuracy; for w = 1, log1p(v) = v.
+__device__ __forceinline__ float softplusf(float x) {
+  const float v = exp_hw(-fabsf(x));
+  const float w = 1.0f + v;
+  const float l = w == 1.0f ? v : 0.6931471805599453f * __builtin_amdgcn_logf(w) * (v / (w - 1.0f));
+  return fmaxf(x, 0.0f) + l;
+}
 
 // ---------------------------------------------------------------------------
 // density MLP on one sample per lane (occupancy grid), weights broadcast from

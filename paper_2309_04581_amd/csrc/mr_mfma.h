@@ -221,9 +221,9 @@ __device__ __forceinline__ void mlp_tile(const uint32_t* __restrict__ W, const f
     s += __shfl_xor(s, 32, 64);
     o[ch] = s;
   }
-  rgb[0] = expf(o[0]);
-  rgb[1] = expf(o[1]);
-  rgb[2] = expf(o[2]);
+  rgb[0] = exp_hw(o[0]);
+  rgb[1] = exp_hw(o[1]);
+  rgb[2] = exp_hw(o[2]);
 }
 
 // SH contribution to colour layer 1 for hidden rows mt*16 + 4g + v: the

@@ -181,6 +181,22 @@ def test_field_query_matches_oracle(kind, amp):
     assert_close_rel(host(out["rgb"]), ref["rgb"], 1e-4, 1e-7, "rgb")
 
 
+@pytest.mark.parametrize("offset", [-9.0, -5.0, 5.0])
+def test_field_query_sigma_over_the_softplus_range(offset):
+    """Amplitude-1 tiny field with its density offset moved so that sigma
+    spans small (softplus of -12 .. -6: the log1p term is the whole value)
+    and large values; sigma within 2e-5 relative of the oracle's."""
+    M = mr()
+    f = sg.tiny_field(table_amp=1.0)
+    f.density_offset = offset
+    x, d = lattice_points(f, 4000, seed=107)
+    out = M.Field(f).query(dev(x), dev(d), want_feat=False, want_raw=False)
+    ref = orc.field_batch(f, x, d)
+    assert ref["sigma"].min() < 1e-2 or offset > 0
+    assert_close_rel(host(out["sigma"]), ref["sigma"], 2e-5, 1e-12, f"sigma offset {offset}")
+    assert_close_rel(host(out["rgb"]), ref["rgb"], 1e-4, 1e-7, f"rgb offset {offset}")
+
+
 @pytest.mark.parametrize("kind", ["tiny", "mid"])
 def test_field_query_random_points_literal_field(kind):
     """Arbitrary FP32 points on the configured fields (table U(-1e-4, 1e-4)):
