@@ -138,6 +138,12 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(RayQueue q, const int* __
   }
 }
 
+// Queues of at most kTailRays rays have their closest hits traced by
+// k_trace_wide (one wave per ray) after the shade pass, not by it.
+constexpr int kTailRays = 2048;   // queues this short are traced a wave per ray
+constexpr int kWideFront = 512;   // frontier nodes per wave and level
+constexpr int kWideWaves = 4;     // waves per block
+
 // ---------------------------------------------------------------------------
 // surface interaction, shadow rays, roulette, termination and compaction
 // ---------------------------------------------------------------------------
@@ -347,14 +353,17 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade(RayQueue qi, const int* _
       qo.rid[slot] = rid;
       qo.depth[slot] = ndepth;
       // closest hit of the new segment, whose range starts at the spawn point
-      const RayPre nr = ray_pre(v3(nox, noy, noz), v3(ndx, ndy, ndz));
-      float th = INFINITY;
-      const int hp = bvh_trace<false>(M.bvh, nr, span, th, stack + threadIdx.x, tstack + threadIdx.x, kTraceBlock);
-      qo.hit_t[slot] = hp >= 0 ? th : INFINITY;
-      qo.hit_p[slot] = hp;
-      const int nseg = ndepth & 0xFFFF;
-      if (hit_ids && nseg < hit_stride)
-        hit_ids[(int64_t)rid * hit_stride + nseg] = hp >= 0 ? __float_as_int(M.bvh.tris[3 * hp].w) : -1;
+      // (for short queues k_trace_wide traces it, a wave per ray)
+      if (cnt > kTailRays) {
+        const RayPre nr = ray_pre(v3(nox, noy, noz), v3(ndx, ndy, ndz));
+        float th = INFINITY;
+        const int hp = bvh_trace<false>(M.bvh, nr, span, th, stack + threadIdx.x, tstack + threadIdx.x, kTraceBlock);
+        qo.hit_t[slot] = hp >= 0 ? th : INFINITY;
+        qo.hit_p[slot] = hp;
+        const int nseg = ndepth & 0xFFFF;
+        if (hit_ids && nseg < hit_stride)
+          hit_ids[(int64_t)rid * hit_stride + nseg] = hp >= 0 ? __float_as_int(M.bvh.tris[3 * hp].w) : -1;
+      }
     }
   }
   }
@@ -372,6 +381,144 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade(RayQueue qi, const int* _
       if (b) atomicAdd(stats + 2, b);
       if (c) atomicAdd(stats + 3, c);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Closest hit of a short queue: one wave per ray, breadth first.  The nodes
+// the ray enters at one depth are expanded together, one per lane, so a deep
+// traversal (a ray leaving a closed, finely tessellated surface enters
+// hundreds of nested boxes) costs one dependent load per level instead of one
+// per node.  Each level's frontier is pruned by the best hit over the whole
+// wave, and the result is the same lexicographic minimum of (t, id) as the
+// per-thread traversal (the same box and triangle tests, limits that are
+// never tighter).  A frontier that outgrows its LDS area hands the ray to the
+// per-thread traversal on lane 0.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__global__ __launch_bounds__(64 * kWideWaves) void k_trace_wide(RayQueue q, const int* __restrict__ gate_count,
+                                                               const int* __restrict__ count, int* __restrict__ work,
+                                                               BvhView B, float tmax, int32_t* __restrict__ hit_ids,
+                                                               int hit_stride) {
+  __shared__ int s_node[kWideWaves][2][kWideFront];
+  __shared__ float s_tin[kWideWaves][2][kWideFront];
+  __shared__ int s_stack[kWideWaves][kStack];
+  __shared__ float s_tstack[kWideWaves][kStack];
+  if (*gate_count > kTailRays) return;   // the shade pass traced this queue itself
+  const int cnt = *count;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  while (true) {
+    int r = 0;
+    if (lane == 0) r = atomicAdd(work, 1);
+    r = __shfl(r, 0, 64);
+    if (r >= cnt) break;
+    const RayPre R = ray_pre(v3(q.ox[r], q.oy[r], q.oz[r]), v3(q.dx[r], q.dy[r], q.dz[r]));
+    float tb = tmax;                     // best hit of the wave: (tb, idb) at triangle pb
+    int pb = -1, idb = 0x7fffffff;
+    int n = B.n_prims > 0 ? 1 : 0, cur = 0;
+    bool overflow = false;
+    if (lane == 0) {
+      s_node[w][0][0] = 0;
+      s_tin[w][0][0] = 0.0f;
+    }
+    wave_lds_sync();
+    while (n > 0) {
+      float lt = tb;
+      int lp = pb, lid = idb;
+      int nn = 0;
+      const float reach = tb * 1.0000003576f;
+      for (int base = 0; base < n; base += 64) {
+        const int i = base + lane;
+        int ch0 = -1, ch1 = -1;
+        float tc0 = 0.0f, tc1 = 0.0f;
+        if (i < n && s_tin[w][cur][i] <= reach) {
+          const BvhNode nd = B.nodes[s_node[w][cur][i]];
+          const float t0 = nd.d.x < 0 ? INFINITY : box_hit(R, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, tb);
+          const float t1 = nd.d.y < 0 ? INFINITY : box_hit(R, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, tb);
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const float tc = c == 0 ? t0 : t1;
+            if (tc == INFINITY) continue;
+            const int child = c == 0 ? nd.d.x : nd.d.y, cn = c == 0 ? nd.d.z : nd.d.w;
+            if (cn > 0) {
+              for (int pp = child; pp < child + cn; ++pp) {
+                const float4 q0 = B.tris[3 * pp], q1 = B.tris[3 * pp + 1], q2 = B.tris[3 * pp + 2];
+                const float t = tri_hit(R, q0, q1, q2);
+                const int id = __float_as_int(q0.w);
+                if (t <= tmax && (t < lt || (t == lt && id < lid))) {
+                  lt = t;
+                  lp = pp;
+                  lid = id;
+                }
+              }
+            } else if (c == 0) {
+              ch0 = child;
+              tc0 = tc;
+            } else {
+              ch1 = child;
+              tc1 = tc;
+            }
+          }
+        }
+        // inner children enter the next level's frontier in lane order
+        const unsigned long long m0 = __ballot(ch0 >= 0), m1 = __ballot(ch1 >= 0);
+        const int p0 = nn + __popcll(m0 & below);
+        const int p1 = nn + __popcll(m0) + __popcll(m1 & below);
+        if (ch0 >= 0 && p0 < kWideFront) {
+          s_node[w][cur ^ 1][p0] = ch0;
+          s_tin[w][cur ^ 1][p0] = tc0;
+        }
+        if (ch1 >= 0 && p1 < kWideFront) {
+          s_node[w][cur ^ 1][p1] = ch1;
+          s_tin[w][cur ^ 1][p1] = tc1;
+        }
+        nn += __popcll(m0) + __popcll(m1);
+      }
+      // best over the wave, lexicographic in (t, id)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const float ot = __shfl_xor(lt, off, 64);
+        const int oid = __shfl_xor(lid, off, 64), op = __shfl_xor(lp, off, 64);
+        if (ot < lt || (ot == lt && oid < lid)) {
+          lt = ot;
+          lid = oid;
+          lp = op;
+        }
+      }
+      tb = lt;
+      pb = lp;
+      idb = lid;
+      if (nn > kWideFront) {
+        overflow = true;
+        break;
+      }
+      n = nn;
+      cur ^= 1;
+      wave_lds_sync();
+    }
+    if (overflow) {
+      if (lane == 0) {
+        float th = tmax;
+        pb = bvh_trace<false>(B, R, tmax, th, &s_stack[w][0], &s_tstack[w][0], 1);
+        tb = th;
+      }
+      pb = __shfl(pb, 0, 64);
+      tb = __shfl(tb, 0, 64);
+    }
+    if (lane == 0) {
+      q.hit_t[r] = pb >= 0 ? tb : INFINITY;
+      q.hit_p[r] = pb;
+      const int seg = q.depth[r] & 0xFFFF;
+      if (hit_ids && seg < hit_stride)
+        hit_ids[(int64_t)q.rid[r] * hit_stride + seg] = pb >= 0 ? __float_as_int(B.tris[3 * pb].w) : -1;
+    }
+    wave_lds_sync();
   }
 }
 
@@ -722,6 +869,8 @@ mr_status render_impl(const mr_field* const* fields, int n_fields, const mr_mesh
   const int shade_blocks =
       persistent_blocks(reinterpret_cast<const void*>(k_shade), kTraceBlock, opts->stage_blocks_per_cu, tiles);
   const int packet_segments = opts->march_packets == 0 ? 1 : std::max(0, opts->march_packets);
+  const int wide_blocks = (int)std::max<int64_t>(
+      1, std::min<int64_t>((std::min<int64_t>(n, kTailRays) + kWideWaves - 1) / kWideWaves, (int64_t)device_cus() * 4));
   for (int b = 0; b <= max_bounces; ++b) {
     RayQueue& qi = Q[b & 1];
     RayQueue& qo = Q[(b + 1) & 1];
@@ -763,6 +912,14 @@ mr_status render_impl(const mr_field* const* fields, int n_fields, const mr_mesh
       StageTimer tm(2, st);
       hipLaunchKernelGGL(k_shade, dim3(shade_blocks), dim3(kTraceBlock), 0, st, qi, counts + b, swork + b, tile, qo,
                          counts + b + 1, mv, S, ro, P.span, out->hit_ids, out->hit_ids ? out->hit_stride : 0, stats);
+      MR_HIP(hipGetLastError());
+    }
+    if (b < max_bounces) {
+      // closest hits of the next segment when this queue is short (the kernel
+      // returns at once otherwise)
+      StageTimer tm(0, st);
+      hipLaunchKernelGGL(k_trace_wide, dim3(wide_blocks), dim3(64 * kWideWaves), 0, st, qo, counts + b, counts + b + 1,
+                         twork + b + 1, mv.bvh, P.span, out->hit_ids, out->hit_ids ? out->hit_stride : 0);
       MR_HIP(hipGetLastError());
     }
   }
