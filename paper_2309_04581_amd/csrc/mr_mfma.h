@@ -57,14 +57,8 @@ __device__ __forceinline__ f4v mma(uint2 a, uint2 b, f4v c) {
                                                    0);
 }
 
-// round-to-nearest-even FP32 -> bf16 bits
-__device__ __forceinline__ uint32_t bf16_bits(float f) {
-  const uint32_t u = __float_as_uint(f);
-  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-}
 // Two FP32 values to bf16 (round to nearest even), the first in the low half:
-// one v_cvt_pk_bf16_f32 on gfx950, which rounds every finite value as
-// bf16_bits does.
+// one v_cvt_pk_bf16_f32 on gfx950.
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t pack2_bf16(float a, float b) {
