@@ -268,6 +268,187 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
 }
 
+// ---------------------------------------------------------------------------
+// Packets with specialised waves: producer waves take the 16-ray packets,
+// place the samples and gather their hash features (vector units and memory);
+// consumer waves, one per producer, run the MLP tiles on the matrix cores and
+// composite.  A pair hands tiles over through two LDS slots, so that while a
+// consumer's MFMAs run, the producer on the same SIMD gathers the next tile:
+// the two kinds of work overlap by construction instead of by the scheduler's
+// chance.  Same samples, same arithmetic and the same results as
+// march_packet.
+// ---------------------------------------------------------------------------
+constexpr int kPcPairs = 4;                 // producer/consumer pairs per block
+constexpr int kPcThreads = 128 * kPcPairs;  // waves 0..3 produce, 4..7 consume
+constexpr long long kPcSpin = 1ll << 26;    // polls before a wait gives up (seconds)
+enum { kSlotEmpty = 0, kSlotStart = 1, kSlotTile = 2, kSlotEnd = 3, kSlotDone = 4 };
+
+template <int NF>
+struct PcSlot {
+  float feat[NF][64];   // lane (g, j)'s features of column j, as the MFMA B operand takes them
+  float D[16];          // interval length of column j (0: no sample there)
+  float dir[16][3];     // START: column j's ray direction in the field frame
+  int r[16];            // START: column j's queue index (-1: no ray)
+  int state;
+};
+
+__device__ __forceinline__ int pc_load(const int* st) {
+  return __hip_atomic_load(st, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void pc_store(int* st, int v) {
+  __hip_atomic_store(st, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// Wait until the slot is empty (producer) or holds a message (consumer);
+// false if the wait gave up (then the wave stops: a bound, not a protocol).
+__device__ __forceinline__ bool pc_wait(const int* st, bool want_empty) {
+  for (long long i = 0; i < kPcSpin; ++i) {
+    const int v = pc_load(st);
+    if ((v == kSlotEmpty) == want_empty) return true;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return false;
+}
+
+template <int NL, int SH, int CL, typename TabT, bool BF>
+__global__ __launch_bounds__(kPcThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_march_pc(RayQueue q, const int* __restrict__ count,
+                                                         int* __restrict__ work, FieldView F,
+                                                         const TabT* __restrict__ table,
+                                                         const uint32_t* __restrict__ frags, MarchParams P,
+                                                         unsigned long long* __restrict__ stats,
+                                                         int* __restrict__ gave_up) {
+  using LY = FragLayout<NL, SH, CL, BF>;
+  constexpr int NF = LY::NF;
+  __shared__ __align__(16) uint32_t sW[LY::TOTAL];
+  __shared__ PcSlot<NF> slots[kPcPairs][2];
+  for (int i = threadIdx.x; i < LY::TOTAL; i += blockDim.x) sW[i] = frags[i];
+  if (threadIdx.x < kPcPairs * 2) slots[threadIdx.x >> 1][threadIdx.x & 1].state = kSlotEmpty;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+  const int wave = threadIdx.x >> 6, pair = wave % kPcPairs;
+  const bool producer = wave < kPcPairs;
+  PcSlot<NF>* sl = slots[pair];
+  int s = 0;
+  unsigned long long nsamp = 0;
+  bool ok = true;
+  if (producer) {
+    const int cnt = *count;
+    const bool use_occ = P.use_occupancy && F.occ;
+    const float delta = P.delta;
+    WorkQueue wq(work, cnt, P.chunk, 16);
+    for (int base = wq.next(lane); base >= 0 && ok; base = wq.next(lane)) {
+      const PacketRay R = packet_ray(q, wq.map(base + j), cnt, F);
+      bool live = R.live;
+      float t_a = 0.0f, lo = 0.0f, hi = 0.0f;
+      int k0 = P.n_samples, k1 = 0;
+      if (live) {
+        t_a = (q.depth[R.r] & 0xFFFF) == 0 ? P.t_near : 0.0f;
+        float box0, box1;
+        live = slab_box(F, R.ox, R.oy, R.oz, R.dx, R.dy, R.dz, box0, box1);
+        if (live) {
+          lo = fmaxf(t_a, box0);
+          hi = fminf(fminf(t_a + P.span, q.hit_t[R.r]), box1);
+          live = hi > lo;
+        }
+        if (live) {
+          k0 = max(0, (int)floorf((lo - t_a) / delta) - 1);
+          k1 = min(P.n_samples, (int)ceilf((hi - t_a) / delta) + 1);
+        }
+      }
+      int kmin = k0, kmax = k1;
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) {
+        kmin = min(kmin, __shfl_xor(kmin, off, 16));
+        kmax = max(kmax, __shfl_xor(kmax, off, 16));
+      }
+      if (kmin >= kmax) continue;
+      // START: the packet's rays
+      if (!(ok = pc_wait(&sl[s].state, true))) break;
+      if (g == 0) {
+        sl[s].r[j] = live ? R.r : -1;
+        sl[s].dir[j][0] = R.dx;
+        sl[s].dir[j][1] = R.dy;
+        sl[s].dir[j][2] = R.dz;
+      }
+      if (lane == 0) pc_store(&sl[s].state, kSlotStart);
+      s ^= 1;
+      for (int k = kmin; k < kmax; ++k) {
+        const float a = fmaxf(t_a + (float)k * delta, lo);
+        const float b = fminf(t_a + (float)(k + 1) * delta, hi);
+        bool valid = live && k >= k0 && k < k1 && b > a;
+        const float tm = 0.5f * (a + b);
+        const float px = R.ox + tm * R.dx, py = R.oy + tm * R.dy, pz = R.oz + tm * R.dz;
+        if (valid && use_occ) valid = occ_lookup(F, px, py, pz);
+        if (__ballot(valid) == 0ull) continue;
+        float fe[NF];
+        encode_group<NL, TabT>(F, table, px, py, pz, g, fe);
+        if (!(ok = pc_wait(&sl[s].state, true))) break;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) sl[s].feat[f][lane] = fe[f];
+        if (g == 0) sl[s].D[j] = valid ? b - a : 0.0f;
+        if (lane == 0) pc_store(&sl[s].state, kSlotTile);
+        s ^= 1;
+        if (g == 0 && valid) ++nsamp;
+      }
+      if (!ok) break;
+      if (!(ok = pc_wait(&sl[s].state, true))) break;
+      if (lane == 0) pc_store(&sl[s].state, kSlotEnd);
+      s ^= 1;
+    }
+    if (ok && (ok = pc_wait(&sl[s].state, true)))
+      if (lane == 0) pc_store(&sl[s].state, kSlotDone);
+  } else {
+    float u[4][4];
+    float T = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
+    int r = -1;
+    while (true) {
+      if (!(ok = pc_wait(&sl[s].state, false))) break;
+      const int kind = pc_load(&sl[s].state);
+      if (kind == kSlotDone) break;
+      if (kind == kSlotStart) {
+        r = sl[s].r[j];
+        const float dx = sl[s].dir[j][0], dy = sl[s].dir[j][1], dz = sl[s].dir[j][2];
+        T = 1.0f;
+        acc0 = acc1 = acc2 = 0.0f;
+        if (lane == 0) pc_store(&sl[s].state, kSlotEmpty);
+        sh_rows<NL, SH, CL, BF>(sW, dx, dy, dz, lane, u);
+      } else if (kind == kSlotTile) {
+        float fe[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) fe[f] = sl[s].feat[f][lane];
+        const float D = sl[s].D[j];
+        if (lane == 0) pc_store(&sl[s].state, kSlotEmpty);
+        float sigma, rgb[3];
+        f4v raw;
+        mlp_tile<NL, SH, CL, BF>(sW, fe, u, F.density_offset, lane, sigma, rgb, raw);
+        const float alpha = D > 0.0f ? -expm1f(-sigma * D) : 0.0f;
+        const float w = T * alpha;
+        acc0 += w * rgb[0];
+        acc1 += w * rgb[1];
+        acc2 += w * rgb[2];
+        T *= 1.0f - alpha;
+      } else {   // kSlotEnd
+        if (lane == 0) pc_store(&sl[s].state, kSlotEmpty);
+        if (r >= 0 && g == 0) {
+          const float tr = q.tr[r], tg = q.tg[r], tb = q.tb[r];
+          q.lr[r] += tr * acc0;
+          q.lg[r] += tg * acc1;
+          q.lb[r] += tb * acc2;
+          q.tr[r] = tr * T;
+          q.tg[r] = tg * T;
+          q.tb[r] = tb * T;
+        }
+      }
+      s ^= 1;
+    }
+  }
+  if (!ok && lane == 0 && gave_up) atomicAdd(gave_up, 1);
+  if (stats) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nsamp += __shfl_xor(nsamp, off, 64);
+    if (lane == 0 && nsamp) atomicAdd(stats + 0, nsamp);
+  }
+}
+
 template <int NL, int SH, int CL, typename TabT, bool BF>
 __global__ __launch_bounds__(256) void k_query_mfma(FieldView F, const TabT* __restrict__ table,
                                                     const uint32_t* __restrict__ frags, int64_t n,
@@ -319,6 +500,15 @@ mr_status launch_march_mode(const mr_field* f, RayQueue q, const int* count, int
                             const BvhView& B, unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st) {
   const uint32_t* fr = BF ? f->frag_bf16_dev : f->frag_f32_dev;
   const TabT* tab = reinterpret_cast<const TabT*>(f->table_dev);
+  if constexpr (PK && !SHADOW) {
+    auto* kp = k_march_pc<NL, SH, CL, TabT, BF>;
+    const int blocks = persistent_blocks(reinterpret_cast<const void*>(kp), kPcThreads, blocks_per_cu,
+                                         (n + 16 * kPcPairs - 1) / (16 * kPcPairs));
+    hipLaunchKernelGGL(kp, dim3(blocks), dim3(kPcThreads), 0, st, q, count, work, f->view, tab, fr, P, stats,
+                       nullptr);
+    MR_HIP(hipGetLastError());
+    return MR_OK;
+  }
   auto* k = k_march_mfma<NL, SH, CL, TabT, BF, PK, SHADOW>;
   const int64_t cap = PK ? (n + 63) / 64 : (n + 3) / 4;
   const int blocks = persistent_blocks(reinterpret_cast<const void*>(k), 256, blocks_per_cu, cap);
