@@ -34,7 +34,7 @@ FP32_MFMA_PEAK_TFLOPS = 157.3   # MI355X published dense FP32 matrix peak
 # counters is reported only while they are unchanged since the counters were taken.
 MARCH_SOURCES = ["march_mfma.hip", "mr_mfma.h", "mr_field_kernels.h", "mr_device.h", "mr_render.h",
                  "mr_common.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_march_mfma_mid_hbm_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_march_mid_hbm_traffic.md")
 
 
 def march_sources_sha256():
@@ -567,7 +567,7 @@ def main():
         "stage_ms_per_step": {"closest_hit": round(stage_ms[0] / args.steps, 3),
                               "march": round(march_ms_per_step, 3),
                               "shade": round(stage_ms[2] / args.steps, 3)},
-        "roofline": {"kernel": "k_march_mfma", "bound": "mfma", "achieved": round(tflops, 2),
+        "roofline": {"kernel": "k_march_pc (camera segment) + k_march_mfma (later segments)", "bound": "mfma", "achieved": round(tflops, 2),
                      "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(tflops / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
                      "traffic_unit": "bytes per launch (L2 fetch + write, copy-calibrated)",
