@@ -379,11 +379,24 @@ __global__ __launch_bounds__(kPcThreads) __attribute__((amdgpu_waves_per_eu(4)))
         const float px = R.ox + tm * R.dx, py = R.oy + tm * R.dy, pz = R.oz + tm * R.dz;
         if (valid && use_occ) valid = occ_lookup(F, px, py, pz);
         if (__ballot(valid) == 0ull) continue;
-        float fe[NF];
-        encode_group<NL, TabT>(F, table, px, py, pz, g, fe);
         if (!(ok = pc_wait(&sl[s].state, true))) break;
+        // the lane's levels in two halves straight into the slot (16 corner
+        // loads in flight instead of 32 keeps the producer within its registers)
+        float xh, yh, zh;
+        to_unit(F, px, py, pz, xh, yh, zh);
+        constexpr int LPG = NL / 4, HL = LPG / 2;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) sl[s].feat[f][lane] = fe[f];
+        for (int h = 0; h < 2; ++h) {
+          float f2[HL][2];
+#pragma unroll
+          for (int i = 0; i < HL; ++i) encode_level<TabT>(F, table, xh, yh, zh, (h * HL + i) * 4 + g, f2[i][0], f2[i][1]);
+#pragma unroll
+          for (int i = 0; i < HL; ++i) {
+            sl[s].feat[2 * (h * HL + i)][lane] = f2[i][0];
+            sl[s].feat[2 * (h * HL + i) + 1][lane] = f2[i][1];
+          }
+          __builtin_amdgcn_sched_barrier(0);   // the second half's loads start here
+        }
         if (g == 0) sl[s].D[j] = valid ? b - a : 0.0f;
         if (lane == 0) pc_store(&sl[s].state, kSlotTile);
         s ^= 1;
@@ -500,7 +513,10 @@ mr_status launch_march_mode(const mr_field* f, RayQueue q, const int* count, int
                             const BvhView& B, unsigned long long* stats, int blocks_per_cu, int64_t n, hipStream_t st) {
   const uint32_t* fr = BF ? f->frag_bf16_dev : f->frag_f32_dev;
   const TabT* tab = reinterpret_cast<const TabT*>(f->table_dev);
-  if constexpr (PK && !SHADOW) {
+  // producer and consumer waves pay for the 16-level layout; with 8 levels a
+  // producer's gather is too short to hide behind a consumer's tile (the cloth
+  // workload ran 6.24 ms per frame with them against 5.56 ms without)
+  if constexpr (PK && !SHADOW && NL == 16) {
     auto* kp = k_march_pc<NL, SH, CL, TabT, BF>;
     const int blocks = persistent_blocks(reinterpret_cast<const void*>(kp), kPcThreads, blocks_per_cu,
                                          (n + 16 * kPcPairs - 1) / (16 * kPcPairs));

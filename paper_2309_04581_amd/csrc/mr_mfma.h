@@ -108,6 +108,27 @@ __device__ __forceinline__ void encode_group(const FieldView& F, const TabT* __r
   }
 }
 
+// The two features of level l at a unit-cube point (one level of encode_group).
+template <typename TabT>
+__device__ __forceinline__ void encode_level(const FieldView& F, const TabT* __restrict__ table, float xh, float yh,
+                                             float zh, int l, float& f0, float& f1) {
+  const size_t T = (size_t)F.table_mask + 1u;
+  uint32_t idx[8];
+  float w[8];
+  level_corners(F, l, xh, yh, zh, idx, w);
+  const TabT* tab = table + (size_t)l * T * 2;
+  float2 e[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) e[c] = load_entry<TabT>(tab, idx[c]);
+  f0 = 0.0f;
+  f1 = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    f0 += w[c] * e[c].x;
+    f1 += w[c] * e[c].y;
+  }
+}
+
 // The MLPs on a 16-sample tile.  fe: this lane's features (its level group,
 // its sample); u[mt][v]: the colour layer-1 contribution of the SH inputs for
 // hidden row mt*16 + 4g + v (per lane's sample); W: fragments in LDS.
