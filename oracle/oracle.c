@@ -685,6 +685,38 @@ static int64_t march_fields(const orc_opts* opt, const double o_world[3], const 
   return ns;
 }
 
+/* Several fields, each sampled by its own proposal.  Reading: with boxes
+ * that do not overlap, every point of the segment belongs to at most one
+ * field, so the summed medium is the fields one after another; each is
+ * marched on its own clipped range with its own proposal (the single-field
+ * proposal march) in the order the ray enters the boxes. */
+static int64_t march_fields_proposal(const orc_opts* opt, const double o_world[3], const double d_world[3],
+                                     double t_a, double t_hit, double T[3], double L[3], int* tie,
+                                     const shadow_ctx* sh_in) {
+  enum { MAXF = 16 };
+  int nf = opt->n_fields < MAXF ? opt->n_fields : MAXF;
+  double entry[MAXF];
+  int order[MAXF];
+  for (int k = 0; k < nf; ++k) {
+    double of[3], df[3], b0, b1;
+    world_to_field(opt->fields[k], o_world, d_world, of, df);
+    entry[k] = slab(opt->fields[k], of, df, &b0, &b1) ? b0 : INFINITY;
+    int j = k;
+    while (j > 0 && entry[order[j - 1]] > entry[k]) { order[j] = order[j - 1]; --j; }
+    order[j] = k;
+  }
+  int64_t ns = 0;
+  for (int i = 0; i < nf; ++i) {
+    const int k = order[i];
+    orc_opts fo = *opt;
+    fo.proposal = opt->field_proposals[k];
+    fo.occ = opt->field_occ ? opt->field_occ[k] : NULL;
+    fo.occ_res = opt->field_occ_res ? opt->field_occ_res[k] : 0;
+    ns += march(opt->fields[k], &fo, o_world, d_world, t_a, t_hit, T, L, tie, sh_in);
+  }
+  return ns;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Surface interaction (Eq. 12-13): perfect mirror, smooth dielectric with   */
 /* exact unpolarised Fresnel (reflect with probability R, else refract),     */
@@ -863,7 +895,10 @@ static void render_ray(const job_t* J, int64_t r) {
     tie |= t_tie;
     if (J->out->hit_ids) J->out->hit_ids[r * stride + s] = hit;
     shadow_ctx sh = {m, J->lights, J->n_lights, opt->shadow_mask, NULL, NULL};
-    if (opt->n_fields > 0)
+    if (opt->n_fields > 0 && opt->field_proposals)
+      nsamp += march_fields_proposal(opt, o, d, t_a, hit >= 0 ? t_hit : INFINITY, T, L, &tie,
+                                     opt->sample_shadows && m && J->n_lights > 0 ? &sh : NULL);
+    else if (opt->n_fields > 0)
       nsamp += march_fields(opt, o, d, t_a, hit >= 0 ? t_hit : INFINITY, T, L, &tie,
                             opt->sample_shadows && m && J->n_lights > 0 ? &sh : NULL);
     else

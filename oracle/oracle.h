@@ -78,6 +78,10 @@ typedef struct {
   const orc_field* const* fields;
   const uint8_t* const* field_occ;
   const int32_t* field_occ_res;
+  /* with several fields, the proposal sampler: field k's own proposal (the
+   * boxes must not overlap; each field is marched on its own range in the
+   * order the ray enters the boxes) */
+  const orc_field* const* field_proposals;
 } orc_opts;
 
 typedef struct {

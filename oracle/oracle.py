@@ -53,7 +53,8 @@ class _Opts(C.Structure):
                 ("proposal", C.c_void_p), ("n_prop", C.c_int32), ("n_fine", C.c_int32),
                 ("sample_shadows", C.c_int32), ("shadow_mask", C.c_double),
                 ("sample_emitters", C.c_int32), ("n_fields", C.c_int32), ("fields", C.c_void_p),
-                ("field_occ", C.c_void_p), ("field_occ_res", C.c_void_p)]
+                ("field_occ", C.c_void_p), ("field_occ_res", C.c_void_p),
+                ("field_proposals", C.c_void_p)]
 
 
 class _Out(C.Structure):
@@ -216,7 +217,7 @@ def occupancy(field, res, thresh, n_threads=None):
 def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
            tie_eps=1e-5, tie_rel=1e-4, occupancy_bits=None, proposal=None, n_prop=32,
            n_fine=32, field=..., mesh=..., shadow_mask=None, sample_emitters=False, fields=None,
-           field_occupancy=None):
+           field_occupancy=None, field_proposals=None):
     """Render FP32 input rays through the whole path in FP64.
 
     shadow_mask: None = no per-sample shadows; else every field sample that a
@@ -224,9 +225,10 @@ def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
     once per such light (Sec. 3.1 "Shadow rays").
     sample_emitters: light sampling toward emitting triangles at diffuse hits
     (Eq. 12's L_e as area lights).
-    fields: several fields marched together (uniform sampler; the scene's own
-    field is then not used); field_occupancy: per field an occupancy bit
-    array or None.
+    fields: several fields marched together (the scene's own field is then
+    not used); field_occupancy: per field an occupancy bit array or None;
+    field_proposals: per field its proposal (the proposal sampler with
+    several fields, boxes disjoint; n_prop and n_fine apply to each).
 
     Returns a dict with radiance, throughput, bounces, hit_ids (segments),
     tie flags, per-ray sample and segment counts.
@@ -264,7 +266,7 @@ def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
     keep = []
     if fields is not None:
         if proposal is not None:
-            raise ValueError("several fields are marched with the uniform sampler only")
+            raise ValueError("with several fields give field_proposals, one per field")
         ofs = [OField(f) for f in fields]
         ptrs = (C.c_void_p * len(ofs))(*[C.cast(C.pointer(x.s), C.c_void_p) for x in ofs])
         occs = (C.c_void_p * len(ofs))()
@@ -280,6 +282,14 @@ def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
         opt.fields = C.cast(ptrs, C.c_void_p)
         opt.field_occ = C.cast(occs, C.c_void_p)
         opt.field_occ_res = C.cast(ress, C.c_void_p)
+        if field_proposals is not None:
+            if len(field_proposals) != len(ofs):
+                raise ValueError("one proposal per field")
+            ops = [OField(pp) for pp in field_proposals]
+            pptrs = (C.c_void_p * len(ops))(*[C.cast(C.pointer(x.s), C.c_void_p) for x in ops])
+            keep += [ops, pptrs]
+            opt.field_proposals = C.cast(pptrs, C.c_void_p)
+            opt.n_prop, opt.n_fine = int(n_prop), int(n_fine)
         if of is None and ofs:
             of = ofs[0]
     res = dict(radiance=np.zeros((n, 3)), throughput=np.zeros((n, 3)),

@@ -1144,3 +1144,37 @@ def test_field_outside_the_segment_changes_nothing():
     b = _fields_render([fa, fb], o, d)
     for k in ("radiance", "throughput", "samples"):
         np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_one_field_with_its_proposal_is_the_single_field_proposal_march():
+    """Several-fields proposal path with one field equals the single-field
+    proposal render bit for bit (the same march, in field order)."""
+    sc = sg.tiny_scene(table_amp=1.0)
+    sc.field.pose = sg.pose_matrix(sg.rotation((0.2, 1.0, 0.1), 0.4), (0.1, -0.05, 0.0))
+    prop = sg.make_proposal(table_amp=0.5)
+    o, d = orc.rays_from_camera(sg.cameras_array(sc.cameras)[0])
+    o, d = o.astype(np.float32), d.astype(np.float32)
+    a = orc.render(sc, o, d, proposal=prop, n_prop=32, n_fine=32)
+    b = orc.render(sc, o, d, fields=[sc.field], field_proposals=[prop], n_prop=32, n_fine=32)
+    for k in ("radiance", "throughput", "samples"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_two_disjoint_fields_with_proposals_composite_in_closed_form():
+    """Each constant field sampled by its own (untrained) proposal: the
+    proposal sampler is exact for a constant medium, so the front-to-back
+    closed form holds exactly, in both ray directions and list orders."""
+    fa, ca = _tinted_field(1.0, (0.9, 0.3, 0.2))
+    fb, cb = _tinted_field(-0.5, (0.1, 0.6, 1.7), center=(0.0, 0.0, 2.5))
+    pa, pb = sg.make_proposal(table_amp=0.5), sg.make_proposal(seed=9, table_amp=0.8)
+    sa, sb = math.log1p(math.exp(1.0)), math.log1p(math.exp(-0.5))
+    Ta, Tb = math.exp(-2 * sa), math.exp(-2 * sb)
+    o = np.array([[0.05, 0.02, -2.5], [0.05, 0.02, 5.5]], np.float32)
+    d = np.array([[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]], np.float32)
+    r = _fields_render([fa, fb], o, d, field_proposals=[pa, pb], n_prop=32, n_fine=24)
+    np.testing.assert_allclose(r["radiance"][0], ca * (1 - Ta) + Ta * cb * (1 - Tb), rtol=1e-12)
+    np.testing.assert_allclose(r["radiance"][1], cb * (1 - Tb) + Tb * ca * (1 - Ta), rtol=1e-12)
+    np.testing.assert_allclose(r["throughput"], Ta * Tb, rtol=1e-12)
+    r2 = _fields_render([fb, fa], o, d, field_proposals=[pb, pa], n_prop=32, n_fine=24)
+    np.testing.assert_allclose(r2["radiance"], r["radiance"], rtol=1e-13)
+    assert r["samples"][0] == 2 * 24
