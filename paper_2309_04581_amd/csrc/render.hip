@@ -782,7 +782,8 @@ void field_box(const mr_field* f, double c[3], double h[3], double R[3][3]) {
     c[i] = R[i][0] * cf[0] + R[i][1] * cf[1] + R[i][2] * cf[2] + (v.has_pose ? (double)v.pose[4 * i + 3] : 0.0);
 }
 
-mr_status render_impl(const mr_field* const* fields, int n_fields, const mr_mesh* mesh, int64_t n,
+mr_status render_impl(const mr_field* const* fields, const mr_field* const* proposals, int n_fields, const mr_mesh* mesh,
+                      int64_t n,
                       const float* origins, const float* dirs, int32_t max_bounces,
                       const int32_t* per_ray_max_bounces, const mr_light* host_lights, int32_t n_lights,
                       const mr_render_opts* opts, mr_render_out* out, void* workspace, size_t workspace_bytes,
@@ -892,8 +893,13 @@ mr_status render_impl(const mr_field* const* fields, int n_fields, const mr_mesh
         float* f = fscratch + (int64_t)6 * k * cap;
         qk.tr = f; qk.tg = f + cap; qk.tb = f + 2 * cap;
         qk.lr = f + 3 * cap; qk.lg = f + 4 * cap; qk.lb = f + 5 * cap;
-        s = dispatch_march_mfma(fields[k], qk, counts + b, fctr + kXcds * k, P, mv.bvh, b < packet_segments, stats,
-                                opts->march_blocks_per_cu, n, st);
+        if (opts->sampler == MR_SAMPLER_PROPOSAL)
+          s = dispatch_march_proposal(fields[k], proposals[k], qk, counts + b, fctr + kXcds * k, P, mv.bvh,
+                                      opts->n_proposal, opts->n_fine, b < packet_segments, stats,
+                                      opts->march_blocks_per_cu, n, st);
+        else
+          s = dispatch_march_mfma(fields[k], qk, counts + b, fctr + kXcds * k, P, mv.bvh, b < packet_segments, stats,
+                                  opts->march_blocks_per_cu, n, st);
         if (s != MR_OK) return s;
       }
       hipLaunchKernelGGL(k_fields_combine, dim3(fblocks), dim3(256), 0, st, qi, counts + b, fscratch, cap, FB);
@@ -934,25 +940,28 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
                                mr_render_out* out, void* workspace, size_t workspace_bytes, void* stream) {
   mr_status s = validate_render(field, mesh, n, origins, dirs, max_bounces, host_lights, n_lights, opts, out);
   if (s != MR_OK) return s;
-  return render_impl(&field, field ? 1 : 0, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, host_lights,
-                     n_lights, opts, out, workspace, workspace_bytes, stream);
+  return render_impl(&field, nullptr, field ? 1 : 0, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces,
+                     host_lights, n_lights, opts, out, workspace, workspace_bytes, stream);
 }
 
-extern "C" mr_status mr_render_fields(const mr_field* const* fields, int32_t n_fields, const mr_mesh* mesh, int64_t n,
-                                      const float* origins, const float* dirs, int32_t max_bounces,
-                                      const int32_t* per_ray_max_bounces, const mr_light* host_lights,
-                                      int32_t n_lights, const mr_render_opts* opts, mr_render_out* out,
-                                      void* workspace, size_t workspace_bytes, void* stream) {
+extern "C" mr_status mr_render_fields(const mr_field* const* fields, const mr_field* const* proposals,
+                                      int32_t n_fields, const mr_mesh* mesh, int64_t n, const float* origins,
+                                      const float* dirs, int32_t max_bounces, const int32_t* per_ray_max_bounces,
+                                      const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
+                                      mr_render_out* out, void* workspace, size_t workspace_bytes, void* stream) {
   if (n_fields < 1 || n_fields > kMaxFields) return fail(MR_ERR_INVALID_ARG, "n_fields must be in 1..8");
   if (!fields) return fail(MR_ERR_INVALID_ARG, "null field list");
+  if (!opts) return fail(MR_ERR_INVALID_ARG, "null opts");
   for (int k = 0; k < n_fields; ++k)
     if (!fields[k]) return fail(MR_ERR_INVALID_ARG, "null field in the list");
+  const bool prop = opts->sampler == MR_SAMPLER_PROPOSAL;
+  if (prop && !proposals) return fail(MR_ERR_INVALID_ARG, "the proposal sampler needs one proposal per field");
   for (int k = 0; k < n_fields; ++k) {
-    mr_status s = validate_render(fields[k], mesh, n, origins, dirs, max_bounces, host_lights, n_lights, opts, out);
+    mr_render_opts ok = *opts;   // each field is validated with its own proposal
+    if (prop) ok.proposal = proposals[k];
+    mr_status s = validate_render(fields[k], mesh, n, origins, dirs, max_bounces, host_lights, n_lights, &ok, out);
     if (s != MR_OK) return s;
   }
-  if (n_fields > 1 && opts->sampler != MR_SAMPLER_UNIFORM)
-    return fail(MR_ERR_UNSUPPORTED, "several fields are marched with the uniform sampler only");
   for (int a = 0; a < n_fields; ++a)
     for (int b = a + 1; b < n_fields; ++b) {
       double c1[3], h1[3], R1[3][3], c2[3], h2[3], R2[3][3];
@@ -962,8 +971,14 @@ extern "C" mr_status mr_render_fields(const mr_field* const* fields, int32_t n_f
         return fail(MR_ERR_INVALID_ARG, "the boxes of fields " + std::to_string(a) + " and " + std::to_string(b) +
                                             " overlap in the world");
     }
-  return render_impl(fields, n_fields, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, host_lights, n_lights,
-                     opts, out, workspace, workspace_bytes, stream);
+  if (n_fields == 1) {   // one field: the ordinary render, with its proposal
+    mr_render_opts o1 = *opts;
+    if (prop) o1.proposal = proposals[0];
+    return render_impl(fields, nullptr, 1, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, host_lights,
+                       n_lights, &o1, out, workspace, workspace_bytes, stream);
+  }
+  return render_impl(fields, prop ? proposals : nullptr, n_fields, mesh, n, origins, dirs, max_bounces,
+                     per_ray_max_bounces, host_lights, n_lights, opts, out, workspace, workspace_bytes, stream);
 }
 
 extern "C" mr_status mr_profile_enable(int32_t on) {

@@ -222,14 +222,15 @@ def mr_render_fields_workspace_size(n, n_fields):
 
 
 def mr_render_fields(fields, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, lights, opts, out,
-                     workspace, workspace_bytes, stream=None):
+                     workspace, workspace_bytes, stream=None, proposals=None):
     nl = len(lights)
     arr = (Light * max(nl, 1))()
     for i, row in enumerate(lights):
         arr[i].pos = (C.c_float * 3)(*[float(x) for x in row[:3]])
         arr[i].intensity = (C.c_float * 3)(*[float(x) for x in row[3:6]])
     hs = (C.c_void_p * max(len(fields), 1))(*fields)
-    _check(lib().mr_render_fields(hs, C.c_int32(len(fields)), mesh, C.c_int64(n), _ptr(origins), _ptr(dirs),
+    ps = (C.c_void_p * max(len(proposals), 1))(*proposals) if proposals is not None else None
+    _check(lib().mr_render_fields(hs, ps, C.c_int32(len(fields)), mesh, C.c_int64(n), _ptr(origins), _ptr(dirs),
                                   C.c_int32(max_bounces), _ptr(per_ray_max_bounces), arr, C.c_int32(nl),
                                   C.byref(opts), C.byref(out), _ptr(workspace), C.c_size_t(workspace_bytes),
                                   _stream(stream)))
@@ -377,9 +378,11 @@ class Renderer:
                   self.ws_bytes, stream)
         return self
 
-    def render_fields(self, fields, mesh, origins, dirs, lights, opts, per_ray_max_bounces=None, stream=None):
-        """Several fields in one scene (mr_render_fields); grows the
-        workspace to the size the field count needs."""
+    def render_fields(self, fields, mesh, origins, dirs, lights, opts, per_ray_max_bounces=None, stream=None,
+                      proposals=None):
+        """Several fields in one scene (mr_render_fields), with one proposal
+        per field for the proposal sampler; grows the workspace to the size
+        the field count needs."""
         need = mr_render_fields_workspace_size(self.n, len(fields))
         if need > self.ws_bytes:
             import torch
@@ -387,7 +390,8 @@ class Renderer:
             self.ws_bytes = need
         mr_render_fields([f.handle for f in fields], mesh.handle if mesh is not None else None, self.n,
                          origins, dirs, self.max_bounces, per_ray_max_bounces, lights, opts, self.out,
-                         self.workspace, self.ws_bytes, stream)
+                         self.workspace, self.ws_bytes, stream,
+                         proposals=[p.handle for p in proposals] if proposals is not None else None)
         return self
 
 

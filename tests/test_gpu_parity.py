@@ -713,9 +713,12 @@ def test_emitter_sampling_after_refit_matches_oracle():
 # several fields in one scene (mr_render_fields)
 # ---------------------------------------------------------------------------
 
-def _fields_gpu(sc, o, d, fields=None, packets=0, use_occupancy=False, occ_res=0, **kw):
+def _fields_gpu(sc, o, d, fields=None, packets=0, use_occupancy=False, occ_res=0, proposals=None, **kw):
     M = mr()
     Fs = [M.Field(f) for f in (fields if fields is not None else sc.fields)]
+    Ps = [M.Field(p, table_dtype=M.MR_F32) for p in proposals] if proposals is not None else None
+    if Ps is not None:
+        kw = dict(kw, sampler=M.MR_SAMPLER_PROPOSAL)
     if use_occupancy:
         for F in Fs:
             F.build_occupancy(occ_res, sc.occupancy_thresh)
@@ -723,10 +726,26 @@ def _fields_gpu(sc, o, d, fields=None, packets=0, use_occupancy=False, occ_res=0
     R = M.Renderer(len(o), sc.max_bounces)
     opts = M.make_opts(sc, use_occupancy=use_occupancy, **kw)
     opts.march_packets = packets
-    R.render_fields(Fs, G, dev(o), dev(d), sc.lights, opts)
+    R.render_fields(Fs, G, dev(o), dev(d), sc.lights, opts, proposals=Ps)
     torch.cuda.synchronize()
     return dict(radiance=host(R.radiance), throughput=host(R.throughput), bounces=host(R.bounces),
                 hit_ids=host(R.hit_ids), counters=host(R.counters))
+
+
+@pytest.mark.parametrize("n_fields,packets", [(2, 0), (3, 0), (3, -1)])
+def test_several_fields_with_proposals_match_oracle(n_fields, packets):
+    """Each field sampled by its own proposal (32 + 32 samples per segment,
+    FP32 proposal tables): the passes use the proposal march per field and
+    are composited in box order, against the oracle's front-to-back march of
+    the disjoint fields."""
+    sc = sg.fields_scene(n_fields, 48, 27, kind="tiny", table_amp=1.0)
+    props = [sg.make_proposal(seed=5 + k, table_amp=0.5) for k in range(n_fields)]
+    o, d = oracle_camera_rays(sc)
+    r = orc.render(sc, o, d, fields=sc.fields, field_proposals=props, n_prop=32, n_fine=32)
+    assert (r["samples"] > 0).mean() > 0.3
+    g = _fields_gpu(sc, o, d, packets=packets, proposals=props)
+    compare_render(g, r, f"{n_fields} fields with proposals packets={packets}", rtol=1e-3, atol=1e-6)
+    assert int(g["counters"][0]) == int(r["samples"].sum())
 
 
 @pytest.mark.parametrize("n_fields,packets", [(2, 0), (3, 0), (3, -1), (3, 99)])
@@ -776,8 +795,9 @@ def test_one_field_list_is_mr_render():
 
 
 def test_several_fields_validated():
-    """Overlapping boxes, the proposal sampler, more than 8 fields and a
-    missing occupancy grid are refused; boxes that touch are accepted."""
+    """Overlapping boxes, the proposal sampler without one proposal per field
+    (or with a field that is no proposal), more than 8 fields and a missing
+    occupancy grid are refused; boxes that touch are accepted."""
     M = mr()
     sc = sg.tiny_scene()
     o, d = oracle_camera_rays(sc)
@@ -796,9 +816,13 @@ def test_several_fields_validated():
         R.render_fields([placed(0.0), placed(2.3, math.pi / 4)], G, dev(o), dev(d), sc.lights, opts)
     R.render_fields([placed(0.0), placed(2.5, math.pi / 4)], G, dev(o), dev(d), sc.lights, opts)
     P = M.Field(sg.make_proposal(), table_dtype=M.MR_F32)
-    with pytest.raises(M.MrError):
-        R.render_fields([placed(0.0), placed(3.0)], G, dev(o), dev(d), sc.lights,
-                        M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P))
+    popts = M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P)
+    with pytest.raises(M.MrError, match="one proposal per field"):
+        R.render_fields([placed(0.0), placed(3.0)], G, dev(o), dev(d), sc.lights, popts)
+    R.render_fields([placed(0.0), placed(3.0)], G, dev(o), dev(d), sc.lights, popts, proposals=[P, P])
+    with pytest.raises(M.MrError):   # a full field is no proposal
+        R.render_fields([placed(0.0), placed(3.0)], G, dev(o), dev(d), sc.lights, popts,
+                        proposals=[P, placed(6.0)])
     with pytest.raises(M.MrError):
         R.render_fields([placed(3.0 * k) for k in range(9)], G, dev(o), dev(d), sc.lights, opts)
     with pytest.raises(M.MrError):
