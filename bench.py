@@ -343,7 +343,7 @@ def emitters(M, sg, steps):
                                     "mean_radiance": [round(float(x), 5) for x in R.radiance.mean(0).cpu().numpy()]}}
 
 
-def several_fields(M, sg, steps, n_fields=3):
+def several_fields(M, sg, steps, n_fields=3, train_steps=0):
     """Several NeRF objects in one scene (mr_render_fields): three mid-layout
     fields (64 MiB tables each), turned and side by side, over a floor with a
     glass sphere and a mirror cube, 800x450, 8 bounces, plain FP32 with each
@@ -366,8 +366,36 @@ def several_fields(M, sg, steps, n_fields=3):
         R.render_fields(Fs, G, o, d, sc.lights, opts)
     ms = timed(step, steps, 1)
     c = R.counters.cpu().numpy()
-    return {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms, 3), "fields": n_fields,
-            "rays": n, "samples_per_step": int(c[0]), "samples_per_s": round(int(c[0]) / (ms / 1e3), 1)}
+    out = {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms, 3), "fields": n_fields,
+           "rays": n, "samples_per_step": int(c[0]), "samples_per_s": round(int(c[0]) / (ms / 1e3), 1)}
+    if train_steps > 0:
+        # each field sampled by its own proposal (32 + 32), trained on that field
+        # in its own frame; FP16 tables + BF16 MLPs; PSNR against the plain image
+        import dataclasses
+        plain_img = R.radiance.cpu().numpy()
+        F16s, props = [], []
+        for k, f in enumerate(sc.fields):
+            F16 = M.Field(f, table_dtype=M.MR_F16, mlp_dtype=M.MR_BF16)
+            F16.build_occupancy(sc.occupancy_res, sc.occupancy_thresh)
+            F16s.append(F16)
+            local = M.Field(dataclasses.replace(f, pose=None))
+            P = M.Field(sg.make_proposal(), table_dtype=M.MR_F16)
+            T = M.ProposalTrainer(P)
+            to, td = sg.random_rays(1 << 18, seed=507 + k)
+            to, td = torch.from_numpy(to).cuda(), torch.from_numpy(td).cuda()
+            lohi, tgt = T.targets(local, to, td, 0.05, 4.0, 256)
+            T.train(to, td, lohi, tgt, steps=train_steps, batch=1 << 14)
+            props.append(P)
+        popts = M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, use_occupancy=True)
+
+        def step_p():
+            M.mr_rays_from_cameras(cams, o, d, None, n)
+            R.render_fields(F16s, G, o, d, sc.lights, popts, proposals=props)
+        ms_p = timed(step_p, steps, 1)
+        out["proposal_fp16"] = {"value": round(n / (ms_p / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms_p, 3),
+                                "psnr_db_vs_plain_fp32": round(psnr_tonemapped(R.radiance.cpu().numpy(), plain_img), 2),
+                                "samples": "32 proposal + 32 fine per field and segment", "train_steps": train_steps}
+    return out
 
 
 def multicam(M, sg, steps):
@@ -591,7 +619,7 @@ def main():
         line["moving_field"] = moving_field(M, sg, sc, F, G, cams, n, args.steps)
         line["sample_shadows"] = sample_shadows(M, sg, sc, F, G, cams, n, args.steps)
         line["emitters"] = emitters(M, sg, args.steps)
-        line["several_fields"] = several_fields(M, sg, args.steps)
+        line["several_fields"] = several_fields(M, sg, args.steps, train_steps=args.train_steps)
         line["multicam_16_cameras"] = multicam(M, sg, 2)
         line["scaling_spheres"] = scaling(M, sg, 3)
         line["cloth_refit"] = cloth(M, sg, args.cloth_frames, args.train_steps)
