@@ -263,20 +263,24 @@ mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64_t n, const
  * among the meshes; the paper's dynamic, mesh-aware scenes hold more than one
  * radiance field).  The medium is their sum: density sigma_1 + sigma_2 + ...
  * and colour the density-weighted mean, each field zero outside its box.
- * Every field is marched along each segment (on the same uniform grid, or
- * with its own proposal) in a pass of its own, and the passes are composited
- * in the order the ray enters the boxes, which is that sum because the boxes
- * may not overlap.
- * fields: host array of n_fields (1..8) field handles whose world boxes
- * (aabb under the pose) are pairwise disjoint (checked: MR_ERR_INVALID_ARG
- * names the first overlapping pair; touching is allowed).  proposals: host
+ * When the world boxes (aabb under the pose) are pairwise disjoint (touching
+ * allowed), every field is marched along each segment in a pass of its own
+ * (on the same uniform grid, or with its own proposal) and the passes are
+ * composited in the order the ray enters the boxes, which is that sum.  When
+ * some boxes overlap, all fields are marched together over the summed medium:
+ * the uniform grid is cut at every box face a segment crosses and each piece
+ * sums the fields whose boxes hold it.  That needs the uniform sampler (a
+ * proposal sampler is MR_ERR_UNSUPPORTED, naming the first overlapping pair)
+ * and fields of one layout (levels, SH components, colour layers, table and
+ * MLP types; else MR_ERR_UNSUPPORTED).
+ * fields: host array of n_fields (1..8) field handles.  proposals: host
  * array of n_fields proposal fields, field k sampled by proposals[k], when
  * opts->sampler is MR_SAMPLER_PROPOSAL (opts->proposal is then not used; a
  * missing list is MR_ERR_INVALID_ARG); NULL for the uniform sampler.  With
- * use_occupancy every field needs its own grid.  Other arguments as
- * mr_render; workspace of mr_render_fields_workspace_size(n, n_fields)
- * bytes, which for one field is mr_render_workspace_size(n) (the call is then
- * mr_render). */
+ * use_occupancy every field needs its own grid, and a piece is skipped for a
+ * field whose grid marks its cell empty.  Other arguments as mr_render;
+ * workspace of mr_render_fields_workspace_size(n, n_fields) bytes, which for
+ * one field is mr_render_workspace_size(n) (the call is then mr_render). */
 size_t mr_render_fields_workspace_size(int64_t n, int32_t n_fields);
 mr_status mr_render_fields(const mr_field* const* fields, const mr_field* const* proposals, int32_t n_fields,
                            const mr_mesh* mesh, int64_t n, const float* origins, const float* dirs,

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmeshrf.so")
-SOURCES = ["api.cpp", "field.hip", "bvh.hip", "render.hip", "march_mfma.hip", "proposal.hip", "probe.hip"]
+SOURCES = ["api.cpp", "field.hip", "bvh.hip", "render.hip", "march_mfma.hip", "march_fields.hip", "proposal.hip", "probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -25,51 +25,6 @@ using namespace mr;
 
 namespace {
 
-__device__ __forceinline__ float scan16_mul(float v, int j) {
-#pragma unroll
-  for (int off = 1; off < 16; off <<= 1) {
-    const float u = __shfl_up(v, off, 16);
-    if (j >= off) v *= u;
-  }
-  return v;
-}
-
-__device__ __forceinline__ float sum16(float v) {
-#pragma unroll
-  for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 16);
-  return v;
-}
-
-__device__ __forceinline__ bool slab_box(const FieldView& F, float ox, float oy, float oz, float dx, float dy, float dz,
-                                         float& t0, float& t1) {
-  float lo = -INFINITY, hi = INFINITY;
-  const float o[3] = {ox, oy, oz}, d[3] = {dx, dy, dz};
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    if (d[k] == 0.0f) {
-      if (o[k] < F.amin[k] || o[k] > F.amax[k]) return false;
-      continue;
-    }
-    const float inv = 1.0f / d[k];
-    float a = (F.amin[k] - o[k]) * inv, b = (F.amax[k] - o[k]) * inv;
-    if (a > b) { const float t = a; a = b; b = t; }
-    lo = fmaxf(lo, a);
-    hi = fminf(hi, b);
-  }
-  t0 = lo;
-  t1 = hi;
-  return hi > lo;
-}
-
-__device__ __forceinline__ bool occ_lookup(const FieldView& F, float px, float py, float pz) {
-  float xh, yh, zh;
-  to_unit(F, px, py, pz, xh, yh, zh);
-  const int R = F.occ_res;
-  const int cx = min((int)(xh * R), R - 1), cy = min((int)(yh * R), R - 1), cz = min((int)(zh * R), R - 1);
-  const int64_t c = ((int64_t)cz * R + cy) * R + cx;
-  return (F.occ[c >> 5] >> (c & 31)) & 1u;
-}
-
 // One ray per wave: lane j takes sample kb + j of each 16-sample tile, and
 // transmittance is a 16-lane prefix product carried from tile to tile.
 template <int NL, int SH, int CL, typename TabT, bool BF, bool SHADOW>

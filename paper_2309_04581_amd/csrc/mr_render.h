@@ -40,11 +40,12 @@ struct MarchParams {
 // group 0 sends a ray from the sample's world position to every light, and
 // each light a mesh hides multiplies the mask by P.shadow_mask; every lane
 // returns its column's mask.  stack: that lane's LDS stack, stride 16.
-__device__ __forceinline__ float sample_shadow(const FieldView& F, const BvhView& B, const MarchParams& P,
-                                               bool valid, float px, float py, float pz, int lane, int* stack) {
+// This form takes the sample's world position; sample_shadow below takes a
+// point in the frame of field F.
+__device__ __forceinline__ float sample_shadow_world(const BvhView& B, const MarchParams& P, bool valid, float px,
+                                                     float py, float pz, int lane, int* stack) {
   float m = 1.0f;
   if (lane < 16 && valid) {
-    field_to_world(F, px, py, pz);
     for (int li = 0; li < P.n_lights; ++li) {
       const float sx = P.light_pos[li][0] - px, sy = P.light_pos[li][1] - py, sz = P.light_pos[li][2] - pz;
       const float dist = sqrtf(sx * sx + sy * sy + sz * sz);
@@ -54,6 +55,12 @@ __device__ __forceinline__ float sample_shadow(const FieldView& F, const BvhView
     }
   }
   return __shfl(m, lane & 15, 64);
+}
+
+__device__ __forceinline__ float sample_shadow(const FieldView& F, const BvhView& B, const MarchParams& P,
+                                               bool valid, float px, float py, float pz, int lane, int* stack) {
+  if (lane < 16 && valid) field_to_world(F, px, py, pz);
+  return sample_shadow_world(B, P, valid, px, py, pz, lane, stack);
 }
 
 struct ShadeParams {
@@ -127,6 +134,13 @@ int persistent_blocks(const void* kernel, int threads, int per_cu, int64_t cap);
 mr_status dispatch_march_mfma(const mr_field* f, RayQueue q, const int* count, int* work, const MarchParams& P,
                               const BvhView& B, bool packets, unsigned long long* stats, int blocks_per_cu, int64_t n,
                               hipStream_t st);
+
+// march of several fields whose boxes overlap, over their summed medium
+// (march_fields.hip): one ray per wave on the uniform grid; the fields share
+// one layout (levels, SH components, colour layers, table and MLP types)
+mr_status dispatch_march_fields(const mr_field* const* fields, int n_fields, RayQueue q, const int* count, int* work,
+                                const MarchParams& P, const BvhView& B, unsigned long long* stats, int blocks_per_cu,
+                                int64_t n, hipStream_t st);
 
 // proposal-sampled march (defined with the proposal kernels)
 // packets: 16 consecutive queue rays per wave when n_prop = 32 and n_fine <= 32

@@ -527,7 +527,8 @@ __global__ __launch_bounds__(64 * kWideWaves) void k_trace_wide(RayQueue q, cons
 // the segment's throughput and radiance (starting at T = 1, L = 0); the
 // passes are then composited in the order the ray enters the fields' boxes.
 // With boxes that do not overlap, every sample lies in at most one field, so
-// this is the march of the summed medium.
+// this is the march of the summed medium.  Boxes that overlap are marched
+// together instead, in one pass (march_fields.hip).
 // ---------------------------------------------------------------------------
 struct FieldBoxes {
   int n;
@@ -787,7 +788,7 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
                       const float* origins, const float* dirs, int32_t max_bounces,
                       const int32_t* per_ray_max_bounces, const mr_light* host_lights, int32_t n_lights,
                       const mr_render_opts* opts, mr_render_out* out, void* workspace, size_t workspace_bytes,
-                      void* stream) {
+                      void* stream, bool overlapping = false) {
   mr_status s = MR_OK;
   const mr_field* field = n_fields == 1 ? fields[0] : nullptr;
   if (n == 0) return MR_OK;
@@ -882,7 +883,13 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
                          opts->t_far, P.span, out->hit_ids, out->hit_ids ? out->hit_stride : 0);
       MR_HIP(hipGetLastError());
     }
-    if (n_fields > 1) {
+    if (n_fields > 1 && overlapping) {
+      // boxes that overlap: one march over the summed medium
+      StageTimer tm(1, st);
+      s = dispatch_march_fields(fields, n_fields, qi, counts + b, work + kXcds * b, P, mv.bvh, stats,
+                                opts->march_blocks_per_cu, n, st);
+      if (s != MR_OK) return s;
+    } else if (n_fields > 1) {
       StageTimer tm(1, st);
       const int fblocks = (int)std::min<int64_t>((n + 255) / 256, 65535);
       hipLaunchKernelGGL(k_fields_prep, dim3(fblocks), dim3(256), 0, st, counts + b, fscratch, n_fields, cap, fctr,
@@ -962,14 +969,26 @@ extern "C" mr_status mr_render_fields(const mr_field* const* fields, const mr_fi
     mr_status s = validate_render(fields[k], mesh, n, origins, dirs, max_bounces, host_lights, n_lights, &ok, out);
     if (s != MR_OK) return s;
   }
+  bool overlapping = false;
   for (int a = 0; a < n_fields; ++a)
     for (int b = a + 1; b < n_fields; ++b) {
       double c1[3], h1[3], R1[3][3], c2[3], h2[3], R2[3][3];
       field_box(fields[a], c1, h1, R1);
       field_box(fields[b], c2, h2, R2);
-      if (boxes_overlap(c1, h1, R1, c2, h2, R2))
-        return fail(MR_ERR_INVALID_ARG, "the boxes of fields " + std::to_string(a) + " and " + std::to_string(b) +
-                                            " overlap in the world");
+      if (!boxes_overlap(c1, h1, R1, c2, h2, R2)) continue;
+      if (prop)
+        return fail(MR_ERR_UNSUPPORTED, "the boxes of fields " + std::to_string(a) + " and " + std::to_string(b) +
+                                            " overlap in the world: overlapping fields take the uniform sampler");
+      overlapping = true;
+    }
+  if (overlapping)
+    for (int k = 1; k < n_fields; ++k) {   // one kernel marches them all: one layout
+      const FieldView &v0 = fields[0]->view, &vk = fields[k]->view;
+      if (vk.n_levels != v0.n_levels || vk.sh != v0.sh || vk.c_layers != v0.c_layers ||
+          vk.table_dtype != v0.table_dtype || vk.mlp_dtype != v0.mlp_dtype)
+        return fail(MR_ERR_UNSUPPORTED, "fields 0 and " + std::to_string(k) +
+                                            " differ in layout (levels, SH components, colour layers, table or MLP "
+                                            "type); fields whose boxes overlap must share one");
     }
   if (n_fields == 1) {   // one field: the ordinary render, with its proposal
     mr_render_opts o1 = *opts;
@@ -978,7 +997,8 @@ extern "C" mr_status mr_render_fields(const mr_field* const* fields, const mr_fi
                        n_lights, &o1, out, workspace, workspace_bytes, stream);
   }
   return render_impl(fields, prop ? proposals : nullptr, n_fields, mesh, n, origins, dirs, max_bounces,
-                     per_ray_max_bounces, host_lights, n_lights, opts, out, workspace, workspace_bytes, stream);
+                     per_ray_max_bounces, host_lights, n_lights, opts, out, workspace, workspace_bytes, stream,
+                     overlapping);
 }
 
 extern "C" mr_status mr_profile_enable(int32_t on) {

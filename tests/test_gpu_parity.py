@@ -784,6 +784,62 @@ def test_several_fields_with_occupancy_and_sample_shadows_match_oracle():
     compare_render(g, r, "3 sparse fields, occupancy, sample shadows", rtol=1e-3, atol=1e-6)
 
 
+def _overlap_fraction(fields, o, d):
+    """Fraction of the rays whose line crosses a stretch shared by two boxes."""
+    spans = []
+    for f in fields:
+        P = np.asarray(f.pose, np.float64)
+        of, df = (o - P[:, 3]) @ P[:, :3], d @ P[:, :3]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t0 = (np.asarray(f.aabb_min, np.float64) - of) / df
+            t1 = (np.asarray(f.aabb_max, np.float64) - of) / df
+        spans.append((np.nanmax(np.minimum(t0, t1), axis=1), np.nanmin(np.maximum(t0, t1), axis=1)))
+    both = np.zeros(len(o), bool)
+    for i in range(len(fields)):
+        for j in range(i + 1, len(fields)):
+            both |= np.minimum(spans[i][1], spans[j][1]) > np.maximum(spans[i][0], spans[j][0])
+    return both.mean()
+
+
+@pytest.mark.parametrize("n_fields,spacing", [(2, 1.2), (3, 1.2), (3, 0.0)])
+def test_overlapping_fields_match_oracle(n_fields, spacing):
+    """Boxes that overlap (1.2 apart, or all on one centre with different
+    turns): the fields are marched together over the summed medium (density
+    sum, density-weighted colour, the grid cut at every box face), against the
+    oracle's march of the same sum; the count of field evaluations equals the
+    oracle's."""
+    sc = sg.fields_scene(n_fields, 48, 27, kind="tiny", table_amp=1.0, spacing=spacing)
+    o, d = oracle_camera_rays(sc)
+    assert _overlap_fraction(sc.fields, o.astype(np.float64), d.astype(np.float64)) > 0.04
+    r = orc.render(sc, o, d, fields=sc.fields)
+    assert (r["samples"] > 0).mean() > 0.15
+    g = _fields_gpu(sc, o, d)
+    compare_render(g, r, f"{n_fields} overlapping fields spacing={spacing}", rtol=1e-3, atol=1e-6)
+    assert int(g["counters"][0]) == int(r["samples"].sum())
+
+
+def test_overlapping_fields_with_occupancy_and_sample_shadows_match_oracle():
+    """Three overlapping copies of the sparse field, each with its own
+    occupancy grid, and the per-sample shadow mask toward the light."""
+    sc = sg.fields_scene(3, 48, 27, kind="tiny", spacing=1.0)
+    base = _sparse_field()
+    fields = []
+    for f in sc.fields:
+        g = copy.deepcopy(base)
+        g.pose = f.pose
+        fields.append(g)
+    sc.fields = fields
+    sc.occupancy_thresh = _unambiguous_threshold(base, 32)
+    bits, margin = orc.occupancy(base, 32, sc.occupancy_thresh)
+    assert np.abs(margin).min() > 5e-7
+    o, d = oracle_camera_rays(sc)
+    assert _overlap_fraction(fields, o.astype(np.float64), d.astype(np.float64)) > 0.04
+    r = orc.render(sc, o, d, fields=fields, field_occupancy=[bits] * 3, shadow_mask=0.2)
+    g = _fields_gpu(sc, o, d, use_occupancy=True, occ_res=32, shadow_mask=0.2)
+    compare_render(g, r, "3 overlapping sparse fields, occupancy, sample shadows", rtol=1e-3, atol=1e-6)
+    assert int(g["counters"][0]) == int(r["samples"].sum())
+
+
 def test_one_field_list_is_mr_render():
     """mr_render_fields with one field is mr_render, bit for bit."""
     sc = sg.tiny_scene(table_amp=1.0)
@@ -795,9 +851,11 @@ def test_one_field_list_is_mr_render():
 
 
 def test_several_fields_validated():
-    """Overlapping boxes, the proposal sampler without one proposal per field
-    (or with a field that is no proposal), more than 8 fields and a missing
-    occupancy grid are refused; boxes that touch are accepted."""
+    """Overlapping boxes with the proposal sampler or with fields of different
+    layouts, the proposal sampler without one proposal per field (or with a
+    field that is no proposal), more than 8 fields and a missing occupancy
+    grid are refused; overlapping boxes under the uniform sampler and boxes
+    that touch are accepted."""
     M = mr()
     sc = sg.tiny_scene()
     o, d = oracle_camera_rays(sc)
@@ -810,13 +868,20 @@ def test_several_fields_validated():
         return M.Field(f)
     opts = M.make_opts(sc)
     R.render_fields([placed(0.0), placed(2.0)], G, dev(o), dev(d), sc.lights, opts)    # touching
-    with pytest.raises(M.MrError, match="overlap"):
-        R.render_fields([placed(0.0), placed(1.9)], G, dev(o), dev(d), sc.lights, opts)
-    with pytest.raises(M.MrError, match="overlap"):
-        R.render_fields([placed(0.0), placed(2.3, math.pi / 4)], G, dev(o), dev(d), sc.lights, opts)
+    R.render_fields([placed(0.0), placed(1.9)], G, dev(o), dev(d), sc.lights, opts)    # overlapping
+    R.render_fields([placed(0.0), placed(2.3, math.pi / 4)], G, dev(o), dev(d), sc.lights, opts)
     R.render_fields([placed(0.0), placed(2.5, math.pi / 4)], G, dev(o), dev(d), sc.lights, opts)
+    def placed_f16(x):
+        f = copy.deepcopy(sc.field)
+        f.pose = sg.pose_matrix(np.eye(3), (x, 0.0, 0.0))
+        return M.Field(f, table_dtype=M.MR_F16)
+    with pytest.raises(M.MrError, match="layout"):   # an FP16 table overlapping an FP32 one
+        R.render_fields([placed(0.0), placed_f16(1.0)], G, dev(o), dev(d), sc.lights, opts)
+    R.render_fields([placed(0.0), placed_f16(3.0)], G, dev(o), dev(d), sc.lights, opts)   # disjoint: accepted
     P = M.Field(sg.make_proposal(), table_dtype=M.MR_F32)
     popts = M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P)
+    with pytest.raises(M.MrError, match="overlap"):
+        R.render_fields([placed(0.0), placed(1.9)], G, dev(o), dev(d), sc.lights, popts, proposals=[P, P])
     with pytest.raises(M.MrError, match="one proposal per field"):
         R.render_fields([placed(0.0), placed(3.0)], G, dev(o), dev(d), sc.lights, popts)
     R.render_fields([placed(0.0), placed(3.0)], G, dev(o), dev(d), sc.lights, popts, proposals=[P, P])
