@@ -347,7 +347,8 @@ def several_fields(M, sg, steps, n_fields=3, train_steps=0):
     """Several NeRF objects in one scene (mr_render_fields): three mid-layout
     fields (64 MiB tables each), turned and side by side, over a floor with a
     glass sphere and a mirror cube, 800x450, 8 bounces, plain FP32 with each
-    field's occupancy grid."""
+    field's occupancy grid; then the same fields 1.2 apart, where neighbouring
+    boxes overlap and the fields are marched together."""
     import torch
     sc = sg.fields_scene(n_fields)
     cams = sg.cameras_array(sc.cameras)
@@ -368,6 +369,23 @@ def several_fields(M, sg, steps, n_fields=3, train_steps=0):
     c = R.counters.cpu().numpy()
     out = {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms, 3), "fields": n_fields,
            "rays": n, "samples_per_step": int(c[0]), "samples_per_s": round(int(c[0]) / (ms / 1e3), 1)}
+    # the same fields 1.2 apart: neighbouring boxes overlap, and all fields are
+    # marched together over the summed medium (one ray per wave)
+    sco = sg.fields_scene(n_fields, spacing=1.2)
+    Fo = [M.Field(f) for f in sco.fields]
+    for F in Fo:
+        F.build_occupancy(sco.occupancy_res, sco.occupancy_thresh)
+    oopts = M.make_opts(sco, use_occupancy=True)
+
+    def step_o():
+        M.mr_rays_from_cameras(cams, o, d, None, n)
+        R.render_fields(Fo, G, o, d, sco.lights, oopts)
+    ms_o = timed(step_o, steps, 1)
+    c = R.counters.cpu().numpy()
+    out["overlapping"] = {"value": round(n / (ms_o / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms_o, 3),
+                          "spacing": 1.2, "field_samples_per_step": int(c[0]),
+                          "field_samples_per_s": round(int(c[0]) / (ms_o / 1e3), 1)}
+    del Fo
     if train_steps > 0:
         # each field sampled by its own proposal (32 + 32), trained on that field
         # in its own frame; FP16 tables + BF16 MLPs; PSNR against the plain image

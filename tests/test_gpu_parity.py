@@ -840,6 +840,37 @@ def test_overlapping_fields_with_occupancy_and_sample_shadows_match_oracle():
     assert int(g["counters"][0]) == int(r["samples"].sum())
 
 
+def test_overlapping_mid_fields_full_size_sampled():
+    """Three mid-layout fields (16 levels, 2^19-entry tables) 1.2 apart, so
+    that neighbouring boxes overlap, at the several-fields benchmark's settings
+    (800x450, 516 samples per segment, 8 bounces, each field's 128^3 occupancy
+    grid; the oracle uses its own grids, every cell occupied by a wide
+    margin); 1000 seeded rays re-rendered one by one by the oracle."""
+    sc = sg.fields_scene(3, spacing=1.2)
+    M = mr()
+    o, d, _ = M.camera_rays(sg.cameras_array(sc.cameras))
+    assert _overlap_fraction(sc.fields, host(o).astype(np.float64), host(d).astype(np.float64)) > 0.05
+    Fs = [M.Field(f) for f in sc.fields]
+    bits = []
+    for F, f in zip(Fs, sc.fields):
+        F.build_occupancy(sc.occupancy_res, sc.occupancy_thresh)
+        b, margin = orc.occupancy(f, sc.occupancy_res, sc.occupancy_thresh)
+        assert np.abs(margin).min() > 1e-3
+        bits.append(b)
+    G = M.Mesh(sc.mesh)
+    R = M.Renderer(o.shape[0], sc.max_bounces)
+    R.render_fields(Fs, G, o, d, sc.lights, M.make_opts(sc, use_occupancy=True))
+    torch.cuda.synchronize()
+    g = dict(radiance=host(R.radiance), throughput=host(R.throughput), bounces=host(R.bounces),
+             hit_ids=host(R.hit_ids))
+    rng = np.random.default_rng(106)
+    idx = np.sort(rng.choice(o.shape[0], 1000, replace=False))
+    r = orc.render(sc, host(o)[idx], host(d)[idx], ray_ids=idx, fields=sc.fields, field_occupancy=bits)
+    assert (r["samples"] > 0).mean() > 0.2
+    compare_render({k: v[idx] for k, v in g.items()}, r, "3 overlapping mid fields 800x450 sample")
+    assert np.all(g["throughput"] <= 1 + 1e-6) and np.all(g["radiance"] >= 0)
+
+
 def test_one_field_list_is_mr_render():
     """mr_render_fields with one field is mr_render, bit for bit."""
     sc = sg.tiny_scene(table_amp=1.0)
