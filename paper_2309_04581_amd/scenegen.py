@@ -525,7 +525,8 @@ def fields_scene(n_fields=3, width=800, height=450, kind="mid", table_amp=1e-4, 
     """Several NeRF objects in one scene: n copies of the mid (or tiny) field
     layout with seeds 2, 3, ... (tiny: 1, 2, ...), each turned about y by a
     seeded angle in [-pi/4, pi/4] and set `spacing` apart along x (a box turned
-    about y spans at most 2 sqrt 2 in x, so the boxes stay disjoint), over a
+    about y spans at most 2 sqrt 2 in x, so at the default spacing the boxes
+    stay disjoint; below 2 neighbouring boxes always overlap), over a
     wide diffuse floor with a glass sphere and a mirror cube in front of them;
     camera 4.8 back.  The segment length covers the far boxes (t in [0.05,
     8.0]) with about the interval length of the single-field workloads (mid:
