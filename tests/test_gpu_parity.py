@@ -801,11 +801,12 @@ def _overlap_fraction(fields, o, d):
     return both.mean()
 
 
-@pytest.mark.parametrize("n_fields,spacing", [(2, 1.2), (3, 1.2), (3, 0.0)])
+@pytest.mark.parametrize("n_fields,spacing", [(2, 1.2), (3, 1.2), (3, 0.0), (8, 0.5)])
 def test_overlapping_fields_match_oracle(n_fields, spacing):
-    """Boxes that overlap (1.2 apart, or all on one centre with different
-    turns): the fields are marched together over the summed medium (density
-    sum, density-weighted colour, the grid cut at every box face), against the
+    """Boxes that overlap (1.2 apart, all on one centre with different turns,
+    which makes their y faces coincide, or the most fields, 0.5 apart): the
+    fields are marched together over the summed medium (density sum,
+    density-weighted colour, the grid cut at every box face), against the
     oracle's march of the same sum; the count of field evaluations equals the
     oracle's."""
     sc = sg.fields_scene(n_fields, 48, 27, kind="tiny", table_amp=1.0, spacing=spacing)
