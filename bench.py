@@ -369,6 +369,7 @@ def several_fields(M, sg, steps, n_fields=3, train_steps=0):
     c = R.counters.cpu().numpy()
     out = {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms, 3), "fields": n_fields,
            "rays": n, "samples_per_step": int(c[0]), "samples_per_s": round(int(c[0]) / (ms / 1e3), 1)}
+    plain_img = R.radiance.cpu().numpy()
     # the same fields 1.2 apart: neighbouring boxes overlap, and all fields are
     # marched together over the summed medium (one ray per wave)
     sco = sg.fields_scene(n_fields, spacing=1.2)
@@ -390,7 +391,6 @@ def several_fields(M, sg, steps, n_fields=3, train_steps=0):
         # each field sampled by its own proposal (32 + 32), trained on that field
         # in its own frame; FP16 tables + BF16 MLPs; PSNR against the plain image
         import dataclasses
-        plain_img = R.radiance.cpu().numpy()
         F16s, props = [], []
         for k, f in enumerate(sc.fields):
             F16 = M.Field(f, table_dtype=M.MR_F16, mlp_dtype=M.MR_BF16)
