@@ -841,6 +841,26 @@ def test_overlapping_fields_with_occupancy_and_sample_shadows_match_oracle():
     assert int(g["counters"][0]) == int(r["samples"].sum())
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_overlapping_fields_random_placements_match_oracle(seed):
+    """2 to 5 tiny-layout fields of table amplitude 1 at seeded placements:
+    any rotation axis and angle, centres within 0.9 of the origin (so boxes
+    overlap, often three or more at a time), and a seeded sample count
+    (64 to 200 per segment), in the several-fields scene at 40x24."""
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(2, 6))
+    sc = sg.fields_scene(n, 40, 24, kind="tiny", table_amp=1.0, n_samples=int(rng.integers(64, 201)))
+    for f in sc.fields:
+        axis = rng.normal(size=3)
+        f.pose = sg.pose_matrix(sg.rotation(axis, rng.uniform(-math.pi, math.pi)), rng.uniform(-0.9, 0.9, 3))
+    o, d = oracle_camera_rays(sc)
+    assert _overlap_fraction(sc.fields, o.astype(np.float64), d.astype(np.float64)) > 0.05
+    r = orc.render(sc, o, d, fields=sc.fields)
+    g = _fields_gpu(sc, o, d)
+    compare_render(g, r, f"{n} fields at random placements, seed {seed}", rtol=1e-3, atol=1e-6)
+    assert int(g["counters"][0]) == int(r["samples"].sum())
+
+
 @pytest.mark.parametrize("shadow_mask", [None, 0.3])
 def test_overlapping_fields_around_meshes_match_oracle(shadow_mask):
     """Two tiny-layout fields (table amplitude 1), turned and shifted so that
