@@ -713,9 +713,11 @@ def test_emitter_sampling_after_refit_matches_oracle():
 # several fields in one scene (mr_render_fields)
 # ---------------------------------------------------------------------------
 
-def _fields_gpu(sc, o, d, fields=None, packets=0, use_occupancy=False, occ_res=0, proposals=None, **kw):
+def _fields_gpu(sc, o, d, fields=None, packets=0, use_occupancy=False, occ_res=0, proposals=None, table_dtype=0,
+                mlp_dtype=0, **kw):
     M = mr()
-    Fs = [M.Field(f) for f in (fields if fields is not None else sc.fields)]
+    Fs = [M.Field(f, table_dtype=table_dtype, mlp_dtype=mlp_dtype)
+          for f in (fields if fields is not None else sc.fields)]
     Ps = [M.Field(p, table_dtype=M.MR_F32) for p in proposals] if proposals is not None else None
     if Ps is not None:
         kw = dict(kw, sampler=M.MR_SAMPLER_PROPOSAL)
