@@ -916,6 +916,79 @@ def test_overlapping_mid_fields_full_size_sampled():
     assert np.all(g["throughput"] <= 1 + 1e-6) and np.all(g["radiance"] >= 0)
 
 
+def test_several_mid_fields_full_size_sampled():
+    """The several-fields benchmark at full size: three mid-layout fields 2.9
+    apart (disjoint boxes, one pass per field), 800x450, 516 samples per
+    segment, 8 bounces, each field's 128^3 occupancy grid (the oracle uses its
+    own grids); 1000 seeded rays re-rendered one by one by the oracle."""
+    sc = sg.fields_scene(3)
+    M = mr()
+    o, d, _ = M.camera_rays(sg.cameras_array(sc.cameras))
+    Fs = [M.Field(f) for f in sc.fields]
+    bits = []
+    for F, f in zip(Fs, sc.fields):
+        F.build_occupancy(sc.occupancy_res, sc.occupancy_thresh)
+        b, margin = orc.occupancy(f, sc.occupancy_res, sc.occupancy_thresh)
+        assert np.abs(margin).min() > 1e-3
+        bits.append(b)
+    G = M.Mesh(sc.mesh)
+    R = M.Renderer(o.shape[0], sc.max_bounces)
+    R.render_fields(Fs, G, o, d, sc.lights, M.make_opts(sc, use_occupancy=True))
+    torch.cuda.synchronize()
+    g = dict(radiance=host(R.radiance), throughput=host(R.throughput), bounces=host(R.bounces),
+             hit_ids=host(R.hit_ids))
+    rng = np.random.default_rng(107)
+    idx = np.sort(rng.choice(o.shape[0], 1000, replace=False))
+    r = orc.render(sc, host(o)[idx], host(d)[idx], ray_ids=idx, fields=sc.fields, field_occupancy=bits)
+    assert (r["samples"] > 0).mean() > 0.2
+    compare_render({k: v[idx] for k, v in g.items()}, r, "3 disjoint mid fields 800x450 sample")
+    assert np.all(g["throughput"] <= 1 + 1e-6) and np.all(g["radiance"] >= 0)
+
+
+def test_several_mid_fields_proposal_fp16_full_size_sampled():
+    """The several-fields benchmark's proposal configuration at full size:
+    three mid-layout fields with FP16 tables + BF16 MLPs, each sampled by its
+    own proposal (FP16 table, 32 + 32 samples), occupancy grids.  The oracle
+    runs on the parameters as the GPU holds them (tables rounded to FP16,
+    BF16-held layers rounded) with seeded proposals (trained weights would come
+    from the GPU); 1000 seeded rays; radiance within 2e-3 relative (the BF16
+    rounding of layer inputs) and 1e-5 absolute."""
+    import bench
+    sc = sg.fields_scene(3)
+    M = mr()
+    o, d, _ = M.camera_rays(sg.cameras_array(sc.cameras))
+    props = [sg.make_proposal(seed=11 + k) for k in range(3)]
+    Fs = [M.Field(f, table_dtype=M.MR_F16, mlp_dtype=M.MR_BF16) for f in sc.fields]
+    rounded = [bench._rounded_field(sg, f) for f in sc.fields]
+    bits = []
+    for F, f in zip(Fs, rounded):
+        F.build_occupancy(sc.occupancy_res, sc.occupancy_thresh)
+        b, margin = orc.occupancy(f, sc.occupancy_res, sc.occupancy_thresh)
+        assert np.abs(margin).min() > 1e-3
+        bits.append(b)
+    Ps = [M.Field(p, table_dtype=M.MR_F16) for p in props]
+    G = M.Mesh(sc.mesh)
+    R = M.Renderer(o.shape[0], sc.max_bounces)
+    opts = M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, use_occupancy=True)
+    R.render_fields(Fs, G, o, d, sc.lights, opts, proposals=Ps)
+    torch.cuda.synchronize()
+    g = dict(radiance=host(R.radiance), throughput=host(R.throughput), bounces=host(R.bounces),
+             hit_ids=host(R.hit_ids))
+    propr = []
+    for p in props:
+        q = copy.deepcopy(p)
+        q.table = p.table.astype(np.float16).astype(np.float32)
+        propr.append(q)
+    rng = np.random.default_rng(108)
+    idx = np.sort(rng.choice(o.shape[0], 1000, replace=False))
+    r = orc.render(sc, host(o)[idx], host(d)[idx], ray_ids=idx, fields=rounded, field_occupancy=bits,
+                   field_proposals=propr, n_prop=32, n_fine=32)
+    assert (r["samples"] > 0).mean() > 0.2
+    compare_render({k: v[idx] for k, v in g.items()}, r, "3 mid fields, proposals, fp16 800x450 sample",
+                   rtol=2e-3, atol=1e-5)
+    assert np.all(g["throughput"] <= 1 + 1e-6) and np.all(g["radiance"] >= 0)
+
+
 def test_one_field_list_is_mr_render():
     """mr_render_fields with one field is mr_render, bit for bit."""
     sc = sg.tiny_scene(table_amp=1.0)
