@@ -1,0 +1,135 @@
+"""The benchmark's further workloads at full size, compared with the oracle on
+seeded samples of their rays: the GPU renders the whole image in the launch
+configuration bench.py times, and the oracle re-renders the sampled rays one
+by one (hit ids and bounces exact off ties, radiance to the FP32 tolerance)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2309_04581_amd import scenegen as sg
+
+torch = pytest.importorskip("torch")
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+pytestmark = pytest.mark.gpu
+
+from test_gpu_parity import compare_render, host, mr  # noqa: E402
+
+N_SAMPLE = 500
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    orc.build(force=False)
+
+
+@pytest.fixture(scope="module")
+def mid_occupancy():
+    """The oracle's own 128^3 grid of the mid field (every cell occupied by a
+    wide margin, so FP32 and FP64 agree on it)."""
+    sc = sg.mid_scene()
+    bits, margin = orc.occupancy(sc.field, sc.occupancy_res, sc.occupancy_thresh)
+    assert np.abs(margin).min() > 1e-3
+    return bits
+
+
+def _sampled(n, seed, k=N_SAMPLE):
+    return np.sort(np.random.default_rng(seed).choice(n, k, replace=False))
+
+
+def _gpu_image(M, R):
+    torch.cuda.synchronize()
+    return dict(radiance=host(R.radiance), throughput=host(R.throughput), bounces=host(R.bounces),
+                hit_ids=host(R.hit_ids))
+
+
+def _check(g, sc, o, d, idx, what, max_tie_frac=0.05, rtol=1e-4, **oracle_kw):
+    r = orc.render(sc, host(o)[idx], host(d)[idx], ray_ids=idx, **oracle_kw)
+    compare_render({k: v[idx] for k, v in g.items()}, r, what, rtol=rtol, max_tie_frac=max_tie_frac)
+    assert np.all(g["throughput"] <= 1 + 1e-6) and np.all(g["radiance"] >= 0)
+    return r
+
+
+@pytest.mark.parametrize("step", [3, 11])
+def test_moving_field_full_size_sampled(step, mid_occupancy):
+    """The moving-field workload: the mid scene with the field placed as the
+    benchmark places it on a given step (turned 0.05 rad per step about y,
+    moved 0.02 per step along x), occupancy grid, 800x800.  Radiance within
+    1e-3 relative: a chord that enters the turned box through one face and
+    leaves through the next one close to their common edge has both ends set
+    by direction components in the field frame that cancel (0.04 for one
+    sampled ray at step 11), so the FP32 rounding of the change of frame moves
+    the chord by about 3e-7 / 0.04; for that ray a one-ulp change of the input
+    direction already moves the FP64 radiance by 5e-4 relative."""
+    M = mr()
+    sc = sg.mid_scene()
+    sc.field.pose = sg.pose_matrix(sg.rotation((0.0, 1.0, 0.0), 0.05 * step), (0.02 * step, 0.0, 0.0))
+    o, d, _ = M.camera_rays(sg.cameras_array(sc.cameras))
+    F, G = M.Field(sc.field), M.Mesh(sc.mesh)
+    F.build_occupancy(sc.occupancy_res, sc.occupancy_thresh)
+    R = M.Renderer(o.shape[0], sc.max_bounces)
+    R.render(F, G, o, d, sc.lights, M.make_opts(sc, use_occupancy=True))
+    g = _gpu_image(M, R)
+    _check(g, sc, o, d, _sampled(o.shape[0], 200 + step), f"moving field step {step}", rtol=1e-3,
+           occupancy_bits=mid_occupancy)
+
+
+def test_sample_shadows_full_size_sampled(mid_occupancy):
+    """The per-sample shadow mask workload: mid scene, mask 0.2, occupancy
+    grid, 800x800."""
+    M = mr()
+    sc = sg.mid_scene()
+    o, d, _ = M.camera_rays(sg.cameras_array(sc.cameras))
+    F, G = M.Field(sc.field), M.Mesh(sc.mesh)
+    F.build_occupancy(sc.occupancy_res, sc.occupancy_thresh)
+    R = M.Renderer(o.shape[0], sc.max_bounces)
+    R.render(F, G, o, d, sc.lights, M.make_opts(sc, use_occupancy=True, shadow_mask=0.2))
+    g = _gpu_image(M, R)
+    # a shadow ray that grazes a triangle edge is a tie: about 4% of the paths
+    # send one such ray among their tens of shadow rays
+    _check(g, sc, o, d, _sampled(o.shape[0], 210), "sample shadows 800x800", max_tie_frac=0.08,
+           occupancy_bits=mid_occupancy, shadow_mask=0.2)
+
+
+@pytest.mark.parametrize("sample_emitters", [False, True])
+def test_emitter_scene_full_size_sampled(sample_emitters):
+    """The emitter workload: the mid scene with an emitting ceiling panel,
+    800x800, occupancy grid, with and without light sampling toward it."""
+    M = mr()
+    sc = sg.emitter_scene()
+    bits, margin = orc.occupancy(sc.field, sc.occupancy_res, sc.occupancy_thresh)
+    assert np.abs(margin).min() > 1e-3
+    o, d, _ = M.camera_rays(sg.cameras_array(sc.cameras))
+    F, G = M.Field(sc.field), M.Mesh(sc.mesh)
+    F.build_occupancy(sc.occupancy_res, sc.occupancy_thresh)
+    R = M.Renderer(o.shape[0], sc.max_bounces)
+    R.render(F, G, o, d, sc.lights, M.make_opts(sc, use_occupancy=True, sample_emitters=sample_emitters))
+    g = _gpu_image(M, R)
+    _check(g, sc, o, d, _sampled(o.shape[0], 220 + int(sample_emitters)),
+           f"emitter scene 800x800 sample_emitters={sample_emitters}", occupancy_bits=bits,
+           sample_emitters=sample_emitters)
+
+
+def test_cloth_full_size_sampled_after_refits():
+    """The cloth workload: 800x800 over the tiny field, 256 samples, 8 bounces.
+    The BVH is built on frame 0 and refit frame by frame as the benchmark does;
+    frames 0 and 37 are compared on 2000 seeded rays each (the cloth covers
+    about 5% of the image; the oracle takes each frame's mesh itself)."""
+    M = mr()
+    sc0 = sg.cloth_scene(0)
+    o, d, _ = M.camera_rays(sg.cameras_array(sc0.cameras))
+    F, G = M.Field(sc0.field), M.Mesh(sc0.mesh)
+    R = M.Renderer(o.shape[0], sc0.max_bounces)
+    for frame in range(38):
+        if frame:
+            G.refit(torch.from_numpy(sg.cloth_vertices(frame)).cuda())
+        if frame in (0, 37):
+            sc = sg.cloth_scene(frame)
+            R.render(F, G, o, d, sc.lights, M.make_opts(sc))
+            g = _gpu_image(M, R)
+            r = _check(g, sc, o, d, _sampled(o.shape[0], 230 + frame, 2000), f"cloth frame {frame}")
+            assert (r["hit_ids"][:, 0] >= 0).sum() > 40
