@@ -81,6 +81,28 @@ RayQueue queue_at(void* base, int64_t cap) {
 
 namespace {
 
+// a*b - c*d as the difference of the exact products, rounded: Kahan's method
+// (the rounding error of c*d recovered by an FMA) is within 1.5 ulp, so its
+// sign is the exact one, and two equal nonzero products give +0.  When c*d is
+// zero the plain difference is that value already, with the signed zero that
+// IEEE arithmetic gives.
+__device__ __forceinline__ float diff_prod(float a, float b, float c, float d) {
+  const float w = c * d;
+  if (w == 0.0f) return a * b - w;
+  const float e = __fmaf_rn(-c, d, w);   // w - c d, exactly
+  const float f = __fmaf_rn(a, b, -w);   // a b - w, rounded once
+  return f + e;
+}
+
+// Unnormalised face normal e1 x e2 with every component the rounded
+// difference of exact products.  The cosine-sampling basis switches on the
+// sign of the normal's z: for a triangle parallel to z (two vertices with
+// equal x and y) a plain FMA-contracted product difference returns the
+// rounding error of one product, of either sign, instead of zero.
+__device__ __forceinline__ V3 face_normal(V3 a, V3 b) {
+  return v3(diff_prod(a.y, b.z, a.z, b.y), diff_prod(a.z, b.x, a.x, b.z), diff_prod(a.x, b.y, a.y, b.x));
+}
+
 // ---------------------------------------------------------------------------
 // queue initialisation from caller rays
 // ---------------------------------------------------------------------------
@@ -204,7 +226,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade(RayQueue qi, const int* _
         const float t = qi.hit_t[i];
         const float4 q0 = M.bvh.tris[3 * p], q1 = M.bvh.tris[3 * p + 1], q2 = M.bvh.tris[3 * p + 2];
         const V3 v0 = v3(q0.x, q0.y, q0.z), v1 = v3(q1.x, q1.y, q1.z), v2 = v3(q2.x, q2.y, q2.z);
-        V3 n = cross(v1 - v0, v2 - v0);
+        V3 n = face_normal(v1 - v0, v2 - v0);
         const float nl = sqrtf(dot(n, n));
         n = v3(n.x / nl, n.y / nl, n.z / nl);
         const V3 P = o + t * d;

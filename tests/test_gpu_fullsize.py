@@ -133,3 +133,22 @@ def test_cloth_full_size_sampled_after_refits():
             g = _gpu_image(M, R)
             r = _check(g, sc, o, d, _sampled(o.shape[0], 230 + frame, 2000), f"cloth frame {frame}")
             assert (r["hit_ids"][:, 0] >= 0).sum() > 40
+
+
+@pytest.mark.parametrize("n_balls", [1000, 10000])
+def test_scaling_spheres_full_size_sampled(n_balls, mid_occupancy):
+    """The App. A scaling workload at its largest sizes: 1 000 and 10 000
+    spheres (80 002 and 800 002 triangles) over the mid field, 900x450,
+    occupancy grid.  Many small spheres put more shadow and scatter rays near
+    triangle edges, so up to 6% of the sampled paths are ties."""
+    M = mr()
+    sc = sg.balls_scene(n_balls)
+    o, d, _ = M.camera_rays(sg.cameras_array(sc.cameras))
+    F, G = M.Field(sc.field), M.Mesh(sc.mesh)
+    F.build_occupancy(sc.occupancy_res, sc.occupancy_thresh)
+    R = M.Renderer(o.shape[0], sc.max_bounces)
+    R.render(F, G, o, d, sc.lights, M.make_opts(sc, use_occupancy=True))
+    g = _gpu_image(M, R)
+    r = _check(g, sc, o, d, _sampled(o.shape[0], 240 + n_balls % 7), f"{n_balls} spheres 900x450",
+               max_tie_frac=0.06, occupancy_bits=mid_occupancy)
+    assert (r["hit_ids"][:, 0] >= 0).mean() > 0.1
