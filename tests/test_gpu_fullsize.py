@@ -152,3 +152,66 @@ def test_scaling_spheres_full_size_sampled(n_balls, mid_occupancy):
     r = _check(g, sc, o, d, _sampled(o.shape[0], 240 + n_balls % 7), f"{n_balls} spheres 900x450",
                max_tie_frac=0.06, occupancy_bits=mid_occupancy)
     assert (r["hit_ids"][:, 0] >= 0).mean() > 0.1
+
+
+def _rounded_proposal(p):
+    import copy
+    q = copy.deepcopy(p)
+    q.table = p.table.astype(np.float16).astype(np.float32)
+    return q
+
+
+def test_proposal_fp16_with_sample_shadows_full_size_sampled(mid_occupancy):
+    """The proposal configuration with the per-sample shadow mask (mask 0.2):
+    mid scene 800x800, FP16 table + BF16 MLPs, FP16 seeded proposal, 32 + 32
+    samples, occupancy grid; the oracle on the parameters as the GPU holds
+    them; radiance within 2e-3 relative (the BF16 rounding of layer inputs)."""
+    import bench
+    M = mr()
+    sc = sg.mid_scene()
+    prop = sg.make_proposal()
+    o, d, _ = M.camera_rays(sg.cameras_array(sc.cameras))
+    F = M.Field(sc.field, table_dtype=M.MR_F16, mlp_dtype=M.MR_BF16)
+    F.build_occupancy(sc.occupancy_res, sc.occupancy_thresh)
+    P = M.Field(prop, table_dtype=M.MR_F16)
+    G = M.Mesh(sc.mesh)
+    R = M.Renderer(o.shape[0], sc.max_bounces)
+    R.render(F, G, o, d, sc.lights, M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P, use_occupancy=True,
+                                                shadow_mask=0.2))
+    g = _gpu_image(M, R)
+    scr = sg.mid_scene()
+    scr.field = bench._rounded_field(sg, sc.field)
+    bits, margin = orc.occupancy(scr.field, sc.occupancy_res, sc.occupancy_thresh)
+    assert np.abs(margin).min() > 1e-3
+    idx = _sampled(o.shape[0], 250)
+    r = orc.render(scr, host(o)[idx], host(d)[idx], ray_ids=idx, occupancy_bits=bits, proposal=_rounded_proposal(prop),
+                   n_prop=32, n_fine=32, shadow_mask=0.2)
+    compare_render({k: v[idx] for k, v in g.items()}, r, "proposal fp16 + sample shadows 800x800", rtol=2e-3,
+                   atol=1e-5, max_tie_frac=0.08)
+
+
+def test_cloth_proposal_fp16_full_size_sampled():
+    """The cloth workload's proposal configuration: 800x800 over the tiny field
+    with FP16 table + BF16 MLPs and an FP16 seeded proposal (32 + 32), after
+    refits to frame 20; the oracle on the rounded parameters, 2000 rays."""
+    import bench
+    M = mr()
+    sc0 = sg.cloth_scene(0)
+    prop = sg.make_proposal(seed=9)
+    o, d, _ = M.camera_rays(sg.cameras_array(sc0.cameras))
+    F = M.Field(sc0.field, table_dtype=M.MR_F16, mlp_dtype=M.MR_BF16)
+    P = M.Field(prop, table_dtype=M.MR_F16)
+    G = M.Mesh(sc0.mesh)
+    for frame in range(1, 21):
+        G.refit(torch.from_numpy(sg.cloth_vertices(frame)).cuda())
+    sc = sg.cloth_scene(20)
+    R = M.Renderer(o.shape[0], sc.max_bounces)
+    R.render(F, G, o, d, sc.lights, M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P))
+    g = _gpu_image(M, R)
+    scr = sg.cloth_scene(20)
+    scr.field = bench._rounded_field(sg, sc.field)
+    idx = _sampled(o.shape[0], 260, 2000)
+    r = orc.render(scr, host(o)[idx], host(d)[idx], ray_ids=idx, proposal=_rounded_proposal(prop), n_prop=32,
+                   n_fine=32)
+    compare_render({k: v[idx] for k, v in g.items()}, r, "cloth proposal fp16 frame 20", rtol=2e-3, atol=1e-5)
+    assert (r["hit_ids"][:, 0] >= 0).sum() > 40
