@@ -263,16 +263,16 @@ mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64_t n, const
  * among the meshes; the paper's dynamic, mesh-aware scenes hold more than one
  * radiance field).  The medium is their sum: density sigma_1 + sigma_2 + ...
  * and colour the density-weighted mean, each field zero outside its box.
- * When the world boxes (aabb under the pose) are pairwise disjoint (touching
- * allowed), every field is marched along each segment in a pass of its own
- * (on the same uniform grid, or with its own proposal) and the passes are
- * composited in the order the ray enters the boxes, which is that sum.  When
- * some boxes overlap, all fields are marched together over the summed medium:
- * the uniform grid is cut at every box face a segment crosses and each piece
- * sums the fields whose boxes hold it.  That needs the uniform sampler (a
- * proposal sampler is MR_ERR_UNSUPPORTED, naming the first overlapping pair)
- * and fields of one layout (levels, SH components, colour layers, table and
- * MLP types; else MR_ERR_UNSUPPORTED).
+ * Under the uniform sampler, fields of one layout (levels, SH components,
+ * colour layers, table and MLP types) are marched together over the summed
+ * medium: the grid is cut at every box face a segment crosses and each piece
+ * sums the fields whose world boxes (aabb under the pose) hold it; their
+ * boxes may overlap.  With the proposal sampler, or fields of different
+ * layouts, the world boxes must be pairwise disjoint (touching allowed): every
+ * field is marched in a pass of its own (with its own proposal) and the
+ * passes are composited in the order the ray enters the boxes, which is that
+ * sum.  Overlapping boxes there are MR_ERR_UNSUPPORTED, naming the first
+ * overlapping pair or the differing layouts.
  * fields: host array of n_fields (1..8) field handles.  proposals: host
  * array of n_fields proposal fields, field k sampled by proposals[k], when
  * opts->sampler is MR_SAMPLER_PROPOSAL (opts->proposal is then not used; a

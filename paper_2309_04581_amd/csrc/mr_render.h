@@ -135,12 +135,13 @@ mr_status dispatch_march_mfma(const mr_field* f, RayQueue q, const int* count, i
                               const BvhView& B, bool packets, unsigned long long* stats, int blocks_per_cu, int64_t n,
                               hipStream_t st);
 
-// march of several fields whose boxes overlap, over their summed medium
-// (march_fields.hip): one ray per wave on the uniform grid; the fields share
-// one layout (levels, SH components, colour layers, table and MLP types)
+// march of several fields, overlapping or not, over their summed medium
+// (march_fields.hip) on the uniform grid; the fields share one layout
+// (levels, SH components, colour layers, table and MLP types).  packets: 16
+// consecutive queue rays per wave in step (else one ray per wave)
 mr_status dispatch_march_fields(const mr_field* const* fields, int n_fields, RayQueue q, const int* count, int* work,
-                                const MarchParams& P, const BvhView& B, unsigned long long* stats, int blocks_per_cu,
-                                int64_t n, hipStream_t st);
+                                const MarchParams& P, const BvhView& B, bool packets, unsigned long long* stats,
+                                int blocks_per_cu, int64_t n, hipStream_t st);
 
 // proposal-sampled march (defined with the proposal kernels)
 // packets: 16 consecutive queue rays per wave when n_prop = 32 and n_fine <= 32

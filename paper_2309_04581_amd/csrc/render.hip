@@ -549,8 +549,9 @@ __global__ __launch_bounds__(64 * kWideWaves) void k_trace_wide(RayQueue q, cons
 // the segment's throughput and radiance (starting at T = 1, L = 0); the
 // passes are then composited in the order the ray enters the fields' boxes.
 // With boxes that do not overlap, every sample lies in at most one field, so
-// this is the march of the summed medium.  Boxes that overlap are marched
-// together instead, in one pass (march_fields.hip).
+// this is the march of the summed medium.  It serves the proposal sampler and
+// fields of different layouts; fields of one layout under the uniform sampler,
+// overlapping or not, are marched together in one pass (march_fields.hip).
 // ---------------------------------------------------------------------------
 struct FieldBoxes {
   int n;
@@ -810,7 +811,7 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
                       const float* origins, const float* dirs, int32_t max_bounces,
                       const int32_t* per_ray_max_bounces, const mr_light* host_lights, int32_t n_lights,
                       const mr_render_opts* opts, mr_render_out* out, void* workspace, size_t workspace_bytes,
-                      void* stream, bool overlapping = false) {
+                      void* stream, bool joint = false) {
   mr_status s = MR_OK;
   const mr_field* field = n_fields == 1 ? fields[0] : nullptr;
   if (n == 0) return MR_OK;
@@ -905,11 +906,11 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
                          opts->t_far, P.span, out->hit_ids, out->hit_ids ? out->hit_stride : 0);
       MR_HIP(hipGetLastError());
     }
-    if (n_fields > 1 && overlapping) {
-      // boxes that overlap: one march over the summed medium
+    if (n_fields > 1 && joint) {
+      // one march over the summed medium
       StageTimer tm(1, st);
-      s = dispatch_march_fields(fields, n_fields, qi, counts + b, work + kXcds * b, P, mv.bvh, stats,
-                                opts->march_blocks_per_cu, n, st);
+      s = dispatch_march_fields(fields, n_fields, qi, counts + b, work + kXcds * b, P, mv.bvh, b < packet_segments,
+                                stats, opts->march_blocks_per_cu, n, st);
       if (s != MR_OK) return s;
     } else if (n_fields > 1) {
       StageTimer tm(1, st);
@@ -1003,15 +1004,24 @@ extern "C" mr_status mr_render_fields(const mr_field* const* fields, const mr_fi
                                             " overlap in the world: overlapping fields take the uniform sampler");
       overlapping = true;
     }
-  if (overlapping)
-    for (int k = 1; k < n_fields; ++k) {   // one kernel marches them all: one layout
-      const FieldView &v0 = fields[0]->view, &vk = fields[k]->view;
-      if (vk.n_levels != v0.n_levels || vk.sh != v0.sh || vk.c_layers != v0.c_layers ||
-          vk.table_dtype != v0.table_dtype || vk.mlp_dtype != v0.mlp_dtype)
-        return fail(MR_ERR_UNSUPPORTED, "fields 0 and " + std::to_string(k) +
-                                            " differ in layout (levels, SH components, colour layers, table or MLP "
-                                            "type); fields whose boxes overlap must share one");
+  bool one_layout = true;
+  int other = 0;
+  for (int k = 1; k < n_fields; ++k) {
+    const FieldView &v0 = fields[0]->view, &vk = fields[k]->view;
+    if (vk.n_levels != v0.n_levels || vk.sh != v0.sh || vk.c_layers != v0.c_layers ||
+        vk.table_dtype != v0.table_dtype || vk.mlp_dtype != v0.mlp_dtype) {
+      one_layout = false;
+      other = k;
+      break;
     }
+  }
+  if (overlapping && !one_layout)   // one kernel marches them all: one layout
+    return fail(MR_ERR_UNSUPPORTED, "fields 0 and " + std::to_string(other) +
+                                        " differ in layout (levels, SH components, colour layers, table or MLP "
+                                        "type); fields whose boxes overlap must share one");
+  // fields of one layout under the uniform sampler are marched together
+  // whether or not their boxes overlap: one pass instead of one per field
+  const bool joint = !prop && one_layout;
   if (n_fields == 1) {   // one field: the ordinary render, with its proposal
     mr_render_opts o1 = *opts;
     if (prop) o1.proposal = proposals[0];
@@ -1020,7 +1030,7 @@ extern "C" mr_status mr_render_fields(const mr_field* const* fields, const mr_fi
   }
   return render_impl(fields, prop ? proposals : nullptr, n_fields, mesh, n, origins, dirs, max_bounces,
                      per_ray_max_bounces, host_lights, n_lights, opts, out, workspace, workspace_bytes, stream,
-                     overlapping);
+                     joint);
 }
 
 extern "C" mr_status mr_profile_enable(int32_t on) {

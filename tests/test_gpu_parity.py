@@ -803,27 +803,31 @@ def _overlap_fraction(fields, o, d):
     return both.mean()
 
 
-@pytest.mark.parametrize("n_fields,spacing", [(2, 1.2), (3, 1.2), (3, 0.0), (8, 0.5)])
-def test_overlapping_fields_match_oracle(n_fields, spacing):
+@pytest.mark.parametrize("n_fields,spacing,packets", [(2, 1.2, 0), (3, 1.2, 0), (3, 1.2, -1), (3, 1.2, 99),
+                                                      (3, 0.0, 0), (8, 0.5, 0), (8, 0.5, -1)])
+def test_overlapping_fields_match_oracle(n_fields, spacing, packets):
     """Boxes that overlap (1.2 apart, all on one centre with different turns,
     which makes their y faces coincide, or the most fields, 0.5 apart): the
     fields are marched together over the summed medium (density sum,
     density-weighted colour, the grid cut at every box face), against the
     oracle's march of the same sum; the count of field evaluations equals the
-    oracle's."""
+    oracle's.  Packets on the camera segment (default), on no segment or on
+    every segment."""
     sc = sg.fields_scene(n_fields, 48, 27, kind="tiny", table_amp=1.0, spacing=spacing)
     o, d = oracle_camera_rays(sc)
     assert _overlap_fraction(sc.fields, o.astype(np.float64), d.astype(np.float64)) > 0.04
     r = orc.render(sc, o, d, fields=sc.fields)
     assert (r["samples"] > 0).mean() > 0.15
-    g = _fields_gpu(sc, o, d)
-    compare_render(g, r, f"{n_fields} overlapping fields spacing={spacing}", rtol=1e-3, atol=1e-6)
+    g = _fields_gpu(sc, o, d, packets=packets)
+    compare_render(g, r, f"{n_fields} overlapping fields spacing={spacing} packets={packets}", rtol=1e-3, atol=1e-6)
     assert int(g["counters"][0]) == int(r["samples"].sum())
 
 
-def test_overlapping_fields_with_occupancy_and_sample_shadows_match_oracle():
+@pytest.mark.parametrize("packets", [0, 99])
+def test_overlapping_fields_with_occupancy_and_sample_shadows_match_oracle(packets):
     """Three overlapping copies of the sparse field, each with its own
-    occupancy grid, and the per-sample shadow mask toward the light."""
+    occupancy grid, and the per-sample shadow mask toward the light; packets
+    on the camera segment or on every segment."""
     sc = sg.fields_scene(3, 48, 27, kind="tiny", spacing=1.0)
     base = _sparse_field()
     fields = []
@@ -838,8 +842,9 @@ def test_overlapping_fields_with_occupancy_and_sample_shadows_match_oracle():
     o, d = oracle_camera_rays(sc)
     assert _overlap_fraction(fields, o.astype(np.float64), d.astype(np.float64)) > 0.04
     r = orc.render(sc, o, d, fields=fields, field_occupancy=[bits] * 3, shadow_mask=0.2)
-    g = _fields_gpu(sc, o, d, use_occupancy=True, occ_res=32, shadow_mask=0.2)
-    compare_render(g, r, "3 overlapping sparse fields, occupancy, sample shadows", rtol=1e-3, atol=1e-6)
+    g = _fields_gpu(sc, o, d, use_occupancy=True, occ_res=32, shadow_mask=0.2, packets=packets)
+    compare_render(g, r, f"3 overlapping sparse fields, occupancy, sample shadows, packets={packets}", rtol=1e-3,
+                   atol=1e-6)
     assert int(g["counters"][0]) == int(r["samples"].sum())
 
 
