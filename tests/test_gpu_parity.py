@@ -994,6 +994,29 @@ def test_several_mid_fields_proposal_fp16_full_size_sampled():
     assert np.all(g["throughput"] <= 1 + 1e-6) and np.all(g["radiance"] >= 0)
 
 
+def test_several_fields_of_different_layouts_match_oracle():
+    """Disjoint fields of different layouts under the uniform sampler take one
+    pass per field (the joint march needs one layout): a tiny field with an
+    FP32 table beside two with FP16 tables, against the oracle with those
+    tables rounded to FP16."""
+    M = mr()
+    sc = sg.fields_scene(3, 48, 27, kind="tiny", table_amp=1.0)
+    o, d = oracle_camera_rays(sc)
+    rounded = [sc.fields[0]] + [copy.deepcopy(f) for f in sc.fields[1:]]
+    for f in rounded[1:]:
+        f.table = f.table.astype(np.float16).astype(np.float32)
+    r = orc.render(sc, o, d, fields=rounded)
+    Fs = [M.Field(sc.fields[0])] + [M.Field(f, table_dtype=M.MR_F16) for f in sc.fields[1:]]
+    G = M.Mesh(sc.mesh)
+    R = M.Renderer(len(o), sc.max_bounces)
+    R.render_fields(Fs, G, dev(o), dev(d), sc.lights, M.make_opts(sc))
+    torch.cuda.synchronize()
+    g = dict(radiance=host(R.radiance), throughput=host(R.throughput), bounces=host(R.bounces),
+             hit_ids=host(R.hit_ids), counters=host(R.counters))
+    compare_render(g, r, "3 fields of two layouts", rtol=1e-3, atol=1e-6)
+    assert int(g["counters"][0]) == int(r["samples"].sum())
+
+
 def test_one_field_list_is_mr_render():
     """mr_render_fields with one field is mr_render, bit for bit."""
     sc = sg.tiny_scene(table_amp=1.0)
