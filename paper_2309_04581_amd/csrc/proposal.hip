@@ -507,6 +507,11 @@ __global__ __launch_bounds__(256) void k_prop_targets(FieldView F, const TabT* _
 // ---------------------------------------------------------------------------
 // proposal loss and gradient (one wave per segment, one bin per lane)
 // ---------------------------------------------------------------------------
+// The gradient of a dense level 0 of up to 17^3 entries is summed in LDS per
+// block and added to the global gradient once per block: every sample hits
+// that level, and the samples of one segment share most of its corners.
+constexpr int kPropL0Lds = 2 * 17 * 17 * 17;
+
 __global__ __launch_bounds__(256) void k_prop_grad(FieldView P, const float* __restrict__ table,
                                                    const float* __restrict__ mlp, int64_t n,
                                                    const float* __restrict__ o, const float* __restrict__ d,
@@ -515,10 +520,14 @@ __global__ __launch_bounds__(256) void k_prop_grad(FieldView P, const float* __r
                                                    float* __restrict__ g_mlp, float* __restrict__ loss) {
   __shared__ float sW[kPropMlp];
   __shared__ float sG[kPropMlp];
+  __shared__ float sL0[kPropL0Lds];
   for (int i = threadIdx.x; i < kPropMlp; i += blockDim.x) {
     sW[i] = mlp[i];
     sG[i] = 0.0f;
   }
+  const int n1 = P.res[0] + 1;
+  const int n_l0 = (P.dense_mask & 1u) && 2 * n1 * n1 * n1 <= kPropL0Lds ? 2 * n1 * n1 * n1 : 0;
+  for (int i = threadIdx.x; i < n_l0; i += blockDim.x) sL0[i] = 0.0f;
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
@@ -582,7 +591,7 @@ __global__ __launch_bounds__(256) void k_prop_grad(FieldView P, const float* __r
       uint32_t idx[8];
       float wc[8];
       level_corners(P, l, xh, yh, zh, idx, wc);
-      float* gt = g_table + (size_t)l * T * 2;
+      float* gt = (l == 0 && n_l0) ? sL0 : g_table + (size_t)l * T * 2;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         atomicAdd(gt + 2 * (size_t)idx[c], wc[c] * df[2 * l]);
@@ -595,6 +604,8 @@ __global__ __launch_bounds__(256) void k_prop_grad(FieldView P, const float* __r
   __syncthreads();
   for (int i = threadIdx.x; i < kPropMlp; i += blockDim.x)
     if (sG[i] != 0.0f) atomicAdd(g_mlp + i, sG[i]);
+  for (int i = threadIdx.x; i < n_l0; i += blockDim.x)
+    if (sL0[i] != 0.0f) atomicAdd(g_table + i, sL0[i]);
 }
 
 __global__ void k_fill(float* __restrict__ p, int64_t n, float v) {
