@@ -537,12 +537,40 @@ void orc_proposal_weights(const orc_field* p, const double o[3], const double d[
   }
 }
 
+/* Fine edges of the proposal sampler (the learned sampler is not in the
+ * paper; it follows the proposal resampling of Mip-NeRF 360): the proposal
+ * weights w_j on np uniform intervals of [lo, hi] are dilated to
+ * max(w_{j-1}, w_j, w_{j+1}), their mean is added to every interval (a
+ * half-and-half mixture with a uniform density) and so is 1e-3/np; the
+ * resulting piecewise-constant density is inverted at u = k/nf for the
+ * nf + 1 edges, edges[0] = lo and edges[nf] = hi. */
+void orc_proposal_edges(const double* w, int32_t np, int32_t nf, double lo, double hi,
+                        double* edges) {
+  double wd[1024], cdf[1025], sw = 0.0, tot = 0.0;
+  for (int j = 0; j < np; ++j) {
+    double m = w[j];
+    if (j > 0 && w[j - 1] > m) m = w[j - 1];
+    if (j + 1 < np && w[j + 1] > m) m = w[j + 1];
+    wd[j] = m;
+    sw += m;
+  }
+  cdf[0] = 0.0;
+  for (int j = 0; j < np; ++j) { tot += wd[j] + sw / np + 1e-3 / np; cdf[j + 1] = tot; }
+  double step = (hi - lo) / np;
+  int j = 0;
+  for (int k = 0; k <= nf; ++k) {
+    double u = (double)k / nf * tot;
+    if (k == 0) { edges[k] = lo; continue; }
+    if (k == nf) { edges[k] = hi; continue; }
+    while (j < np - 1 && cdf[j + 1] < u) ++j;
+    double fr = (u - cdf[j]) / (cdf[j + 1] - cdf[j]);
+    edges[k] = lo + (j + fr) * step;
+  }
+}
+
 /* Segment march over [lo, hi]: uniform grid of n_samples intervals of width
- * (t_far - t_near)/n_samples anchored at t_a, or the proposal's fine intervals:
- * proposal weights w_j on n_prop uniform intervals, dilated to
- * max(w_{j-1}, w_j, w_{j+1}), plus their mean (a half-and-half mixture with a
- * uniform density) plus 1e-3/n_prop; the n_fine + 1 edges are the inverse CDF
- * of that piecewise-constant density at u = k/n_fine. */
+ * (t_far - t_near)/n_samples anchored at t_a, or, with a proposal, the
+ * n_fine intervals between the edges of orc_proposal_edges. */
 static int64_t march(const orc_field* f, const orc_opts* opt, const double o_world[3],
                      const double d_world[3], double t_a, double t_hit, double T[3], double L[3],
                      int* tie, const shadow_ctx* sh_in) {
@@ -566,30 +594,9 @@ static int64_t march(const orc_field* f, const orc_opts* opt, const double o_wor
   int64_t ns = 0;
   if (opt->proposal) {
     int np = opt->n_prop, nf = opt->n_fine;
-    double w[1024], cdf[1025], edges[1025];
+    double w[1024], edges[1025];
     orc_proposal_weights(opt->proposal, o, d, lo, hi, np, w);
-    double tot = 0.0;
-    cdf[0] = 0.0;
-    /* dilate over adjacent bins, then mix half and half with a uniform density */
-    double wd[1024], sw = 0.0;
-    for (int j = 0; j < np; ++j) {
-      double m = w[j];
-      if (j > 0 && w[j - 1] > m) m = w[j - 1];
-      if (j + 1 < np && w[j + 1] > m) m = w[j + 1];
-      wd[j] = m;
-      sw += m;
-    }
-    for (int j = 0; j < np; ++j) { tot += wd[j] + sw / np + 1e-3 / np; cdf[j + 1] = tot; }
-    double step = (hi - lo) / np;
-    int j = 0;
-    for (int k = 0; k <= nf; ++k) {
-      double u = (double)k / nf * tot;
-      if (k == 0) { edges[k] = lo; continue; }
-      if (k == nf) { edges[k] = hi; continue; }
-      while (j < np - 1 && cdf[j + 1] < u) ++j;
-      double fr = (u - cdf[j]) / (cdf[j + 1] - cdf[j]);
-      edges[k] = lo + (j + fr) * step;
-    }
+    orc_proposal_edges(w, np, nf, lo, hi, edges);
     for (int k = 0; k < nf; ++k) ns += composite_interval(f, opt, o, d, edges[k], edges[k + 1], T, L, tie, sh);
     return ns;
   }

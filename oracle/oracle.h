@@ -123,6 +123,8 @@ void orc_build_occupancy(const orc_field* f, int32_t res, double thresh, uint8_t
 /* ---- proposal sampler and its loss (proposal forward / backward) ---- */
 void orc_proposal_weights(const orc_field* p, const double o[3], const double d[3],
                           double lo, double hi, int32_t n, double* w);
+void orc_proposal_edges(const double* w, int32_t np, int32_t nf, double lo, double hi,
+                        double* edges);
 void orc_proposal_targets(const orc_field* f, int64_t n, const float* origins, const float* dirs,
                           double t_near, double t_far, int32_t n_samples, int32_t n_bins,
                           double* lohi, double* target);

@@ -317,6 +317,16 @@ def proposal_weights(prop, o, d, lo, hi, n):
     return w
 
 
+def proposal_edges(w, n_fine, lo, hi):
+    """Fine-interval edges (n_fine + 1) that the proposal sampler places on
+    [lo, hi] for the proposal weights w (one per uniform interval)."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    e = np.zeros(n_fine + 1)
+    lib().orc_proposal_edges(_p(w), C.c_int32(len(w)), C.c_int32(n_fine), C.c_double(lo),
+                             C.c_double(hi), _p(e))
+    return e
+
+
 def proposal_loss(prop, o, d, lohi, target, grads=True, n_threads=None):
     """Mean proposal loss over segments and, optionally, its exact FP64
     gradient w.r.t. the table [L, T, F] and the flat MLP weights."""
