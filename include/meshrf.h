@@ -91,10 +91,12 @@ typedef struct mr_field mr_field;
  *             (color_hidden_layers = 0) only the two density layers.
  * Supported shapes: density_in = 32 (or n_levels*feats <= 16 for a proposal),
  * density_hidden = 64 (16 for a proposal), density_out = 16 (1), color_in =
- * 32, color_hidden = 64, color_hidden_layers 1 or 2, sh_components 4 or 16.
- * Non-finite parameters are MR_ERR_INVALID_ARG; other shapes are
- * MR_ERR_UNSUPPORTED.  The table is converted to table_dtype and the MLP
- * copied (and rounded to bf16 for MR_BF16) on the device. */
+ * 32, color_hidden = 64, and (n_levels, sh_components, color_hidden_layers)
+ * one of (8, 4, 1), (16, 16, 2), (16, 4, 1), (8, 16, 2); a proposal field
+ * has 5 levels.  Non-finite parameters are MR_ERR_INVALID_ARG; other shapes
+ * are MR_ERR_UNSUPPORTED, refused before anything is allocated.  The table
+ * is converted to table_dtype and the MLP copied (and rounded to bf16 for
+ * MR_BF16) on the device. */
 mr_status mr_field_create(const mr_field_desc* desc, const float* host_table,
                           const float* host_mlp, void* stream, mr_field** out);
 mr_status mr_field_destroy(mr_field* f);
@@ -228,6 +230,12 @@ typedef struct {
                                    (emitters two-sided).  A path that reaches an emitter
                                    straight after a diffuse scatter then adds no L_e there.
                                    0: emission only where paths reach it */
+  int32_t wait_polls;           /* bound on each wait between the producer and consumer
+                                   waves of the packet march, in polls (0 = 2^26, about
+                                   seconds).  A wave whose wait runs out stops; the rays of
+                                   its packets then miss this segment's medium and
+                                   mr_render_status reports it.  Never reached in a correct
+                                   run: a bound that keeps every kernel finite */
 } mr_render_opts;
 
 /* One launch shape (the launch fields of mr_render_opts). */
@@ -253,11 +261,22 @@ size_t mr_render_workspace_size(int64_t n);
  * Each ray marches at most max_bounces + 1 segments.  field NULL = empty
  * medium; mesh NULL = no surfaces.  host_lights: n_lights point lights.
  * workspace: device buffer of mr_render_workspace_size(n) bytes, 256-byte
- * aligned, not shared with a concurrent call. */
+ * aligned, not shared with a concurrent call.
+ * The proposal sampler serves the (8, 4, 1) and (16, 16, 2) layouts; another
+ * layout is MR_ERR_UNSUPPORTED.  Every refusal (status other than MR_OK and
+ * MR_ERR_DEVICE) comes before the first launch, and then no output or
+ * workspace byte is written. */
 mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64_t n, const float* origins,
                     const float* dirs, int32_t max_bounces, const int32_t* per_ray_max_bounces,
                     const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
                     mr_render_out* out, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Status of the last render that used this workspace (mr_render,
+ * mr_render_fields or a graph launch): waits for `stream`, writes to
+ * *gave_up (optional) the number of packet-march waves whose bounded wait
+ * gave up, and returns MR_ERR_DEVICE when it is not 0 (the render's outputs
+ * are then incomplete), else MR_OK.  Synchronises with the host. */
+mr_status mr_render_status(const void* workspace, int64_t* gave_up, void* stream);
 
 /* Several fields in one scene (NeRF objects placed by mr_field_set_pose
  * among the meshes; the paper's dynamic, mesh-aware scenes hold more than one
@@ -366,8 +385,11 @@ mr_status mr_proposal_grad(const mr_field* proposal, int64_t n, const float* ori
                            float* g_table, float* g_mlp, void* stream);
 
 /* One Adam step on the FP32 master parameters with the gradient above; the
- * render copy of the table (FP16 or FP32) is refreshed.  The optimiser state
- * is allocated (hipMalloc) on the first call.  loss: device float. */
+ * render copy of the table (FP16 or FP32) is refreshed.  Step t (counted
+ * per field from 1) sets m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2 and
+ * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), with lr > 0,
+ * 0 <= b1, b2 < 1 and eps > 0 (else MR_ERR_INVALID_ARG).  The optimiser
+ * state is allocated (hipMalloc) on the first call.  loss: device float. */
 mr_status mr_proposal_train_step(mr_field* proposal, int64_t n, const float* origins, const float* dirs,
                                  const float* lohi, const float* targets, int32_t n_bins, const mr_adam* adam,
                                  float* loss, void* stream);

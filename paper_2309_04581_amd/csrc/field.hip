@@ -98,8 +98,9 @@ bool field_supported(const mr_field_desc& d, std::string& why) {
     why = "supported level counts: 8 and 16";
     return false;
   }
-  if (!((d.sh_components == 4 || d.sh_components == 16) && (d.color_hidden_layers == 1 || d.color_hidden_layers == 2))) {
-    why = "supported colour heads: 4 or 16 SH components, 1 or 2 hidden layers";
+  if (!march_layout(d.n_levels, d.sh_components, d.color_hidden_layers)) {
+    why = "supported layouts (levels, SH components, colour hidden layers): (8, 4, 1), (16, 16, 2), (16, 4, 1), "
+          "(8, 16, 2)";
     return false;
   }
   if (16 + d.sh_components > d.color_in) {

@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // ---------------------------------------------------------------------------
 constexpr int kPcPairs = 4;                 // producer/consumer pairs per block
 constexpr int kPcThreads = 128 * kPcPairs;  // waves 0..3 produce, 4..7 consume
-constexpr long long kPcSpin = 1ll << 26;    // polls before a wait gives up (seconds)
+constexpr int kPcSpin = 1 << 26;            // default polls before a wait gives up (seconds)
 enum { kSlotEmpty = 0, kSlotStart = 1, kSlotTile = 2, kSlotEnd = 3, kSlotDone = 4 };
 
 template <int NF>
@@ -255,8 +255,8 @@ __device__ __forceinline__ void pc_store(int* st, int v) {
 }
 // Wait until the slot is empty (producer) or holds a message (consumer);
 // false if the wait gave up (then the wave stops: a bound, not a protocol).
-__device__ __forceinline__ bool pc_wait(const int* st, bool want_empty) {
-  for (long long i = 0; i < kPcSpin; ++i) {
+__device__ __forceinline__ bool pc_wait(const int* st, bool want_empty, int polls) {
+  for (int i = 0; i < polls; ++i) {
     const int v = pc_load(st);
     if ((v == kSlotEmpty) == want_empty) return true;
     __builtin_amdgcn_s_sleep(1);
@@ -269,8 +269,7 @@ __global__ __launch_bounds__(kPcThreads) __attribute__((amdgpu_waves_per_eu(4)))
                                                          int* __restrict__ work, FieldView F,
                                                          const TabT* __restrict__ table,
                                                          const uint32_t* __restrict__ frags, MarchParams P,
-                                                         unsigned long long* __restrict__ stats,
-                                                         int* __restrict__ gave_up) {
+                                                         unsigned long long* __restrict__ stats) {
   using LY = FragLayout<NL, SH, CL, BF>;
   constexpr int NF = LY::NF;
   __shared__ __align__(16) uint32_t sW[LY::TOTAL];
@@ -317,7 +316,7 @@ __global__ __launch_bounds__(kPcThreads) __attribute__((amdgpu_waves_per_eu(4)))
       }
       if (kmin >= kmax) continue;
       // START: the packet's rays
-      if (!(ok = pc_wait(&sl[s].state, true))) break;
+      if (!(ok = pc_wait(&sl[s].state, true, P.wait_polls))) break;
       if (g == 0) {
         sl[s].r[j] = live ? R.r : -1;
         sl[s].dir[j][0] = R.dx;
@@ -334,7 +333,7 @@ __global__ __launch_bounds__(kPcThreads) __attribute__((amdgpu_waves_per_eu(4)))
         const float px = R.ox + tm * R.dx, py = R.oy + tm * R.dy, pz = R.oz + tm * R.dz;
         if (valid && use_occ) valid = occ_lookup(F, px, py, pz);
         if (__ballot(valid) == 0ull) continue;
-        if (!(ok = pc_wait(&sl[s].state, true))) break;
+        if (!(ok = pc_wait(&sl[s].state, true, P.wait_polls))) break;
         // the lane's levels in two halves straight into the slot (16 corner
         // loads in flight instead of 32 keeps the producer within its registers)
         float xh, yh, zh;
@@ -358,18 +357,18 @@ __global__ __launch_bounds__(kPcThreads) __attribute__((amdgpu_waves_per_eu(4)))
         if (g == 0 && valid) ++nsamp;
       }
       if (!ok) break;
-      if (!(ok = pc_wait(&sl[s].state, true))) break;
+      if (!(ok = pc_wait(&sl[s].state, true, P.wait_polls))) break;
       if (lane == 0) pc_store(&sl[s].state, kSlotEnd);
       s ^= 1;
     }
-    if (ok && (ok = pc_wait(&sl[s].state, true)))
+    if (ok && (ok = pc_wait(&sl[s].state, true, P.wait_polls)))
       if (lane == 0) pc_store(&sl[s].state, kSlotDone);
   } else {
     float u[4][4];
     float T = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
     int r = -1;
     while (true) {
-      if (!(ok = pc_wait(&sl[s].state, false))) break;
+      if (!(ok = pc_wait(&sl[s].state, false, P.wait_polls))) break;
       const int kind = pc_load(&sl[s].state);
       if (kind == kSlotDone) break;
       if (kind == kSlotStart) {
@@ -409,7 +408,7 @@ __global__ __launch_bounds__(kPcThreads) __attribute__((amdgpu_waves_per_eu(4)))
       s ^= 1;
     }
   }
-  if (!ok && lane == 0 && gave_up) atomicAdd(gave_up, 1);
+  if (!ok && lane == 0 && P.gave_up) atomicAdd(P.gave_up, 1);
   if (stats) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) nsamp += __shfl_xor(nsamp, off, 64);
@@ -475,8 +474,9 @@ mr_status launch_march_mode(const mr_field* f, RayQueue q, const int* count, int
     auto* kp = k_march_pc<NL, SH, CL, TabT, BF>;
     const int blocks = persistent_blocks(reinterpret_cast<const void*>(kp), kPcThreads, blocks_per_cu,
                                          (n + 16 * kPcPairs - 1) / (16 * kPcPairs));
-    hipLaunchKernelGGL(kp, dim3(blocks), dim3(kPcThreads), 0, st, q, count, work, f->view, tab, fr, P, stats,
-                       nullptr);
+    MarchParams Pw = P;
+    if (Pw.wait_polls <= 0) Pw.wait_polls = kPcSpin;
+    hipLaunchKernelGGL(kp, dim3(blocks), dim3(kPcThreads), 0, st, q, count, work, f->view, tab, fr, Pw, stats);
     MR_HIP(hipGetLastError());
     return MR_OK;
   }

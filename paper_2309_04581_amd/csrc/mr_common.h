@@ -18,6 +18,18 @@ constexpr int kStack = 48;          // BVH traversal stack depth (tree depth is 
 constexpr int kLeafSize = 4;
 constexpr int kTraceBlock = 128;    // threads per block of the traversal kernels
 
+// Radiance-field layouts (levels, SH components, colour hidden layers) that
+// have march and query kernels, and the subset that the proposal-sampled march
+// serves.  mr_field_create refuses every other layout and mr_render refuses a
+// proposal render of a layout outside the subset, before any launch.
+inline bool march_layout(int nl, int sh, int cl) {
+  return (nl == 8 && sh == 4 && cl == 1) || (nl == 16 && sh == 16 && cl == 2) || (nl == 16 && sh == 4 && cl == 1) ||
+         (nl == 8 && sh == 16 && cl == 2);
+}
+inline bool proposal_march_layout(int nl, int sh, int cl) {
+  return (nl == 8 && sh == 4 && cl == 1) || (nl == 16 && sh == 16 && cl == 2);
+}
+
 // ---------------------------------------------------------------------------
 // error reporting
 // ---------------------------------------------------------------------------

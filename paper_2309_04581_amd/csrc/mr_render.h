@@ -34,6 +34,11 @@ struct MarchParams {
   float shadow_mask;
   int n_lights;
   float light_pos[kMaxLights][3];
+  // producer/consumer packet march: polls each wait takes at most, and the
+  // device word that counts the waves whose wait gave up (their packets'
+  // rays are then left without this segment's medium)
+  int wait_polls;
+  int* gave_up;
 };
 
 // Shadow mask of the sample of column j (Sec. 3.1 "Shadow rays"): a lane of

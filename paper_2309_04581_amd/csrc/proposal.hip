@@ -730,6 +730,8 @@ extern "C" mr_status mr_proposal_targets(const mr_field* fine, int64_t n, const 
                                          float t_near, float t_far, int32_t n_samples, int32_t n_bins, float* lohi,
                                          float* targets, void* stream) {
   if (!fine || fine->view.c_layers == 0) return fail(MR_ERR_INVALID_ARG, "fine must be a radiance field");
+  if (!proposal_march_layout(fine->view.n_levels, fine->view.sh, fine->view.c_layers))
+    return fail(MR_ERR_UNSUPPORTED, "training targets support the 8-level/SH4/1-layer and 16-level/SH16/2-layer fields");
   if (n < 0) return fail(MR_ERR_INVALID_ARG, "n < 0");
   if (n == 0) return MR_OK;
   if (!origins || !dirs || !lohi || !targets) return fail(MR_ERR_INVALID_ARG, "null array");
@@ -768,8 +770,9 @@ extern "C" mr_status mr_proposal_train_step(mr_field* prop, int64_t n, const flo
   if (s != MR_OK) return s;
   if (!adam || !loss) return fail(MR_ERR_INVALID_ARG, "null adam or loss");
   if (!(adam->lr > 0.0f) || !(adam->beta1 >= 0.0f && adam->beta1 < 1.0f) ||
-      !(adam->beta2 >= 0.0f && adam->beta2 < 1.0f) || !(adam->eps >= 0.0f))
-    return fail(MR_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+      !(adam->beta2 >= 0.0f && adam->beta2 < 1.0f) || !(adam->eps > 0.0f) || !std::isfinite(adam->lr) ||
+      !std::isfinite(adam->eps))
+    return fail(MR_ERR_INVALID_ARG, "bad Adam hyper-parameters (need lr > 0, 0 <= beta < 1, eps > 0, finite)");
   hipStream_t st = (hipStream_t)stream;
   if (!prop->opt_dev) {
     const int64_t tot = 3 * (prop->n_table + kPropMlp);    // grad, m, v

@@ -719,6 +719,9 @@ mr_status validate_render(const mr_field* field, const mr_mesh* mesh, int64_t n,
       return fail(MR_ERR_INVALID_ARG, "proposal sampler needs a proposal field");
     if (opts->n_proposal < 1 || opts->n_proposal > 64 || opts->n_fine < 1 || opts->n_fine > 64)
       return fail(MR_ERR_INVALID_ARG, "n_proposal and n_fine must be in 1..64");
+    if (field && !proposal_march_layout(field->view.n_levels, field->view.sh, field->view.c_layers))
+      return fail(MR_ERR_UNSUPPORTED, "proposal sampling supports the 8-level/SH4/1-layer and 16-level/SH16/2-layer "
+                                      "fields");
   }
   if (field && field->view.c_layers == 0) return fail(MR_ERR_INVALID_ARG, "field is a proposal field");
   if (opts->march_blocks_per_cu < 0 || opts->march_blocks_per_cu > 64 || opts->stage_blocks_per_cu < 0 ||
@@ -729,6 +732,7 @@ mr_status validate_render(const mr_field* field, const mr_mesh* mesh, int64_t n,
   if (opts->march_chunk < 0) return fail(MR_ERR_INVALID_ARG, "march_chunk must be >= 0");
   if (opts->march_batch < 0 || opts->march_batch > 64) return fail(MR_ERR_INVALID_ARG, "march_batch must be in 0..64");
   if (opts->march_packets < -1) return fail(MR_ERR_INVALID_ARG, "march_packets must be >= -1");
+  if (opts->wait_polls < 0) return fail(MR_ERR_INVALID_ARG, "wait_polls must be >= 0");
   if (opts->sample_shadows && !(opts->shadow_mask >= 0.0f && opts->shadow_mask <= 1.0f))
     return fail(MR_ERR_INVALID_ARG, "shadow_mask must be in [0, 1]");
   if (opts->use_occupancy && field && !field->occ_dev)
@@ -747,6 +751,7 @@ extern "C" size_t mr_render_workspace_size(int64_t n) {
 // counters (kXcds per field) and the per-field scratch T and L arrays
 static constexpr size_t kFieldCtrBytes = 256;
 static_assert(kMaxFields * kXcds * sizeof(int) <= kFieldCtrBytes, "field counters");
+static_assert(((3 + kXcds) * (kMaxBounces + 2) + 1) * sizeof(int) <= kHeaderBytes, "workspace header");
 
 extern "C" size_t mr_render_fields_workspace_size(int64_t n, int32_t n_fields) {
   const int64_t cap = ((std::max<int64_t>(n, 1) + 63) / 64) * 64;
@@ -826,6 +831,7 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
   int* twork = counts + (kMaxBounces + 2);                  // closest-hit tile queue heads
   int* swork = twork + (kMaxBounces + 2);                   // shade tile queue heads
   int* work = swork + (kMaxBounces + 2);                    // march: kXcds ray queue heads per segment
+  int* gave_up = work + kXcds * (kMaxBounces + 2);          // march waits that gave up (mr_render_status)
   RayQueue Q[2] = {queue_at(ws + kHeaderBytes, cap), queue_at(ws + kHeaderBytes + queue_bytes(cap), cap)};
   int* fctr = reinterpret_cast<int*>(ws + mr_render_workspace_size(n));     // several fields only
   float* fscratch = reinterpret_cast<float*>(ws + mr_render_workspace_size(n) + kFieldCtrBytes);
@@ -845,7 +851,7 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
 
   const int init_blocks = (int)std::min<int64_t>((n + 255) / 256, 65535);
   hipLaunchKernelGGL(k_init, dim3(init_blocks), dim3(256), 0, st, n, origins, dirs, per_ray_max_bounces, max_bounces,
-                     Q[0], counts, (3 + kXcds) * (kMaxBounces + 2), out->hit_ids, out->hit_ids ? out->hit_stride : 0,
+                     Q[0], counts, (3 + kXcds) * (kMaxBounces + 2) + 1, out->hit_ids, out->hit_ids ? out->hit_stride : 0,
                      stats);
   MR_HIP(hipGetLastError());
 
@@ -868,6 +874,8 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
   P.n_lights = n_lights;
   for (int i = 0; i < n_lights; ++i)
     for (int k = 0; k < 3; ++k) P.light_pos[i][k] = host_lights[i].pos[k];
+  P.wait_polls = opts->wait_polls;
+  P.gave_up = gave_up;
 
   ShadeParams S;
   std::memset(&S, 0, sizeof(S));
@@ -972,6 +980,19 @@ extern "C" mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64
   if (s != MR_OK) return s;
   return render_impl(&field, nullptr, field ? 1 : 0, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces,
                      host_lights, n_lights, opts, out, workspace, workspace_bytes, stream);
+}
+
+extern "C" mr_status mr_render_status(const void* workspace, int64_t* gave_up, void* stream) {
+  if (!workspace) return fail(MR_ERR_INVALID_ARG, "null workspace");
+  const int* w = reinterpret_cast<const int*>(workspace) + (3 + kXcds) * (kMaxBounces + 2);
+  int v = 0;
+  MR_HIP(hipMemcpyAsync(&v, w, sizeof(int), hipMemcpyDeviceToHost, (hipStream_t)stream));
+  MR_HIP(hipStreamSynchronize((hipStream_t)stream));
+  if (gave_up) *gave_up = v;
+  if (v != 0)
+    return fail(MR_ERR_DEVICE, std::to_string(v) + " wave(s) of the packet march gave up a bounded wait: the "
+                                                    "radiance and throughput of their packets' rays are incomplete");
+  return MR_OK;
 }
 
 extern "C" mr_status mr_render_fields(const mr_field* const* fields, const mr_field* const* proposals,

@@ -28,8 +28,9 @@ EXPORTED = [
     "mr_graph_launch", "mr_last_error", "mr_mesh_build_bvh", "mr_mesh_closest_hit", "mr_mesh_destroy",
     "mr_mesh_info", "mr_mesh_refit", "mr_probe_gather", "mr_profile_enable", "mr_profile_read",
     "mr_proposal_grad", "mr_proposal_targets", "mr_proposal_train_step", "mr_rays_from_cameras", "mr_render",
-    "mr_render_fields", "mr_render_fields_workspace_size", "mr_render_graph_create", "mr_render_workspace_size",
-    "mr_version",
+    "mr_render_fields", "mr_render_fields_workspace_size", "mr_render_graph_create",
+    "mr_render_status",
+    "mr_render_workspace_size", "mr_version",
 ]
 
 
@@ -67,7 +68,7 @@ class RenderOpts(C.Structure):
                 ("march_blocks_per_cu", C.c_int32), ("stage_blocks_per_cu", C.c_int32),
                 ("stage_tile", C.c_int32), ("march_chunk", C.c_int32), ("march_batch", C.c_int32),
                 ("march_packets", C.c_int32), ("sample_shadows", C.c_int32), ("shadow_mask", C.c_float),
-                ("sample_emitters", C.c_int32)]
+                ("sample_emitters", C.c_int32), ("wait_polls", C.c_int32)]
 
 
 class LaunchCfg(C.Structure):
@@ -215,6 +216,14 @@ def mr_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, l
                            C.c_int32(max_bounces), _ptr(per_ray_max_bounces), arr, C.c_int32(nl),
                            C.byref(opts), C.byref(out), _ptr(workspace), C.c_size_t(workspace_bytes),
                            _stream(stream)))
+
+
+def mr_render_status(workspace, stream=None):
+    """Number of packet-march waves whose bounded wait gave up in the last
+    render on this workspace; raises MrError (MR_ERR_DEVICE) when not 0."""
+    g = C.c_int64()
+    _check(lib().mr_render_status(_ptr(workspace), C.byref(g), _stream(stream)))
+    return g.value
 
 
 def mr_render_fields_workspace_size(n, n_fields):
@@ -377,6 +386,10 @@ class Renderer:
                   self.max_bounces, per_ray_max_bounces, lights, opts, self.out, self.workspace,
                   self.ws_bytes, stream)
         return self
+
+    def status(self, stream=None):
+        """mr_render_status of the last render into this workspace."""
+        return mr_render_status(self.workspace, stream)
 
     def render_fields(self, fields, mesh, origins, dirs, lights, opts, per_ray_max_bounces=None, stream=None,
                       proposals=None):

@@ -89,5 +89,27 @@ def test_mesh_and_field_validation_before_any_upload():
     assert "non-finite" in str(e.value)
 
 
+@pytest.mark.parametrize("levels,sh,layers", [(8, 4, 2), (8, 16, 1), (16, 4, 2), (16, 16, 1)])
+def test_field_layouts_without_kernels_are_refused_before_upload(levels, sh, layers):
+    """Only layouts with march kernels are accepted: the others are refused
+    by mr_field_create before any device allocation (no GPU is needed to see
+    the refusal)."""
+    from paper_2309_04581_amd import scenegen as sg
+    fld = sg.tiny_field() if levels == 8 else sg.mid_field()
+    d = meshrf.FieldDesc()
+    res = np.array(fld.resolutions, np.int32)
+    d.n_levels, d.feats_per_level, d.log2_table_size = levels, 2, int(fld.log2_table)
+    d.host_resolutions = res.ctypes.data
+    d.density_in, d.density_hidden, d.density_out = 32, 64, 16
+    d.color_in, d.color_hidden, d.color_hidden_layers, d.sh_components = 32, 64, layers, sh
+    d.aabb_min = (C.c_float * 3)(-1, -1, -1)
+    d.aabb_max = (C.c_float * 3)(1, 1, 1)
+    n_mlp = 64 * 32 + 16 * 64 + 64 * 32 + (layers - 1) * 64 * 64 + 3 * 64
+    mlp = np.zeros(n_mlp, np.float32)
+    with pytest.raises(meshrf.MrError) as e:
+        meshrf.mr_field_create(d, fld.table, mlp, stream=_Null())
+    assert e.value.status == meshrf.MR_ERR_UNSUPPORTED and "layouts" in str(e.value)
+
+
 class _Null:
     cuda_stream = 0
