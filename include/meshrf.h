@@ -278,6 +278,27 @@ mr_status mr_render(const mr_field* field, const mr_mesh* mesh, int64_t n, const
  * are then incomplete), else MR_OK.  Synchronises with the host. */
 mr_status mr_render_status(const void* workspace, int64_t* gave_up, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, hosts that forbid hipMalloc): mr_render without a
+ * workspace.  The ray queues and counters live in a fixed device array of
+ * the library, MR_NOALLOC_MAX_RAYS * 128 + 4096 bytes (32 MiB + 4 KiB), that
+ * every device the library runs on holds until the process ends; the call
+ * allocates nothing (the array's address is looked up once per device, on
+ * its first call there).  Arguments, outputs, validation and results are
+ * those of mr_render, plus:
+ *   n <= MR_NOALLOC_MAX_RAYS, else MR_ERR_INVALID_ARG before any launch;
+ *   gave_up: optional device int32, set at the end of the render to the
+ *   number of packet-march waves whose bounded wait gave up (0 in a correct
+ *   run; what mr_render_status reports for mr_render).
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (two streams, two threads) race and give wrong results;
+ * serialise them.  Stage timing (mr_profile_enable) does not cover it. */
+#define MR_NOALLOC_MAX_RAYS 262144
+mr_status mr_render_noalloc(const mr_field* field, const mr_mesh* mesh, int64_t n, const float* origins,
+                            const float* dirs, int32_t max_bounces, const int32_t* per_ray_max_bounces,
+                            const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
+                            mr_render_out* out, int32_t* gave_up, void* stream);
+
 /* Several fields in one scene (NeRF objects placed by mr_field_set_pose
  * among the meshes; the paper's dynamic, mesh-aware scenes hold more than one
  * radiance field).  The medium is their sum: density sigma_1 + sigma_2 + ...

@@ -48,8 +48,8 @@ struct StageTimer {
   int stage;
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
-  StageTimer(int s, hipStream_t stream) : stage(s), st(stream) {
-    if (!g_prof.on) return;
+  StageTimer(int s, hipStream_t stream, bool allowed = true) : stage(s), st(stream) {
+    if (!allowed || !g_prof.on) return;
     a = g_prof.get();
     b = g_prof.get();
     if (a && b) (void)hipEventRecord(a, st);
@@ -816,7 +816,7 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
                       const float* origins, const float* dirs, int32_t max_bounces,
                       const int32_t* per_ray_max_bounces, const mr_light* host_lights, int32_t n_lights,
                       const mr_render_opts* opts, mr_render_out* out, void* workspace, size_t workspace_bytes,
-                      void* stream, bool joint = false) {
+                      void* stream, bool joint = false, bool timed = true) {
   mr_status s = MR_OK;
   const mr_field* field = n_fields == 1 ? fields[0] : nullptr;
   if (n == 0) return MR_OK;
@@ -909,19 +909,19 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
     RayQueue& qo = Q[(b + 1) & 1];
     if (b == 0) {
       // later segments are traced by the shade pass that spawns them
-      StageTimer tm(0, st);
+      StageTimer tm(0, st, timed);
       hipLaunchKernelGGL(k_trace, dim3(trace_blocks), dim3(kTraceBlock), 0, st, qi, counts + b, twork + b, tile, mv.bvh,
                          opts->t_far, P.span, out->hit_ids, out->hit_ids ? out->hit_stride : 0);
       MR_HIP(hipGetLastError());
     }
     if (n_fields > 1 && joint) {
       // one march over the summed medium
-      StageTimer tm(1, st);
+      StageTimer tm(1, st, timed);
       s = dispatch_march_fields(fields, n_fields, qi, counts + b, work + kXcds * b, P, mv.bvh, b < packet_segments,
                                 stats, opts->march_blocks_per_cu, n, st);
       if (s != MR_OK) return s;
     } else if (n_fields > 1) {
-      StageTimer tm(1, st);
+      StageTimer tm(1, st, timed);
       const int fblocks = (int)std::min<int64_t>((n + 255) / 256, 65535);
       hipLaunchKernelGGL(k_fields_prep, dim3(fblocks), dim3(256), 0, st, counts + b, fscratch, n_fields, cap, fctr,
                          n_fields * kXcds);
@@ -943,7 +943,7 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
       hipLaunchKernelGGL(k_fields_combine, dim3(fblocks), dim3(256), 0, st, qi, counts + b, fscratch, cap, FB);
       MR_HIP(hipGetLastError());
     } else if (field) {
-      StageTimer tm(1, st);
+      StageTimer tm(1, st, timed);
       if (opts->sampler == MR_SAMPLER_PROPOSAL)
         s = dispatch_march_proposal(field, opts->proposal, qi, counts + b, work + kXcds * b, P, mv.bvh, opts->n_proposal,
                                     opts->n_fine, b < packet_segments, stats, opts->march_blocks_per_cu, n, st);
@@ -953,7 +953,7 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
       if (s != MR_OK) return s;
     }
     {
-      StageTimer tm(2, st);
+      StageTimer tm(2, st, timed);
       hipLaunchKernelGGL(k_shade, dim3(shade_blocks), dim3(kTraceBlock), 0, st, qi, counts + b, swork + b, tile, qo,
                          counts + b + 1, mv, S, ro, P.span, out->hit_ids, out->hit_ids ? out->hit_stride : 0, stats);
       MR_HIP(hipGetLastError());
@@ -961,7 +961,7 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
     if (b < max_bounces) {
       // closest hits of the next segment when this queue is short (the kernel
       // returns at once otherwise)
-      StageTimer tm(0, st);
+      StageTimer tm(0, st, timed);
       hipLaunchKernelGGL(k_trace_wide, dim3(wide_blocks), dim3(64 * kWideWaves), 0, st, qo, counts + b, counts + b + 1,
                          twork + b + 1, mv.bvh, P.span, out->hit_ids, out->hit_ids ? out->hit_stride : 0);
       MR_HIP(hipGetLastError());
@@ -992,6 +992,72 @@ extern "C" mr_status mr_render_status(const void* workspace, int64_t* gave_up, v
   if (v != 0)
     return fail(MR_ERR_DEVICE, std::to_string(v) + " wave(s) of the packet march gave up a bounded wait: the "
                                                     "radiance and throughput of their packets' rays are incomplete");
+  return MR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// render without allocation: the ray queues and counters live in a fixed
+// array of the library's code object, one per device, instead of a caller
+// workspace
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kNoAllocMaxRays = MR_NOALLOC_MAX_RAYS;
+constexpr size_t kScratchBytes = kHeaderBytes + 2 * (size_t)kQueueArrays * 4 * (size_t)kNoAllocMaxRays;
+static_assert(kNoAllocMaxRays % 64 == 0, "queue capacity is a multiple of 64");
+
+// Host code must not pass this name to a kernel or a copy: it stands for the
+// device array only in device code.  scratch_on_device() gives its address.
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's copy of scratch, looked up once per device.
+mr_status scratch_on_device(void** ptr) {
+  int dev = 0;
+  MR_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(MR_ERR_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(MR_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return MR_OK;
+}
+
+__global__ void k_copy_gave_up(const int* src, int32_t* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
+}  // namespace
+
+extern "C" mr_status mr_render_noalloc(const mr_field* field, const mr_mesh* mesh, int64_t n, const float* origins,
+                                       const float* dirs, int32_t max_bounces, const int32_t* per_ray_max_bounces,
+                                       const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
+                                       mr_render_out* out, int32_t* gave_up, void* stream) {
+  if (n > kNoAllocMaxRays)
+    return fail(MR_ERR_INVALID_ARG, "n = " + std::to_string(n) + " exceeds the " + std::to_string(kNoAllocMaxRays) +
+                                        " rays mr_render_noalloc holds; use mr_render with a workspace");
+  mr_status s = validate_render(field, mesh, n, origins, dirs, max_bounces, host_lights, n_lights, opts, out);
+  if (s != MR_OK) return s;
+  if (n == 0) return MR_OK;
+  void* ws = nullptr;
+  s = scratch_on_device(&ws);
+  if (s != MR_OK) return s;
+  s = render_impl(&field, nullptr, field ? 1 : 0, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces,
+                  host_lights, n_lights, opts, out, ws, kScratchBytes, stream, false, /*timed=*/false);
+  if (s != MR_OK) return s;
+  if (gave_up) {
+    const int* src = reinterpret_cast<const int*>(ws) + (3 + kXcds) * (kMaxBounces + 2);
+    hipLaunchKernelGGL(k_copy_gave_up, dim3(1), dim3(64), 0, (hipStream_t)stream, src, gave_up);
+    MR_HIP(hipGetLastError());
+  }
   return MR_OK;
 }
 

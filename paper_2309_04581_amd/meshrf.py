@@ -29,7 +29,7 @@ EXPORTED = [
     "mr_mesh_info", "mr_mesh_refit", "mr_probe_gather", "mr_profile_enable", "mr_profile_read",
     "mr_proposal_grad", "mr_proposal_targets", "mr_proposal_train_step", "mr_rays_from_cameras", "mr_render",
     "mr_render_fields", "mr_render_fields_workspace_size", "mr_render_graph_create",
-    "mr_render_status",
+    "mr_render_noalloc", "mr_render_status",
     "mr_render_workspace_size", "mr_version",
 ]
 
@@ -218,6 +218,19 @@ def mr_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, l
                            _stream(stream)))
 
 
+MR_NOALLOC_MAX_RAYS = 262144
+
+
+def mr_render_noalloc(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, lights, opts, out,
+                      gave_up=None, stream=None):
+    """mr_render without a workspace (the library's fixed per-device array);
+    gave_up: optional device int32 tensor of one element."""
+    arr, nl = _lights_arr(lights)
+    _check(lib().mr_render_noalloc(field, mesh, C.c_int64(n), _ptr(origins), _ptr(dirs),
+                                   C.c_int32(max_bounces), _ptr(per_ray_max_bounces), arr, C.c_int32(nl),
+                                   C.byref(opts), C.byref(out), _ptr(gave_up), _stream(stream)))
+
+
 def mr_render_status(workspace, stream=None):
     """Number of packet-march waves whose bounded wait gave up in the last
     render on this workspace; raises MrError (MR_ERR_DEVICE) when not 0."""
@@ -385,6 +398,15 @@ class Renderer:
                   mesh.handle if mesh is not None else None, self.n, origins, dirs,
                   self.max_bounces, per_ray_max_bounces, lights, opts, self.out, self.workspace,
                   self.ws_bytes, stream)
+        return self
+
+    def render_noalloc(self, field, mesh, origins, dirs, lights, opts, per_ray_max_bounces=None, gave_up=None,
+                       stream=None):
+        """The same render through mr_render_noalloc (the library's own array
+        instead of this object's workspace)."""
+        mr_render_noalloc(field.handle if field is not None else None,
+                          mesh.handle if mesh is not None else None, self.n, origins, dirs,
+                          self.max_bounces, per_ray_max_bounces, lights, opts, self.out, gave_up, stream)
         return self
 
     def status(self, stream=None):

@@ -89,6 +89,24 @@ def test_mesh_and_field_validation_before_any_upload():
     assert "non-finite" in str(e.value)
 
 
+def test_noalloc_render_refuses_more_rays_than_its_array_holds():
+    """mr_render_noalloc checks n against its fixed array before anything else
+    (no device call, so no GPU is needed to see it); n = 0 returns at once."""
+    opts = meshrf.RenderOpts()
+    opts.t_near, opts.t_far, opts.n_samples = 0.05, 4.0, 64
+    out = meshrf.RenderOut()
+    with pytest.raises(meshrf.MrError) as e:
+        meshrf.mr_render_noalloc(None, None, meshrf.MR_NOALLOC_MAX_RAYS + 1, None, None, 4, None, [], opts, out,
+                                 stream=_Null())
+    assert e.value.status == meshrf.MR_ERR_INVALID_ARG and "262144" in str(e.value)
+    with pytest.raises(meshrf.MrError) as e:
+        meshrf.mr_render_noalloc(None, None, 4, None, None, 4, None, [], opts, out, stream=_Null())
+    assert e.value.status == meshrf.MR_ERR_INVALID_ARG and "null rays" in str(e.value)
+    meshrf.mr_render_noalloc(None, None, 0, None, None, 4, None, [], opts, out, stream=_Null())
+    hdr = open(HEADER).read()
+    assert f"#define MR_NOALLOC_MAX_RAYS {meshrf.MR_NOALLOC_MAX_RAYS}" in hdr
+
+
 @pytest.mark.parametrize("levels,sh,layers", [(8, 4, 2), (8, 16, 1), (16, 4, 2), (16, 16, 1)])
 def test_field_layouts_without_kernels_are_refused_before_upload(levels, sh, layers):
     """Only layouts with march kernels are accepted: the others are refused
