@@ -344,12 +344,67 @@ int orc_closest_hit(const orc_mesh* m, const double o[3], const double d[3], dou
   return best;
 }
 
+/* Record of a ray's decisions that single precision could take the other way
+ * (ties).  flag: the ray met one.  Scalar decisions (occupancy of a sample,
+ * visibility of a shadow ray, Fresnel choice, roulette, throughput cut-off,
+ * emitter choice) are counted in the order the path meets them; bit k of
+ * flip takes the other branch of the k-th, so that the outcomes a tie ray
+ * can have in single precision are reachable one by one. */
+typedef struct {
+  int flag;
+  int n;
+  uint32_t flip;
+} tie_t;
+
+/* One flagged scalar decision: returns 1 when its other branch is taken. */
+static int tie_decide(tie_t* t) {
+  t->flag = 1;
+  int k = t->n++;
+  return k < 32 && ((t->flip >> k) & 1u);
+}
+
+/* Whether triangle h is an outcome single precision can reach for the
+ * closest hit of (o, d) on (0, t_max] (h = -1: no hit).  Single precision may
+ * miss a hit that lies within tie_eps of an edge or of either end of the t
+ * range, may hit a near miss, and may order hits within tie_eps in t either
+ * way; so the reachable outcomes are every hit or near miss up to the first
+ * hit that is certain (inside by at least tie_eps, and within the range by
+ * at least tie_eps relative), within tie_eps of it, and no hit when no
+ * certain hit exists.  For a reachable h, *t_h and bary_h are its FP64
+ * distance and barycentrics. */
+static int hit_reachable(const orc_mesh* m, const double o[3], const double d[3], double t_max,
+                         double tie_eps, int h, double* t_h, double bary_h[3]) {
+  if (!m) return h < 0;
+  shear_t s = make_shear(d);
+  double t_cert = INFINITY, th = INFINITY;
+  int h_ok = 0;
+  for (int i = 0; i < m->nf; ++i) {
+    double v[3][3], uvw[3], t;
+    tri_verts(m, i, v);
+    double det = tri_edges(&s, o, v[0], v[1], v[2], uvw, &t);
+    if (det == 0.0) continue;
+    int inside = !((uvw[0] < 0 || uvw[1] < 0 || uvw[2] < 0) && (uvw[0] > 0 || uvw[1] > 0 || uvw[2] > 0));
+    double tol_t = tie_eps * fmax(1.0, fabs(t));
+    double mg = edge_margin(v, d, uvw, det);
+    if (inside && mg >= tie_eps && t > tol_t && t <= t_max - tol_t && t < t_cert) t_cert = t;
+    if (i == h && t > -tol_t && t <= t_max + tol_t && (inside || fabs(mg) < tie_eps)) {
+      h_ok = 1;
+      th = t;
+      for (int k = 0; k < 3; ++k) bary_h[k] = uvw[k] / det;
+    }
+  }
+  if (h < 0) return t_cert == INFINITY;
+  if (!h_ok || th > t_cert + tie_eps * fmax(1.0, t_cert)) return 0;
+  *t_h = th;
+  return 1;
+}
+
 /* Any hit with 0 < t < t_max (shadow rays, Sec. 3.1 "Shadow rays"). */
 static int any_hit(const orc_mesh* m, const double o[3], const double d[3], double t_max,
-                   double tie_eps, int* tie) {
+                   double tie_eps, tie_t* tie) {
   if (!m) return 0;
   shear_t s = make_shear(d);
-  int hit = 0;
+  int hit = 0, near = 0;
   for (int i = 0; i < m->nf; ++i) {
     double v[3][3], uvw[3], t;
     tri_verts(m, i, v);
@@ -360,10 +415,11 @@ static int any_hit(const orc_mesh* m, const double o[3], const double d[3], doub
     if (inside && t > 0.0 && t < t_max) hit = 1;
     if (t > -tol_t && t < t_max + tol_t) {
       double mg = edge_margin(v, d, uvw, det);
-      if (fabs(mg) < tie_eps) *tie = 1;
-      else if (inside && (t < tol_t || t_max - t < tol_t)) *tie = 1;
+      if (fabs(mg) < tie_eps) near = 1;
+      else if (inside && (t < tol_t || t_max - t < tol_t)) near = 1;
     }
   }
+  if (near && tie && tie_decide(tie)) hit = !hit;
   return hit;
 }
 
@@ -452,7 +508,7 @@ static int occ_cell(const orc_opts* opt, const int c[3]) {
   return opt->occ[((int64_t)c[2] * R + c[1]) * R + c[0]] != 0;
 }
 
-static int occupied(const orc_opts* opt, const orc_field* f, const double x[3], int* tie) {
+static int occupied(const orc_opts* opt, const orc_field* f, const double x[3], tie_t* tie) {
   if (!opt->occ) return 1;
   int R = opt->occ_res;
   int c[3];
@@ -463,7 +519,7 @@ static int occupied(const orc_opts* opt, const orc_field* f, const double x[3], 
     int ci = (int)floor(xr[k]);
     c[k] = ci < 0 ? 0 : (ci >= R ? R - 1 : ci);
   }
-  int here = occ_cell(opt, c);
+  int here = occ_cell(opt, c), near = 0;
   for (int k = 0; k < 3; ++k) {
     double face = floor(xr[k] + 0.5);
     if (fabs(xr[k] - face) < opt->tie_eps * R) {
@@ -471,9 +527,10 @@ static int occupied(const orc_opts* opt, const orc_field* f, const double x[3], 
       nb[k] = (face > xr[k] || face == (double)c[k] + 1.0) ? c[k] + 1 : c[k] - 1;
       if (nb[k] == c[k]) continue;
       int there = occ_cell(opt, nb);
-      if (there >= 0 && there != here) *tie = 1;
+      if (there >= 0 && there != here) near = 1;
     }
   }
+  if (near && tie_decide(tie)) here = !here;
   return here;
 }
 
@@ -490,7 +547,7 @@ typedef struct {
 
 /* Shadow mask m(p_t) of one sample: 1, times the mask value for every light
  * that a mesh hides from the sample's world position. */
-static double sample_mask(const shadow_ctx* sh, const orc_opts* opt, double tm, int* tie) {
+static double sample_mask(const shadow_ctx* sh, const orc_opts* opt, double tm, tie_t* tie) {
   double m = 1.0, x[3];
   for (int k = 0; k < 3; ++k) x[k] = sh->o_world[k] + tm * sh->d_world[k];
   for (int li = 0; li < sh->n_lights; ++li) {
@@ -508,7 +565,7 @@ static double sample_mask(const shadow_ctx* sh, const orc_opts* opt, double tm, 
  * T *= (1 - alpha).  Returns the number of field samples. */
 static int composite_interval(const orc_field* f, const orc_opts* opt, const double o[3],
                               const double d[3], double a, double b, double T[3], double L[3],
-                              int* tie, const shadow_ctx* sh) {
+                              tie_t* tie, const shadow_ctx* sh) {
   if (!(b > a)) return 0;
   double tm = 0.5 * (a + b), D = b - a, x[3], sigma, rgb[3];
   for (int k = 0; k < 3; ++k) x[k] = o[k] + tm * d[k];
@@ -573,7 +630,7 @@ void orc_proposal_edges(const double* w, int32_t np, int32_t nf, double lo, doub
  * n_fine intervals between the edges of orc_proposal_edges. */
 static int64_t march(const orc_field* f, const orc_opts* opt, const double o_world[3],
                      const double d_world[3], double t_a, double t_hit, double T[3], double L[3],
-                     int* tie, const shadow_ctx* sh_in) {
+                     tie_t* tie, const shadow_ctx* sh_in) {
   if (!f) return 0;
   shadow_ctx shc;
   const shadow_ctx* sh = NULL;
@@ -620,7 +677,7 @@ static int64_t march(const orc_field* f, const orc_opts* opt, const double o_wor
  * A piece inside no box, or whose fields are all empty there by their
  * occupancy grids, leaves L and T unchanged. */
 static int64_t march_fields(const orc_opts* opt, const double o_world[3], const double d_world[3],
-                            double t_a, double t_hit, double T[3], double L[3], int* tie,
+                            double t_a, double t_hit, double T[3], double L[3], tie_t* tie,
                             const shadow_ctx* sh_in) {
   enum { MAXF = 16 };
   int nf = opt->n_fields;
@@ -698,7 +755,7 @@ static int64_t march_fields(const orc_opts* opt, const double o_world[3], const 
  * marched on its own clipped range with its own proposal (the single-field
  * proposal march) in the order the ray enters the boxes. */
 static int64_t march_fields_proposal(const orc_opts* opt, const double o_world[3], const double d_world[3],
-                                     double t_a, double t_hit, double T[3], double L[3], int* tie,
+                                     double t_a, double t_hit, double T[3], double L[3], tie_t* tie,
                                      const shadow_ctx* sh_in) {
   enum { MAXF = 16 };
   int nf = opt->n_fields < MAXF ? opt->n_fields : MAXF;
@@ -821,7 +878,7 @@ static int near_rel(double a, double b, double eps) {
  * (1 - 1e-3) of the way.  As for the point lights, the shadow ray sees meshes
  * only.  Returns the tie flag of the choice and the shadow ray in *tie. */
 static void emitter_sample(const orc_mesh* m, const double p[3], const double nf[3], const float* mat,
-                           const double u[4], double tie_eps, double tie_rel, double L_add[3], int* tie) {
+                           const double u[4], double tie_eps, double tie_rel, double L_add[3], tie_t* tie) {
   for (int c = 0; c < 3; ++c) L_add[c] = 0.0;
   double W = 0.0;
   for (int i = 0; i < m->nf; ++i) {
@@ -830,18 +887,29 @@ static void emitter_sample(const orc_mesh* m, const double p[3], const double nf
   }
   if (!(W > 0.0)) return;
   double target = u[0] * W, cum = 0.0;
-  int k = -1;
-  double wk = 0.0;
+  int k = -1, prev = -1, alt = -1, want_next = 0;
+  double wk = 0.0, wprev = 0.0, walt = 0.0;
   for (int i = 0; i < m->nf; ++i) {
     const float* em = m->materials + 8 * m->mat_ids[i] + 5;
     double w = (double)em[0] + (double)em[1] + (double)em[2];
     if (!(w > 0.0)) continue;
-    if (near_rel(target, cum, tie_rel) && cum > 0.0) *tie = 1;
+    double lo = cum;
     cum += w;
-    if (k < 0 && target < cum) { k = i; wk = w; }
-    if (near_rel(target, cum, tie_rel) && cum < W) *tie = 1;
+    if (k < 0 && target < cum) {
+      k = i;
+      wk = w;
+      /* near a boundary of its share: the neighbour across it is the other outcome */
+      if (lo > 0.0 && near_rel(target, lo, tie_rel)) { alt = prev; walt = wprev; }
+      else if (cum < W && near_rel(target, cum, tie_rel)) want_next = 1;
+    } else if (want_next && alt < 0) {
+      alt = i;
+      walt = w;
+    }
+    prev = i;
+    wprev = w;
   }
   if (k < 0) return;                     /* u0 < 1 always finds one; kept for safety */
+  if (alt >= 0 && tie_decide(tie)) { k = alt; wk = walt; }
   double v[3][3], e1[3], e2[3], nk[3], x[3], wi[3], l[3];
   tri_verts(m, k, v);
   double s = sqrt(u[1]);
@@ -887,7 +955,8 @@ static void render_ray(const job_t* J, int64_t r) {
   int64_t rid = J->ray_ids ? J->ray_ids[r] : r;
   double o[3], d[3], T[3] = {1, 1, 1}, L[3] = {0, 0, 0};
   for (int k = 0; k < 3; ++k) { o[k] = J->origins[3 * r + k]; d[k] = J->dirs[3 * r + k]; }
-  int nscat = 0, tie = 0, segs = 0, after_diffuse = 0;
+  int nscat = 0, segs = 0, after_diffuse = 0, invalid = 0;
+  tie_t tie = {0, 0, opt->flip ? opt->flip[r] : 0u};
   int64_t nsamp = 0;
   int stride = opt->max_bounces + 1;
   if (J->out->hit_ids)
@@ -899,7 +968,21 @@ static void render_ray(const job_t* J, int64_t r) {
     double t_hit = INFINITY, bary[3];
     int t_tie = 0;
     int hit = m ? orc_closest_hit(m, o, d, t_max, opt->tie_eps, &t_hit, bary, &t_tie) : -1;
-    tie |= t_tie;
+    tie.flag |= t_tie;
+    if (opt->force_hits && opt->force_hits[r * stride + s] != hit) {
+      /* an outcome single precision reached instead: taken if reachable */
+      int h = opt->force_hits[r * stride + s];
+      double th = 0.0, bh[3];
+      if (h >= -1 && h < (m ? m->nf : 0) && hit_reachable(m, o, d, t_max, opt->tie_eps, h, &th, bh)) {
+        hit = h;
+        if (h >= 0) {
+          t_hit = th;
+          for (int k = 0; k < 3; ++k) bary[k] = bh[k];
+        }
+      } else {
+        invalid = 1;
+      }
+    }
     if (J->out->hit_ids) J->out->hit_ids[r * stride + s] = hit;
     shadow_ctx sh = {m, J->lights, J->n_lights, opt->shadow_mask, NULL, NULL};
     if (opt->n_fields > 0 && opt->field_proposals)
@@ -943,9 +1026,7 @@ static void render_ray(const job_t* J, int64_t r) {
         sub3(lp, so, sd);
         double sdist = sqrt(dot3(sd, sd));
         for (int k = 0; k < 3; ++k) sd[k] /= sdist;
-        int stie = 0;
-        int blocked = any_hit(m, so, sd, sdist, opt->tie_eps, &stie);
-        tie |= stie;
+        int blocked = any_hit(m, so, sd, sdist, opt->tie_eps, &tie);
         if (blocked) continue;
         for (int c = 0; c < 3; ++c) L[c] += T[c] * ((double)mat[2 + c] / PI) * lt[3 + c] * cosl / d2;
       }
@@ -961,20 +1042,25 @@ static void render_ray(const job_t* J, int64_t r) {
     draw(opt->seed, rid, s, kind == 1 ? RNG_GLASS : RNG_DIFFUSE, u);
     double wgt[3], R = -1.0;
     orc_scatter(mat, d, n, u, nd, side, wgt, &R);
-    if (kind == 1 && R < 1.0 && near_rel(u[0], R, opt->tie_rel)) tie = 1;
+    if (kind == 1 && R < 1.0 && near_rel(u[0], R, opt->tie_rel) && tie_decide(&tie)) {
+      u[0] = u[0] < R ? 1.0 : 0.0;       /* the other branch of the Fresnel choice */
+      orc_scatter(mat, d, n, u, nd, side, wgt, &R);
+    }
     for (int c = 0; c < 3; ++c) T[c] *= wgt[c];
     ++nscat;
     if (opt->rr_after >= 0 && nscat >= opt->rr_after) {   /* Russian roulette */
       double q = fmin(1.0, fmax(T[0], fmax(T[1], T[2])));
       double u[4];
       draw(opt->seed, rid, s, RNG_RR, u);
-      if (q < 1.0 && near_rel(u[0], q, opt->tie_rel)) tie = 1;
-      if (!(u[0] < q)) { T[0] = T[1] = T[2] = 0.0; break; }
+      int survive = u[0] < q;
+      if (q < 1.0 && near_rel(u[0], q, opt->tie_rel) && tie_decide(&tie)) survive = !survive;
+      if (!survive) { T[0] = T[1] = T[2] = 0.0; break; }
       for (int c = 0; c < 3; ++c) T[c] /= q;
     }
     double tmax = fmax(T[0], fmax(T[1], T[2]));
-    if (near_rel(tmax, opt->t_min_throughput, opt->tie_rel)) tie = 1;
-    if (tmax < opt->t_min_throughput) break;
+    int cut = tmax < opt->t_min_throughput;
+    if (near_rel(tmax, opt->t_min_throughput, opt->tie_rel) && tie_decide(&tie)) cut = !cut;
+    if (cut) break;
     for (int k = 0; k < 3; ++k) { o[k] = p[k] + 1e-4 * side[k]; d[k] = nd[k]; }
   }
   for (int c = 0; c < 3; ++c) {
@@ -982,7 +1068,9 @@ static void render_ray(const job_t* J, int64_t r) {
     J->out->throughput[3 * r + c] = T[c];
   }
   J->out->bounces[r] = nscat;
-  if (J->out->tie) J->out->tie[r] = (uint8_t)tie;
+  if (J->out->tie) J->out->tie[r] = (uint8_t)tie.flag;
+  if (J->out->invalid) J->out->invalid[r] = (uint8_t)invalid;
+  if (J->out->n_flagged) J->out->n_flagged[r] = tie.n;
   if (J->out->samples) J->out->samples[r] = nsamp;
   if (J->out->segments) J->out->segments[r] = segs;
 }

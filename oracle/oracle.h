@@ -82,6 +82,15 @@ typedef struct {
    * boxes must not overlap; each field is marched on its own range in the
    * order the ray enters the boxes) */
   const orc_field* const* field_proposals;
+  /* optional, to check the outcomes of tie rays: force_hits [n][max_bounces+1]
+   * names per segment the triangle (-1 none) to take instead of the closest
+   * hit, taken when single precision can reach it (a hit or near miss no
+   * farther than the first certain hit, or no hit when none is certain), else
+   * the ray is marked invalid; flip [n]: bit k takes the other branch of the
+   * ray's k-th flagged scalar decision (occupancy, shadow visibility, Fresnel,
+   * roulette, cut-off, emitter choice, in path order) */
+  const int32_t* force_hits;
+  const uint32_t* flip;
 } orc_opts;
 
 typedef struct {
@@ -92,6 +101,8 @@ typedef struct {
   uint8_t* tie;              /* [n] */
   int64_t* samples;          /* [n] field evaluations per ray (optional) */
   int32_t* segments;         /* [n] marched segments per ray (optional) */
+  uint8_t* invalid;          /* [n] a forced hit was not reachable (optional) */
+  int32_t* n_flagged;        /* [n] flagged scalar decisions met on the path (optional) */
 } orc_out;
 
 /* ---- building blocks, exposed for the pin tests ---- */

@@ -54,13 +54,13 @@ class _Opts(C.Structure):
                 ("sample_shadows", C.c_int32), ("shadow_mask", C.c_double),
                 ("sample_emitters", C.c_int32), ("n_fields", C.c_int32), ("fields", C.c_void_p),
                 ("field_occ", C.c_void_p), ("field_occ_res", C.c_void_p),
-                ("field_proposals", C.c_void_p)]
+                ("field_proposals", C.c_void_p), ("force_hits", C.c_void_p), ("flip", C.c_void_p)]
 
 
 class _Out(C.Structure):
     _fields_ = [("radiance", C.c_void_p), ("throughput", C.c_void_p), ("bounces", C.c_void_p),
                 ("hit_ids", C.c_void_p), ("tie", C.c_void_p), ("samples", C.c_void_p),
-                ("segments", C.c_void_p)]
+                ("segments", C.c_void_p), ("invalid", C.c_void_p), ("n_flagged", C.c_void_p)]
 
 
 _lib = None
@@ -217,7 +217,7 @@ def occupancy(field, res, thresh, n_threads=None):
 def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
            tie_eps=1e-5, tie_rel=1e-4, occupancy_bits=None, proposal=None, n_prop=32,
            n_fine=32, field=..., mesh=..., shadow_mask=None, sample_emitters=False, fields=None,
-           field_occupancy=None, field_proposals=None):
+           field_occupancy=None, field_proposals=None, force_hits=None, flip=None, _gmax=None):
     """Render FP32 input rays through the whole path in FP64.
 
     shadow_mask: None = no per-sample shadows; else every field sample that a
@@ -230,9 +230,21 @@ def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
     field_proposals: per field its proposal (the proposal sampler with
     several fields, boxes disjoint; n_prop and n_fine apply to each).
 
+    force_hits, flip: outcomes of tie rays (see orc_opts): per ray and
+    segment a triangle to take instead of the closest hit when single
+    precision can reach it, and per ray a bit mask over its flagged scalar
+    decisions whose other branch to take.
+
     Returns a dict with radiance, throughput, bounces, hit_ids (segments),
-    tie flags, per-ray sample and segment counts.
+    tie flags, per-ray sample and segment counts, invalid (a forced hit was
+    not reachable) and n_flagged (flagged scalar decisions on the path), and
+    rerun(idx, force_hits, flip): the same render of the rays idx with those
+    options.
     """
+    call = dict(tie_eps=tie_eps, tie_rel=tie_rel, occupancy_bits=occupancy_bits, proposal=proposal,
+                n_prop=n_prop, n_fine=n_fine, field=field, mesh=mesh, shadow_mask=shadow_mask,
+                sample_emitters=sample_emitters, fields=fields, field_occupancy=field_occupancy,
+                field_proposals=field_proposals, n_threads=n_threads)
     field = scene.field if field is ... else field
     mesh = scene.mesh if mesh is ... else mesh
     origins = np.ascontiguousarray(origins, dtype=np.float32)
@@ -245,6 +257,8 @@ def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
     ids = None if ray_ids is None else np.ascontiguousarray(ray_ids, dtype=np.int64)
     mbs = None if max_bounces is None else np.ascontiguousarray(max_bounces, dtype=np.int32)
     gmax = int(scene.max_bounces if mbs is None else max(scene.max_bounces, int(mbs.max(initial=0))))
+    if _gmax is not None:
+        gmax = int(_gmax)
     opt = _Opts()
     opt.t_near, opt.t_far = float(scene.t_near), float(scene.t_far)
     opt.n_samples, opt.max_bounces = int(scene.n_samples), gmax
@@ -292,18 +306,38 @@ def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
             opt.n_prop, opt.n_fine = int(n_prop), int(n_fine)
         if of is None and ofs:
             of = ofs[0]
+    if force_hits is not None:
+        force_hits = np.ascontiguousarray(force_hits, dtype=np.int32)
+        if force_hits.shape != (n, gmax + 1):
+            raise ValueError(f"force_hits must be ({n}, {gmax + 1})")
+        opt.force_hits = _p(force_hits)
+    if flip is not None:
+        flip = np.ascontiguousarray(flip, dtype=np.uint32)
+        opt.flip = _p(flip)
     res = dict(radiance=np.zeros((n, 3)), throughput=np.zeros((n, 3)),
                bounces=np.zeros(n, dtype=np.int32),
                hit_ids=np.full((n, gmax + 1), -1, dtype=np.int32),
                tie=np.zeros(n, dtype=np.uint8), samples=np.zeros(n, dtype=np.int64),
-               segments=np.zeros(n, dtype=np.int32))
+               segments=np.zeros(n, dtype=np.int32), invalid=np.zeros(n, dtype=np.uint8),
+               n_flagged=np.zeros(n, dtype=np.int32))
     out = _Out()
-    for k in ("radiance", "throughput", "bounces", "hit_ids", "tie", "samples", "segments"):
+    for k in ("radiance", "throughput", "bounces", "hit_ids", "tie", "samples", "segments", "invalid",
+              "n_flagged"):
         setattr(out, k, _p(res[k]))
     lib().orc_render(of.ptr if of else None, om.ptr if om else None, C.c_int64(n), _p(origins),
                      _p(dirs), _p(ids), _p(mbs), _p(lights), C.c_int32(len(lights)),
                      C.byref(opt), C.byref(out), C.c_int32(n_threads or n_threads_default()))
     res["tie"] = res["tie"].astype(bool)
+    res["invalid"] = res["invalid"].astype(bool)
+
+    def rerun(idx, force_hits=None, flip=None):
+        idx = np.asarray(idx, dtype=np.int64)
+        rid = idx if ids is None else ids[idx]
+        return render(scene, origins[idx], dirs[idx], ray_ids=rid,
+                      max_bounces=None if mbs is None else mbs[idx], force_hits=force_hits, flip=flip,
+                      _gmax=gmax, **call)
+
+    res["rerun"] = rerun
     return res
 
 

@@ -73,8 +73,8 @@ def test_multicamera_batch_matches_oracle_on_sampled_rays():
     assert bounces[inside].max() >= 8 and bounces[~inside].max() <= 1
     assert np.all(bounces <= limits[cih])
     rng = np.random.default_rng(401)
-    idx = np.sort(np.concatenate([rng.choice(np.flatnonzero(~inside), 150, replace=False),
-                                  rng.choice(np.flatnonzero(inside), 150, replace=False)]))
+    idx = np.sort(np.concatenate([rng.choice(np.flatnonzero(~inside), 2000, replace=False),
+                                  rng.choice(np.flatnonzero(inside), 2000, replace=False)]))
     r = orc.render(sc, host(o)[idx], host(d)[idx], ray_ids=idx, max_bounces=limits[cih[idx]])
     g = dict(radiance=host(R.radiance)[idx], throughput=host(R.throughput)[idx], bounces=bounces[idx],
              hit_ids=host(R.hit_ids)[idx])

@@ -307,6 +307,71 @@ def test_shared_edge_is_watertight_and_flagged():
     assert hid in (0, 1) and t == pytest.approx(1.75) and tie
 
 
+def test_forced_hit_across_a_shared_edge_is_reachable_and_others_are_not():
+    """Outcomes of a tie ray: a ray through the z- face diagonal of the mirror
+    cube may hit either triangle of the face in single precision (both reflect
+    the same way, so radiance is unchanged); a face the ray never meets, and
+    no hit at all (the far face is a certain hit behind), are not reachable."""
+    f = _constant_field()
+    sc = _scene(f, sg.mirror_cube_mesh())
+    d = np.array([0.0, 0.05, 1.0])
+    d /= np.linalg.norm(d)
+    o = np.array([0.1, 0.1 - 0.05 * 1.75, -2.0])     # meets z = -0.25 at x = y = 0.1
+    o32, d32 = o[None].astype(np.float32), d[None].astype(np.float32)
+    r = orc.render(sc, o32, d32)
+    assert r["tie"][0] and r["hit_ids"][0, 0] in (0, 1)
+    other = 1 - r["hit_ids"][0, 0]
+    fh = r["hit_ids"].copy()
+    fh[0, 0] = other
+    a = r["rerun"]([0], force_hits=fh)
+    assert not a["invalid"][0] and a["hit_ids"][0, 0] == other
+    np.testing.assert_allclose(a["radiance"][0], r["radiance"][0], rtol=1e-12)
+    np.testing.assert_allclose(a["throughput"][0], r["throughput"][0], rtol=1e-12)
+    for bad in (10, -1):                 # x+ face; no hit although the z+ face is certain
+        fb = r["hit_ids"].copy()
+        fb[0, 0] = bad
+        assert r["rerun"]([0], force_hits=fb)["invalid"][0], bad
+    # forcing what the oracle chose anyway changes nothing
+    same = r["rerun"]([0], force_hits=r["hit_ids"])
+    assert not same["invalid"][0]
+    np.testing.assert_array_equal(same["radiance"], r["radiance"])
+
+
+def test_forced_hit_on_a_clear_ray_is_not_reachable():
+    """Away from every edge there is one outcome: forcing the other triangle
+    of the face, or no hit, marks the ray invalid."""
+    sc = _scene(_constant_field(), sg.mirror_cube_mesh())
+    o = np.array([[0.1, -0.12, -2.0]], np.float32)
+    d = np.array([[0.0, 0.0, 1.0]], np.float32)
+    r = orc.render(sc, o, d)
+    assert not r["tie"][0] and r["hit_ids"][0, 0] in (0, 1)
+    for bad in (1 - r["hit_ids"][0, 0], -1):
+        fb = r["hit_ids"].copy()
+        fb[0, 0] = bad
+        assert r["rerun"]([0], force_hits=fb)["invalid"][0]
+
+
+def test_flipping_a_flagged_decision_takes_its_other_branch():
+    """A cut-off equal to the throughput after one diffuse bounce (albedo 0.7
+    stored in FP32, just below 0.7) is a flagged decision: as it stands the
+    path stops after the floor (one segment); with its bit set the path goes
+    on and escapes (two segments).  Bits beyond the flagged decisions change
+    nothing."""
+    plane_v, plane_f = sg.floor_plane(-0.6)
+    mesh = sg.merge_meshes([(plane_v, plane_f, 0)], [[sg.DIFFUSE, 1.0, 0.7, 0.7, 0.7]])
+    sc = _scene(None, mesh, t_min_throughput=0.7)
+    o = np.array([[0.0, 0.5, -2.0]], np.float32)
+    tgt = np.array([0.1, -0.6, 0.2])
+    d = ((tgt - o[0]) / np.linalg.norm(tgt - o[0]))[None].astype(np.float32)
+    r = orc.render(sc, o, d)
+    assert r["tie"][0] and r["n_flagged"][0] == 1 and r["segments"][0] == 1 and r["bounces"][0] == 1
+    f1 = r["rerun"]([0], flip=np.array([1], np.uint32))
+    assert f1["segments"][0] == 2 and f1["bounces"][0] == 1 and not f1["invalid"][0]
+    np.testing.assert_array_equal(f1["throughput"], r["throughput"])
+    f2 = r["rerun"]([0], flip=np.array([2], np.uint32))
+    assert f2["segments"][0] == 1
+
+
 # ---------------------------------------------------------------------------
 # BSDFs
 # ---------------------------------------------------------------------------
