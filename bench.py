@@ -15,6 +15,7 @@ shade/compaction per bounce) for all 640 000 primary rays, with field, mesh
 and workspace resident in HBM.  Prints one JSON line.
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import math
@@ -28,6 +29,8 @@ sys.path.insert(0, ROOT)
 METRIC = "rays/sec (full bounce paths) plain FP32 vs proposal+FP16 at >=40 dB PSNR"
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3   # MI355X published dense FP32 matrix peak
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X published dense BF16 matrix peak
+PROPOSAL_MACS = 10 * 16 + 16 * 1        # proposal MLP 10 -> 16 -> 1 per proposal sample
 
 
 # Sources that make up the march kernel: HBM traffic taken with rocprofv3
@@ -144,6 +147,34 @@ def proposal_variant(M, sg, sc, F_plain, G, cams, n, plain_img, steps, warmup, t
         R.render(F16, G, o, d, sc.lights, opts)
     ms = timed(step, steps, warmup)
     img = R.radiance.cpu().numpy()
+    stage_ms, stage_n, counters = profiled(M, step, steps, R)
+    fine = int(counters[0])
+    prop = fine                             # 32 proposal intervals and 32 fine samples per marched segment
+    march_s = stage_ms[1] / steps / 1e3
+    flops = 2.0 * (field_macs(sc.field) * fine + PROPOSAL_MACS * prop)
+    gbytes = (gather_bytes(sc.field, 2) * fine + 5 * 8 * 2 * 2 * prop) / 1e9
+    roof = {"kernel": "k_march_prop_pk (camera segment) + k_march_prop (later segments)", "bound": "mfma",
+            "achieved": round(flops / march_s / 1e12, 2), "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(flops / march_s / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4),
+            "gather_GB_per_s": round(gbytes / march_s, 1), "peak_hbm": HBM_PEAK_GBS,
+            "fine_samples_per_step": fine, "proposal_samples_per_step": prop,
+            "launch_ms": round(stage_ms[1] / max(1, stage_n[1]), 4),
+            "stage_ms_per_step": {"closest_hit": round(stage_ms[0] / steps, 3), "march": round(stage_ms[1] / steps, 3),
+                                  "shade": round(stage_ms[2] / steps, 3)}}
+    # the uniform sampler on the same FP16 / BF16 engine: 256 samples (the plain count) and 64
+    # (the proposal's budget of 32 + 32)
+    uniform = {}
+    for ns in (256, 64):
+        scu = dataclasses.replace(sc, n_samples=ns)
+        uopts = M.make_opts(scu, use_occupancy=True)
+
+        def ustep():
+            M.mr_rays_from_cameras(cams, o, d, None, n)
+            R.render(F16, G, o, d, sc.lights, uopts)
+        ums = timed(ustep, steps, 1)
+        uniform[f"uniform_{ns}"] = {"value": round(n / (ums / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ums, 3),
+                                    "psnr_db_vs_plain_fp32": round(psnr_tonemapped(R.radiance.cpu().numpy(),
+                                                                                   plain_img), 2)}
     # the same trained proposal with the per-sample shadow mask (0.2)
     opts_sh = M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P, use_occupancy=True, shadow_mask=0.2)
 
@@ -156,8 +187,76 @@ def proposal_variant(M, sg, sc, F_plain, G, cams, n, plain_img, steps, warmup, t
                                     "ms_per_step": round(ms_sh, 3), "mask": 0.2},
             "psnr_db_vs_plain_fp32": round(psnr_tonemapped(img, plain_img), 2),
             "samples": "32 proposal + 32 fine per segment", "table": "fp16", "mlp": "bf16 (MFMA, fp32 accumulate)",
+            "roofline": roof, "fp16_bf16_engine_uniform_sampler": uniform,
             "train": {"steps": train_steps, "batch_segments": 1 << 14, "loss_first": float(hist[0]),
                       "loss_last": float(hist[-1]), "seconds": round(train_s, 2)}}
+
+
+def profiled(M, step, steps, R):
+    """The steps once more with per-stage event timing on (a pass of its own,
+    so that timed headline steps carry no events): per-stage ms and launches,
+    and the render counters of the last step."""
+    import torch
+    torch.cuda.synchronize()
+    M.mr_profile_read()
+    M.mr_profile_enable(True)
+    try:
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+    finally:
+        M.mr_profile_enable(False)
+    stage_ms, stage_n = M.mr_profile_read()
+    return stage_ms, stage_n, R.counters.cpu().numpy()
+
+
+def shell_proposal(M, sg, steps, train_steps):
+    """Where the samples go matters here: a field whose density sits on a thin
+    spherical shell (the tiny layout; sigma = softplus(-4) off the shell, about
+    softplus(26) on it) among the mid scene's meshes and light, 800x800, 8
+    bounces.  The 256-sample plain FP32 image is the reference; 64 uniform
+    samples and the trained proposal's 32 + 32 take the same budget of field
+    evaluations, in FP32 and on the FP16 / BF16 engine."""
+    import torch
+    sc = dataclasses.replace(sg.mid_scene(), field=sg.shell_field(), name="shell")
+    cams = sg.cameras_array(sc.cameras)
+    n = sc.n_rays
+    F = M.Field(sc.field)
+    F16 = M.Field(sc.field, table_dtype=M.MR_F16, mlp_dtype=M.MR_BF16)
+    for f in (F, F16):
+        f.build_occupancy(sc.occupancy_res, sc.occupancy_thresh)
+    G = M.Mesh(sc.mesh)
+    P = M.Field(sg.make_proposal(), table_dtype=M.MR_F16)
+    T = M.ProposalTrainer(P)
+    to, td = sg.random_rays(1 << 18, seed=508)
+    to, td = torch.from_numpy(to).cuda(), torch.from_numpy(td).cuda()
+    lohi, tgt = T.targets(F, to, td, sc.t_near, sc.t_far, sc.n_samples)
+    hist = T.train(to, td, lohi, tgt, steps=train_steps, batch=1 << 14).cpu().numpy()
+    o = torch.empty(n, 3, device="cuda")
+    d = torch.empty(n, 3, device="cuda")
+    R = M.Renderer(n, sc.max_bounces, with_hits=False)
+
+    def run(field, opts):
+        def step():
+            M.mr_rays_from_cameras(cams, o, d, None, n)
+            R.render(field, G, o, d, sc.lights, opts)
+        ms = timed(step, steps, 1)
+        return ms, R.radiance.cpu().numpy()
+    ms_ref, ref = run(F, M.make_opts(sc, use_occupancy=True))
+    out = {"plain_256_fp32": {"value": round(n / (ms_ref / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms_ref, 3)}}
+    sc64 = dataclasses.replace(sc, n_samples=64)
+    for name, field, opts in (
+            ("uniform_64_fp32", F, M.make_opts(sc64, use_occupancy=True)),
+            ("proposal_32_32_fp32", F, M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P, use_occupancy=True)),
+            ("uniform_64_fp16_bf16", F16, M.make_opts(sc64, use_occupancy=True)),
+            ("proposal_32_32_fp16_bf16", F16,
+             M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P, use_occupancy=True))):
+        ms, img = run(field, opts)
+        out[name] = {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms, 3),
+                     "psnr_db_vs_plain_256_fp32": round(psnr_tonemapped(img, ref), 2)}
+    out["train"] = {"steps": train_steps, "batch_segments": 1 << 14, "loss_first": float(hist[0]),
+                    "loss_last": float(hist[-1])}
+    return out
 
 
 def _rounded_field(sg, f):
@@ -500,6 +599,106 @@ def cloth(M, sg, frames, train_steps):
             "frames": frames, "triangles": int(len(sc.mesh.indices))}
 
 
+def _err_entry(L, hits, rr):
+    import numpy as np
+    ok = ~rr["tie"]
+    ref = rr["radiance"][ok]
+    rel = np.abs(L[ok] - ref) / np.maximum(np.abs(ref), 1e-30)
+    return {"rays": int(len(ok)), "max_rel_err": float(rel.max()), "mean_rel_err": float(rel.mean()),
+            "hit_ids_bit_exact_non_tie": bool(np.array_equal(hits[ok], rr["hit_ids"][ok])),
+            "tie_rays": int((~ok).sum())}
+
+
+def error_vs_oracle(M, sg, n_rays=2000):
+    """Error of the GPU against the FP64 oracle per configuration, on seeded
+    samples of n_rays rays of each full-size image: relative radiance error
+    (max, mean) over the rays the oracle does not flag as ties, and whether
+    their hit ids agree bit for bit.  FP16/BF16 engines are compared with the
+    oracle on the master parameters (total error) and on the parameters as
+    the engine holds them (arithmetic only).  The proposal configurations use
+    a seeded proposal (the oracle takes no input that the GPU produced)."""
+    import copy
+    import numpy as np
+    import torch
+    from oracle import oracle as orc
+    out = {}
+    rng = np.random.default_rng(31)
+
+    def gpu(sc, F, G, opts, o, d):
+        R = M.Renderer(len(o), sc.max_bounces)
+        R.render(F, G, o, d, sc.lights, opts)
+        torch.cuda.synchronize()
+        return R.radiance.cpu().numpy().astype(np.float64), R.hit_ids.cpu().numpy()
+
+    def rays(sc):
+        o = torch.empty(sc.n_rays, 3, device="cuda")
+        d = torch.empty(sc.n_rays, 3, device="cuda")
+        M.mr_rays_from_cameras(sg.cameras_array(sc.cameras), o, d, None, sc.n_rays)
+        idx = np.sort(rng.choice(sc.n_rays, n_rays, replace=False))
+        return o, d, idx, o.cpu().numpy()[idx], d.cpu().numpy()[idx]
+
+    # mid scene: plain FP32 and the FP16 / BF16 engine, uniform 256 and seeded proposal 32 + 32
+    sc = sg.mid_scene()
+    o, d, idx, oh, dh = rays(sc)
+    G = M.Mesh(sc.mesh)
+    F32 = M.Field(sc.field)
+    F16 = M.Field(sc.field, table_dtype=M.MR_F16, mlp_dtype=M.MR_BF16)
+    for f in (F32, F16):
+        f.build_occupancy(sc.occupancy_res, sc.occupancy_thresh)
+    occ, _ = orc.occupancy(sc.field, sc.occupancy_res, sc.occupancy_thresh)
+    scr = copy.copy(sc)
+    scr.field = _rounded_field(sg, sc.field)
+    occr, _ = orc.occupancy(scr.field, sc.occupancy_res, sc.occupancy_thresh)
+    ref = orc.render(sc, oh, dh, ray_ids=idx, occupancy_bits=occ)
+    ref_r = orc.render(scr, oh, dh, ray_ids=idx, occupancy_bits=occr)
+    L, h = gpu(sc, F32, G, M.make_opts(sc, use_occupancy=True), o, d)
+    out["mid_uniform256_fp32"] = {"vs_master_params": _err_entry(L[idx], h[idx], ref)}
+    L, h = gpu(sc, F16, G, M.make_opts(sc, use_occupancy=True), o, d)
+    out["mid_uniform256_fp16_table_bf16_mlp"] = {"vs_master_params": _err_entry(L[idx], h[idx], ref),
+                                                 "vs_rounded_params": _err_entry(L[idx], h[idx], ref_r)}
+    prop = sg.make_proposal(table_amp=0.5)
+    propr = copy.deepcopy(prop)
+    propr.table = prop.table.astype(np.float16).astype(np.float32)
+    P = M.Field(prop, table_dtype=M.MR_F16)
+    popts = M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P, use_occupancy=True)
+    L, h = gpu(sc, F16, G, popts, o, d)
+    rp = orc.render(sc, oh, dh, ray_ids=idx, occupancy_bits=occ, proposal=prop, n_prop=32, n_fine=32)
+    rpr = orc.render(scr, oh, dh, ray_ids=idx, occupancy_bits=occr, proposal=propr, n_prop=32, n_fine=32)
+    out["mid_proposal32x32_fp16_table_bf16_mlp_seeded_proposal"] = {
+        "vs_master_params": _err_entry(L[idx], h[idx], rp), "vs_rounded_params": _err_entry(L[idx], h[idx], rpr)}
+    # cloth (frame 0 and frame 37 after refits): plain FP32 and the seeded proposal on the FP16 / BF16 engine
+    for frame in (0, 37):
+        sc = sg.cloth_scene(frame)
+        o, d, idx, oh, dh = rays(sc)
+        G = M.Mesh(sg.cloth_scene(0).mesh)
+        for f in range(1, frame + 1):
+            G.refit(torch.from_numpy(sg.cloth_vertices(f)).cuda())
+        Fc = M.Field(sc.field)
+        Fc16 = M.Field(sc.field, table_dtype=M.MR_F16, mlp_dtype=M.MR_BF16)
+        scr = copy.copy(sc)
+        scr.field = _rounded_field(sg, sc.field)
+        L, h = gpu(sc, Fc, G, M.make_opts(sc), o, d)
+        out[f"cloth_frame{frame}_uniform256_fp32"] = {
+            "vs_master_params": _err_entry(L[idx], h[idx], orc.render(sc, oh, dh, ray_ids=idx))}
+        L, h = gpu(sc, Fc16, G, M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P), o, d)
+        out[f"cloth_frame{frame}_proposal32x32_fp16_table_bf16_mlp_seeded_proposal"] = {
+            "vs_master_params": _err_entry(L[idx], h[idx], orc.render(sc, oh, dh, ray_ids=idx, proposal=prop)),
+            "vs_rounded_params": _err_entry(L[idx], h[idx], orc.render(scr, oh, dh, ray_ids=idx, proposal=propr))}
+    out["sample"] = f"{n_rays} seeded rays per full-size image (800x800), re-rendered by the oracle one by one"
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(sc, o, d, frac, frac_one_core=512):
     from oracle import oracle as orc
     import numpy as np
@@ -517,7 +716,8 @@ def cpu_baseline(sc, o, d, frac, frac_one_core=512):
     t0 = time.perf_counter()
     orc.render(sc, o[idx1], d[idx1], ray_ids=idx1, n_threads=1, occupancy_bits=occ)
     dt1 = time.perf_counter() - t0
-    return {"value": m / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
+    return {"value": m / dt, "unit": "rays/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+            "host_cpus_seen": os.cpu_count(),
             "sample": f"seeded uniform 1/{frac} ray subset ({m} of {n} rays), FP64 brute force with the "
                       f"oracle's own occupancy grid (built untimed), {dt:.1f} s",
             "one_core": {"value": m1 / dt1, "unit": "rays/s", "cores": 1,
@@ -571,20 +771,17 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    M.mr_profile_read()
-    M.mr_profile_enable(True)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0.record()
     for _ in range(args.steps):
         step()
     t1.record()
     torch.cuda.synchronize()
-    M.mr_profile_enable(False)
     ms_total = t0.elapsed_time(t1)
-    stage_ms, stage_n = M.mr_profile_read()
-    counters = R.counters.cpu().numpy()          # last step: samples, segments, shadow rays, scatters
+    # per-stage times from a second pass of the same steps with event pairs
+    # around every launch (on the stream each kernel runs on)
+    stage_ms, stage_n, counters = profiled(M, step, args.steps, R)   # counters: samples, segments, shadow rays, scatters
     ms_step = ms_total / args.steps
     rays_s = n / (ms_step / 1e3)
     samples = int(counters[0])
@@ -612,7 +809,8 @@ def main():
         "segments_per_s": round(segments / (ms_step / 1e3), 1),
         "stage_ms_per_step": {"closest_hit": round(stage_ms[0] / args.steps, 3),
                               "march": round(march_ms_per_step, 3),
-                              "shade": round(stage_ms[2] / args.steps, 3)},
+                              "shade": round(stage_ms[2] / args.steps, 3),
+                              "note": "a second pass of the same steps with event pairs around each launch"},
         "roofline": {"kernel": "k_march_pc (camera segment) + k_march_mfma (later segments)", "bound": "mfma", "achieved": round(tflops, 2),
                      "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(tflops / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
@@ -633,7 +831,7 @@ def main():
     if not args.no_extras:
         line["proposal_fp16"] = proposal_variant(M, sg, sc, F, G, cams, n, plain_img, args.steps, 1,
                                                  args.train_steps)
-        line["precision_tiny_vs_fp64_oracle"] = precision_report(M, sg)
+        line["shell_field_proposal_vs_uniform"] = shell_proposal(M, sg, args.steps, args.train_steps)
         line["moving_field"] = moving_field(M, sg, sc, F, G, cams, n, args.steps)
         line["sample_shadows"] = sample_shadows(M, sg, sc, F, G, cams, n, args.steps)
         line["emitters"] = emitters(M, sg, args.steps)
@@ -642,9 +840,13 @@ def main():
         line["scaling_spheres"] = scaling(M, sg, 3)
         line["cloth_refit"] = cloth(M, sg, args.cloth_frames, args.train_steps)
     if not args.no_cpu_baseline:
+        # the oracle leg: its time on the host cores, and the GPU's error against it per configuration
         oh = o.cpu().numpy()
         dh = d.cpu().numpy()
         line["cpu_baseline"] = cpu_baseline(sc, oh, dh, args.cpu_frac)
+        if not args.no_extras:
+            line["precision_tiny_vs_fp64_oracle"] = precision_report(M, sg)
+            line["error_vs_fp64_oracle"] = error_vs_oracle(M, sg)
     print(json.dumps(line), flush=True)
 
 
