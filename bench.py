@@ -516,7 +516,11 @@ def several_fields(M, sg, steps, n_fields=3, train_steps=0):
 
 
 def multicam(M, sg, steps):
-    """16 cameras of uneven size and bounce depth in one queue, replayed as a graph."""
+    """16 cameras of uneven size and bounce depth in one queue, replayed as a
+    graph, with the launch shape (march and stage grids, stage tile, march
+    queue chunk and batch, packet segments) chosen by the library's autotuner
+    (coordinate descent over its own candidates, cached per architecture and
+    workload); the default shape is timed beside it."""
     import numpy as np
     import torch
     sc = sg.multicam_scene()
@@ -527,17 +531,42 @@ def multicam(M, sg, steps):
     mb = torch.empty(n, dtype=torch.int32, device="cuda")
     M.mr_camera_bounce_limits(ci, n, limits, mb)
     F, G = M.Field(sc.field), M.Mesh(sc.mesh)
-    R = M.Renderer(n, int(limits.max()), with_hits=False)
+    mbmax = int(limits.max())
+    R = M.Renderer(n, mbmax, with_hits=False)
     opts = M.make_opts(sc)
-    g = M.mr_render_graph_create(F.handle, G.handle, n, o, d, int(limits.max()), mb, sc.lights, opts, R.out,
-                                 R.workspace, R.ws_bytes)
-    try:
-        ms = timed(lambda: M.mr_graph_launch(g), steps, 1)
-    finally:
-        M.mr_graph_destroy(g)
+    key = M.autotune_key("multicam", cams.tobytes(), limits.tobytes(), sc.field.resolutions.tobytes(),
+                         len(sc.mesh.indices), sc.n_samples, sc.rr_after)
+    cache = os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")), "meshrf_autotune.json")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    search = {}
+
+    def tune():
+        t0 = time.perf_counter()
+        shape, ms, ms0, nt = M.mr_autotune_search(F.handle, G.handle, n, o, d, mbmax, mb, sc.lights, opts, R.out,
+                                                  R.workspace, R.ws_bytes, reps=1, passes=2)
+        search.update({"shapes_timed": nt, "search_s": round(time.perf_counter() - t0, 2),
+                       "default_ms_in_search": round(ms0, 3)})
+        return shape, ms
+    shape, tuned_ms, hit = M.autotune_cached(cache, key, tune)
+
+    def graph_ms(o_):
+        g = M.mr_render_graph_create(F.handle, G.handle, n, o, d, mbmax, mb, sc.lights, o_, R.out,
+                                     R.workspace, R.ws_bytes)
+        try:
+            return timed(lambda: M.mr_graph_launch(g), steps, 1)
+        finally:
+            M.mr_graph_destroy(g)
+    ms_default = graph_ms(opts)
+    ms = graph_ms(M.apply_launch(M.make_opts(sc), shape))
     c = R.counters.cpu().numpy()
+    names = ("march_blocks_per_cu", "stage_blocks_per_cu", "stage_tile", "march_chunk", "march_batch",
+             "march_packets")
     return {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "rays": n, "ms_per_frame": round(ms, 3),
             "segments_per_s": round(int(c[1]) / (ms / 1e3), 1), "graph": True,
+            "autotuned": {"shape": dict(zip(names, shape)), "cache_hit": hit, "key": key, **search,
+                          "candidates": dict(zip(names, M.mr_autotune_candidates(n)))},
+            "default_shape": {"value": round(n / (ms_default / 1e3), 1), "unit": "rays/s",
+                              "ms_per_frame": round(ms_default, 3)},
             "bounce_histogram": np.bincount(R.bounces.cpu().numpy(), minlength=17).tolist()}
 
 

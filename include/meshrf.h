@@ -345,14 +345,42 @@ mr_status mr_graph_destroy(mr_graph* graph);
  * launch shape (host array), reps times each after one warm-up, timing with
  * HIP events on stream, and writes the index of the fastest candidate and its
  * mean milliseconds.  The call synchronises with the host.  Output buffers
- * receive the result of the last render; results do not depend on the
- * launch shape. */
+ * receive the result of the last render; results depend on the launch shape
+ * only through march_packets, by FP32 rounding (see mr_autotune_search). */
 mr_status mr_autotune_render(const mr_field* field, const mr_mesh* mesh, int64_t n, const float* origins,
                              const float* dirs, int32_t max_bounces, const int32_t* per_ray_max_bounces,
                              const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
                              mr_render_out* out, void* workspace, size_t workspace_bytes,
                              const mr_launch_cfg* host_cands, int32_t n_cands, int32_t reps,
                              int32_t* best_index, float* best_ms, void* stream);
+
+/* The autotuner's own candidate launch shapes for a queue of n rays on the
+ * current device (the batched multi-camera wavefront picks its tile and queue
+ * sizes from these): per axis, in mr_launch_cfg order (march blocks per CU,
+ * stage blocks per CU, stage tile, march chunk, march batch, packet
+ * segments), counts[axis] values in values[axis * 6 ...].  counts: host
+ * int32[6]; values: host int32[36].  The stage tiles are 128 and those that
+ * give each block of an 8-per-CU grid about 16 and 4 grabs of the queue. */
+mr_status mr_autotune_candidates(int64_t n, int32_t* counts, int32_t* values);
+
+/* Launch-shape search: coordinate descent over mr_autotune_candidates'
+ * values, starting from the launch fields of opts.  Each axis in turn tries
+ * each of its values with the other axes held (one warm-up render, then the
+ * mean of reps renders timed with HIP events on stream) and keeps the
+ * fastest; up to `passes` sweeps over the axes, stopping early when a sweep
+ * changes nothing.  Writes the chosen shape, its mean ms, the starting
+ * shape's mean ms (start_ms, optional) and the number of shapes timed
+ * (n_timed, optional).  The outputs hold the render of the chosen shape.
+ * Hit ids and bounces do not depend on the launch shape, nor does radiance
+ * except through march_packets: packets composite with a running product per
+ * ray and the per-ray march with a prefix product, which round differently
+ * (a few ulp).  Synchronises with the host. */
+mr_status mr_autotune_search(const mr_field* field, const mr_mesh* mesh, int64_t n, const float* origins,
+                             const float* dirs, int32_t max_bounces, const int32_t* per_ray_max_bounces,
+                             const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
+                             mr_render_out* out, void* workspace, size_t workspace_bytes, int32_t reps,
+                             int32_t passes, mr_launch_cfg* best, float* best_ms, float* start_ms,
+                             int32_t* n_timed, void* stream);
 
 /* Pinhole camera rays (device output), camera-major, then row-major with the
  * top row first.  host_cams: n_cams records of 12 floats: position (3),

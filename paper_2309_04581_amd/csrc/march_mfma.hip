@@ -521,10 +521,12 @@ namespace mr {
 std::vector<uint32_t> build_fragments(const mr_field_desc& d, const float* mlp, bool bf) {
   const int NL = d.n_levels, SH = d.sh_components, CL = d.color_hidden_layers;
   const int NF = NL / 2;
-  const int Wd = bf ? 2 : 1;
-  const int KS1 = bf ? NF / 4 : NF, KS2 = bf ? 4 : 16, KSC = bf ? 1 : 4;
-  const int L1 = 0, L2 = L1 + 4 * KS1 * 64 * Wd, C1 = L2 + KS2 * 64 * Wd, C2 = C1 + 4 * KSC * 64 * Wd;
-  const int OUT = C2 + (CL == 2 ? 4 * KS2 * 64 * Wd : 0), SHW = OUT + 192, TOTAL = SHW + 64 * SH;
+  // K values per lane and words per lane of each layer kind (FragLayout)
+  const int KP1 = bf ? bf_kpl(0, NF) : 1, KP2 = bf ? bf_kpl(1, NF) : 1, KPC = bf ? bf_kpl(2, NF) : 1;
+  const int KS1 = NF / KP1, KS2 = 16 / KP2, KSC = 4 / KPC;
+  const int WL1 = bf ? KP1 / 2 : 1, WL2 = bf ? KP2 / 2 : 1, WLC = bf ? KPC / 2 : 1;
+  const int L1 = 0, L2 = L1 + 4 * KS1 * 64 * WL1, C1 = L2 + KS2 * 64 * WL2, C2 = C1 + 4 * KSC * 64 * WLC;
+  const int OUT = C2 + (CL == 2 ? 4 * KS2 * 64 * WL2 : 0), SHW = OUT + 192, TOTAL = SHW + 64 * SH;
   std::vector<uint32_t> w(TOTAL, 0u);
   const float* W1 = mlp;
   const float* W2 = W1 + 64 * d.density_in;
@@ -541,6 +543,7 @@ std::vector<uint32_t> build_fragments(const mr_field_desc& d, const float* mlp, 
     return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
   };
   auto put = [&](int base, int mt, int ks, int nks, const float* M, int in_dim, int rows, int kind) {
+    const int kp = bf ? bf_kpl(kind, NF) : 1;
     for (int lane = 0; lane < 64; ++lane) {
       const int g = lane / 16, row = mt * 16 + lane % 16;
       const int slot = (mt * nks + ks) * 64 + lane;
@@ -548,10 +551,11 @@ std::vector<uint32_t> build_fragments(const mr_field_desc& d, const float* mlp, 
         const int k = frag_k(kind, false, NF, ks, g, 0);
         w[base + slot] = row < rows ? bits(M[row * in_dim + k]) : 0u;
       } else {
-        for (int e = 0; e < 4; ++e) {
+        // kp bf16 values per lane, kp / 2 words, element 0 in the low half
+        for (int e = 0; e < kp; ++e) {
           const int k = frag_k(kind, true, NF, ks, g, e);
           const uint32_t v = row < rows ? bf16(M[row * in_dim + k]) : 0u;
-          w[base + 2 * slot + e / 2] |= v << (16 * (e % 2));
+          w[base + (kp / 2) * slot + e / 2] |= v << (16 * (e % 2));
         }
       }
     }

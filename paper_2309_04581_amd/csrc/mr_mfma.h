@@ -3,8 +3,10 @@
 // One wave evaluates 16 samples at a time.  Lane l serves sample j = l % 16
 // and, for the hash encoding, the level group g = l / 16 (levels
 // g*NL/4 .. (g+1)*NL/4 - 1).  The features a lane gathers are exactly the
-// B-operand values it owns in v_mfma_f32_16x16x4f32 (one K value per lane)
-// or v_mfma_f32_16x16x16bf16 (four K values per lane) for the product
+// B-operand values it owns in v_mfma_f32_16x16x4f32 (one K value per lane),
+// v_mfma_f32_16x16x32_bf16 (eight K values per lane, lane l holding
+// k = 8 (l / 16) .. 8 (l / 16) + 7) or, where a layer's K is 16,
+// v_mfma_f32_16x16x16bf16 (four K values per lane) for the product
 // W (M = output rows) x X^T (N = 16 samples).  A 16x16 accumulator leaves
 // row 4g + v, column j in register v of lane l, which is again the B layout of
 // the next layer up to a fixed permutation of K; the weight fragments staged
@@ -17,35 +19,48 @@ namespace mr {
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef short s4v __attribute__((ext_vector_type(4)));
 
+// K values per lane of one BF16 fragment of each layer kind (layer kinds:
+// 0 density layer 1 over the features, 1 layers over 64 hidden units, 2
+// colour layer 1 over the 16 raw outputs): 8 (the 16x16x32 instruction)
+// where a step can take 32 K values, 4 (16x16x16) where the layer's K is 16.
+__host__ __device__ constexpr int bf_kpl(int kind, int nf) { return kind == 2 ? 4 : (kind == 0 && nf % 8 ? 4 : 8); }
+
 // Fragment layout sizes (in 32-bit words) for a field shape.
 template <int NL, int SH, int CL, bool BF>
 struct FragLayout {
   static constexpr int NF = NL / 2;                          // features per lane (2 per level, NL/4 levels)
-  static constexpr int KS1 = BF ? NF / 4 : NF;               // K steps, density layer 1
-  static constexpr int KS2 = BF ? 4 : 16;                    // K steps over 64 hidden units
-  static constexpr int KSC = BF ? 1 : 4;                     // K steps over the 16 raw outputs
-  static constexpr int W = BF ? 2 : 1;                       // words per lane per fragment
+  static constexpr int KP1 = BF ? bf_kpl(0, NF) : 1;         // K values per lane, density layer 1
+  static constexpr int KP2 = BF ? bf_kpl(1, NF) : 1;         // over 64 hidden units
+  static constexpr int KPC = BF ? bf_kpl(2, NF) : 1;         // over the 16 raw outputs
+  static constexpr int KS1 = NF / KP1;                       // K steps, density layer 1
+  static constexpr int KS2 = 16 / KP2;                       // K steps over 64 hidden units
+  static constexpr int KSC = 4 / KPC;                        // K steps over the 16 raw outputs
+  static constexpr int W1 = BF ? KP1 / 2 : 1;                // words per lane per fragment
+  static constexpr int W2 = BF ? KP2 / 2 : 1;
+  static constexpr int WC = BF ? KPC / 2 : 1;
   static constexpr int L1 = 0;                               // [4 mt][KS1] fragments
-  static constexpr int L2 = L1 + 4 * KS1 * 64 * W;           // [KS2]
-  static constexpr int C1 = L2 + KS2 * 64 * W;               // [4 mt][KSC]
-  static constexpr int C2 = C1 + 4 * KSC * 64 * W;           // [4 mt][KS2] (two hidden colour layers)
-  static constexpr int OUT = C2 + (CL == 2 ? 4 * KS2 * 64 * W : 0);   // FP32 [3][64]
+  static constexpr int L2 = L1 + 4 * KS1 * 64 * W1;          // [KS2]
+  static constexpr int C1 = L2 + KS2 * 64 * W2;              // [4 mt][KSC]
+  static constexpr int C2 = C1 + 4 * KSC * 64 * WC;          // [4 mt][KS2] (two hidden colour layers)
+  static constexpr int OUT = C2 + (CL == 2 ? 4 * KS2 * 64 * W2 : 0);  // FP32 [3][64]
   static constexpr int SHW = OUT + 192;                      // FP32 [4 mt][SH/4][64]: SH columns of colour layer 1
   static constexpr int TOTAL = SHW + 64 * SH;
 };
 
 // K index carried by (step ks, lane group g, element e) for each layer kind.
-// Layer kinds: 0 density layer 1 (features), 1 layers over 64 hidden units,
-// 2 colour layer 1 over the 16 raw outputs.
 __host__ __device__ inline int frag_k(int kind, bool bf, int nf, int ks, int g, int e) {
+  const int kp = bf ? bf_kpl(kind, nf) : 1;
   if (kind == 0) {
     // lane group g holds levels g, g + 4, g + 8, ... (register r: level 4 (r / 2) + g, feature r % 2)
-    (void)nf;
-    const int r = bf ? 4 * ks + e : ks;
+    const int r = kp * ks + e;
     return 8 * (r >> 1) + 2 * g + (r & 1);
   }
-  if (kind == 1) return bf ? ks * 16 + 4 * g + e : (ks / 4) * 16 + 4 * g + (ks % 4);
-  return bf ? 4 * g + e : 4 * g + ks;
+  // the previous layer's outputs in C layout: unit 16 mt + 4 g + v (raw
+  // output 4 g + v) in register v of tile mt; q counts the lane's registers
+  // in the order the steps take them
+  const int q = kp * ks + e;
+  if (kind == 1) return (q >> 2) * 16 + 4 * g + (q & 3);
+  return 4 * g + q;
 }
 
 __device__ __forceinline__ f4v mma(float a, float b, f4v c) {
@@ -55,6 +70,12 @@ __device__ __forceinline__ f4v mma(uint2 a, uint2 b, f4v c) {
   // four bf16 values per operand, element 0 in the low half of .x
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4v, a), __builtin_bit_cast(s4v, b), c, 0, 0,
                                                    0);
+}
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ f4v mma(uint4 a, uint4 b, f4v c) {
+  // eight bf16 values per operand (K = 32), element 0 in the low half of .x
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
+                                                 0, 0, 0);
 }
 
 // Two FP32 values to bf16 (round to nearest even), the first in the low half:
@@ -67,6 +88,10 @@ __device__ __forceinline__ uint32_t pack2_bf16(float a, float b) {
 }
 __device__ __forceinline__ uint2 pack_bf16(float a, float b, float c, float d) {
   return make_uint2(pack2_bf16(a, b), pack2_bf16(c, d));
+}
+__device__ __forceinline__ uint4 pack_bf16(const f4v& lo, const f4v& hi) {
+  return make_uint4(pack2_bf16(lo[0], lo[1]), pack2_bf16(lo[2], lo[3]), pack2_bf16(hi[0], hi[1]),
+                    pack2_bf16(hi[2], hi[3]));
 }
 
 // ReLU on the bit pattern: positive floats order like positive integers and
@@ -148,6 +173,16 @@ __device__ __forceinline__ void mlp_tile(const uint32_t* __restrict__ W, const f
     for (int ks = 0; ks < LY::KS1; ++ks)
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) h[mt] = mma(Wf[LY::L1 + (mt * LY::KS1 + ks) * 64 + lane], fe[ks], h[mt]);
+  } else if constexpr (LY::KP1 == 8) {
+    const uint4* Wb = reinterpret_cast<const uint4*>(W);
+#pragma unroll
+    for (int ks = 0; ks < LY::KS1; ++ks) {
+      const f4v lo = {fe[8 * ks], fe[8 * ks + 1], fe[8 * ks + 2], fe[8 * ks + 3]};
+      const f4v hi = {fe[8 * ks + 4], fe[8 * ks + 5], fe[8 * ks + 6], fe[8 * ks + 7]};
+      const uint4 b = pack_bf16(lo, hi);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) h[mt] = mma(Wb[LY::L1 / 4 + (mt * LY::KS1 + ks) * 64 + lane], b, h[mt]);
+    }
   } else {
     const uint2* Wb = reinterpret_cast<const uint2*>(W);
 #pragma unroll
@@ -171,10 +206,9 @@ __device__ __forceinline__ void mlp_tile(const uint32_t* __restrict__ W, const f
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) rp[mt] = mma(Wf[LY::L2 + (mt * 4 + v) * 64 + lane], h[mt][v], rp[mt]);
   } else {
-    const uint2* Wb = reinterpret_cast<const uint2*>(W);
+    const uint4* Wb = reinterpret_cast<const uint4*>(W);
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
-      rp[ks] = mma(Wb[LY::L2 / 2 + ks * 64 + lane], pack_bf16(h[ks][0], h[ks][1], h[ks][2], h[ks][3]), rp[ks]);
+    for (int ks = 0; ks < 2; ++ks) rp[ks] = mma(Wb[LY::L2 / 4 + ks * 64 + lane], pack_bf16(h[2 * ks], h[2 * ks + 1]), rp[ks]);
   }
   raw = (rp[0] + rp[1]) + (rp[2] + rp[3]);
   sigma = softplusf(__shfl(raw[0], j, 64) + density_offset);
@@ -209,12 +243,12 @@ __device__ __forceinline__ void mlp_tile(const uint32_t* __restrict__ W, const f
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) c2[mt] = mma(Wf[LY::C2 + (mt * 16 + ks) * 64 + lane], c[ks / 4][ks % 4], c2[mt]);
     } else {
-      const uint2* Wb = reinterpret_cast<const uint2*>(W);
+      const uint4* Wb = reinterpret_cast<const uint4*>(W);
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        const uint2 b = pack_bf16(c[ks][0], c[ks][1], c[ks][2], c[ks][3]);
+      for (int ks = 0; ks < 2; ++ks) {
+        const uint4 b = pack_bf16(c[2 * ks], c[2 * ks + 1]);
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) c2[mt] = mma(Wb[LY::C2 / 2 + (mt * 4 + ks) * 64 + lane], b, c2[mt]);
+        for (int mt = 0; mt < 4; ++mt) c2[mt] = mma(Wb[LY::C2 / 4 + (mt * 2 + ks) * 64 + lane], b, c2[mt]);
       }
     }
 #pragma unroll

@@ -1310,6 +1310,163 @@ extern "C" mr_status mr_autotune_render(const mr_field* field, const mr_mesh* me
 }
 
 namespace {
+
+// Candidate values of each launch parameter, generated from the device's
+// compute units and the queue length.  Axis order: march blocks per CU, stage
+// blocks per CU, stage tile, march chunk, march batch, packet segments.
+constexpr int kAxes = 6;
+constexpr int kAxisMax = 6;
+struct TuneAxis {
+  int n;
+  int v[kAxisMax];
+};
+
+void add_value(TuneAxis& a, int v) {
+  for (int i = 0; i < a.n; ++i)
+    if (a.v[i] == v) return;
+  if (a.n < kAxisMax) a.v[a.n++] = v;
+}
+
+void tune_axes(int64_t n, int cus, TuneAxis ax[kAxes]) {
+  for (int k = 0; k < kAxes; ++k) ax[k].n = 0;
+  // march: as many 256-thread blocks as are resident (0), or 1, 2, 4 per CU
+  for (int v : {0, 1, 2, 4}) add_value(ax[0], v);
+  // closest hit and shade: resident maximum (0), or 2, 4, 8 blocks of 128 per CU
+  for (int v : {0, 2, 4, 8}) add_value(ax[1], v);
+  // stage tile: 128 rays per grab, and the tiles that give every block of a
+  // grid of 8 blocks per CU about 16 and about 4 grabs over the queue
+  add_value(ax[2], 128);
+  for (int grabs : {16, 4}) {
+    int64_t t = n / ((int64_t)cus * 8 * grabs);
+    t = std::min<int64_t>(4096, std::max<int64_t>(128, (t / 128) * 128));
+    add_value(ax[2], (int)t);
+  }
+  // march queue: one for the device, or chunks dealt round-robin to the dies
+  // (a chunk a few times a die's share of one grab round)
+  add_value(ax[3], 0);
+  add_value(ax[3], 1024);
+  add_value(ax[3], 8192);
+  // rays per march queue grab
+  for (int v : {1, 2, 4, 8}) add_value(ax[4], v);
+  // packets on the camera segment (0), on no segment (-1), or on the first two
+  for (int v : {0, -1, 2}) add_value(ax[5], v);
+}
+
+int& axis_field(mr_launch_cfg& c, int k) {
+  switch (k) {
+    case 0: return c.march_blocks_per_cu;
+    case 1: return c.stage_blocks_per_cu;
+    case 2: return c.stage_tile;
+    case 3: return c.march_chunk;
+    case 4: return c.march_batch;
+    default: return c.march_packets;
+  }
+}
+
+void apply_cfg(mr_render_opts& o, const mr_launch_cfg& c) {
+  o.march_blocks_per_cu = c.march_blocks_per_cu;
+  o.stage_blocks_per_cu = c.stage_blocks_per_cu;
+  o.stage_tile = c.stage_tile;
+  o.march_chunk = c.march_chunk;
+  o.march_batch = c.march_batch;
+  o.march_packets = c.march_packets;
+}
+
+}  // namespace
+
+extern "C" mr_status mr_autotune_candidates(int64_t n, int32_t* counts, int32_t* values) {
+  if (n < 0 || !counts || !values) return fail(MR_ERR_INVALID_ARG, "null argument or n < 0");
+  TuneAxis ax[kAxes];
+  tune_axes(n, device_cus(), ax);
+  for (int k = 0; k < kAxes; ++k) {
+    counts[k] = ax[k].n;
+    for (int i = 0; i < kAxisMax; ++i) values[k * kAxisMax + i] = i < ax[k].n ? ax[k].v[i] : 0;
+  }
+  return MR_OK;
+}
+
+extern "C" mr_status mr_autotune_search(const mr_field* field, const mr_mesh* mesh, int64_t n, const float* origins,
+                                        const float* dirs, int32_t max_bounces, const int32_t* per_ray_max_bounces,
+                                        const mr_light* host_lights, int32_t n_lights, const mr_render_opts* opts,
+                                        mr_render_out* out, void* workspace, size_t workspace_bytes, int32_t reps,
+                                        int32_t passes, mr_launch_cfg* best, float* best_ms, float* start_ms,
+                                        int32_t* n_timed, void* stream) {
+  if (!opts || !best || !best_ms) return fail(MR_ERR_INVALID_ARG, "null argument");
+  if (reps < 1 || reps > 100) return fail(MR_ERR_INVALID_ARG, "reps must be in 1..100");
+  if (passes < 1 || passes > 4) return fail(MR_ERR_INVALID_ARG, "passes must be in 1..4");
+  mr_status s = validate_render(field, mesh, n, origins, dirs, max_bounces, host_lights, n_lights, opts, out);
+  if (s != MR_OK) return s;
+  if (!workspace || workspace_bytes < mr_render_workspace_size(n))
+    return fail(MR_ERR_INVALID_ARG, "workspace smaller than mr_render_workspace_size(n)");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t a = nullptr, b = nullptr;
+  MR_HIP(hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(MR_ERR_DEVICE, "event create");
+  }
+  // mean time of reps renders with launch shape c, after one warm-up render
+  auto time_cfg = [&](const mr_launch_cfg& c, float& ms) -> mr_status {
+    mr_render_opts o = *opts;
+    apply_cfg(o, c);
+    mr_status r = mr_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, host_lights, n_lights,
+                            &o, out, workspace, workspace_bytes, stream);
+    if (r != MR_OK) return r;
+    if (hipEventRecord(a, st) != hipSuccess) return fail(MR_ERR_DEVICE, "event record");
+    for (int i = 0; i < reps && r == MR_OK; ++i)
+      r = mr_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, host_lights, n_lights, &o, out,
+                    workspace, workspace_bytes, stream);
+    if (r != MR_OK) return r;
+    if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&ms, a, b) != hipSuccess)
+      return fail(MR_ERR_DEVICE, "event timing");
+    ms /= reps;
+    return MR_OK;
+  };
+  // coordinate descent from the caller's launch shape: one axis at a time,
+  // every candidate value of it with the others held, keeping the fastest
+  TuneAxis ax[kAxes];
+  tune_axes(n, device_cus(), ax);
+  mr_launch_cfg cur = {opts->march_blocks_per_cu, opts->stage_blocks_per_cu, opts->stage_tile, opts->march_chunk,
+                       opts->march_batch, opts->march_packets};
+  float cur_ms = 0.0f;
+  int timed = 0;
+  s = time_cfg(cur, cur_ms);
+  ++timed;
+  const float first_ms = cur_ms;
+  for (int p = 0; p < passes && s == MR_OK; ++p) {
+    bool moved = false;
+    for (int k = 0; k < kAxes && s == MR_OK; ++k)
+      for (int i = 0; i < ax[k].n && s == MR_OK; ++i) {
+        if (ax[k].v[i] == axis_field(cur, k)) continue;
+        mr_launch_cfg c = cur;
+        axis_field(c, k) = ax[k].v[i];
+        float ms = 0.0f;
+        s = time_cfg(c, ms);
+        ++timed;
+        if (s == MR_OK && ms < cur_ms) {
+          cur = c;
+          cur_ms = ms;
+          moved = true;
+        }
+      }
+    if (!moved) break;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (s != MR_OK) return s;
+  *best = cur;
+  *best_ms = cur_ms;
+  if (start_ms) *start_ms = first_ms;
+  if (n_timed) *n_timed = timed;
+  // leave the outputs holding the render of the chosen shape
+  mr_render_opts o = *opts;
+  apply_cfg(o, cur);
+  return mr_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, host_lights, n_lights, &o, out,
+                   workspace, workspace_bytes, stream);
+}
+
+namespace {
 struct CamLimits {
   int n;
   int lim[64];

@@ -23,7 +23,7 @@ MR_MIRROR, MR_GLASS, MR_DIFFUSE = 0, 1, 2
 MR_SAMPLER_UNIFORM, MR_SAMPLER_PROPOSAL = 0, 1
 
 EXPORTED = [
-    "mr_autotune_render", "mr_camera_bounce_limits", "mr_field_build_occupancy", "mr_field_create",
+    "mr_autotune_candidates", "mr_autotune_render", "mr_autotune_search", "mr_camera_bounce_limits", "mr_field_build_occupancy", "mr_field_create",
     "mr_field_destroy", "mr_field_params", "mr_field_query", "mr_field_set_pose", "mr_graph_destroy",
     "mr_graph_launch", "mr_last_error", "mr_mesh_build_bvh", "mr_mesh_closest_hit", "mr_mesh_destroy",
     "mr_mesh_info", "mr_mesh_refit", "mr_probe_gather", "mr_profile_enable", "mr_profile_read",
@@ -566,15 +566,60 @@ def mr_autotune_render(field, mesh, n, origins, dirs, max_bounces, per_ray_max_b
     return tuple(candidates[best.value]), ms.value
 
 
+def mr_autotune_candidates(n):
+    """The library's candidate values per launch axis for a queue of n rays:
+    a list of six lists in mr_launch_cfg order."""
+    counts = (C.c_int32 * 6)()
+    values = (C.c_int32 * 36)()
+    _check(lib().mr_autotune_candidates(C.c_int64(n), counts, values))
+    return [[values[6 * k + i] for i in range(counts[k])] for k in range(6)]
+
+
+def mr_autotune_search(field, mesh, n, origins, dirs, max_bounces, per_ray_max_bounces, lights, opts, out,
+                       workspace, workspace_bytes, reps=1, passes=2, stream=None):
+    """Coordinate-descent launch-shape search in the library; returns
+    (best shape as a 6-tuple, its ms, the starting shape's ms, shapes timed)."""
+    arr, nl = _lights_arr(lights)
+    best = LaunchCfg()
+    ms, ms0, nt = C.c_float(), C.c_float(), C.c_int32()
+    _check(lib().mr_autotune_search(field, mesh, C.c_int64(n), _ptr(origins), _ptr(dirs), C.c_int32(max_bounces),
+                                    _ptr(per_ray_max_bounces), arr, C.c_int32(nl), C.byref(opts), C.byref(out),
+                                    _ptr(workspace), C.c_size_t(workspace_bytes), C.c_int32(reps), C.c_int32(passes),
+                                    C.byref(best), C.byref(ms), C.byref(ms0), C.byref(nt), _stream(stream)))
+    shape = (best.march_blocks_per_cu, best.stage_blocks_per_cu, best.stage_tile, best.march_chunk,
+             best.march_batch, best.march_packets)
+    return shape, ms.value, ms0.value, nt.value
+
+
+def apply_launch(opts, shape):
+    """Set the six launch fields of a RenderOpts from a shape tuple."""
+    (opts.march_blocks_per_cu, opts.stage_blocks_per_cu, opts.stage_tile, opts.march_chunk, opts.march_batch,
+     opts.march_packets) = shape
+    return opts
+
+
 def mr_camera_bounce_limits(cam_index, n, cam_limits, out, stream=None):
     lim = np.ascontiguousarray(cam_limits, dtype=np.int32)
     _check(lib().mr_camera_bounce_limits(_ptr(cam_index), C.c_int64(n), _ptr(lim), C.c_int32(len(lim)),
                                          _ptr(out), _stream(stream)))
 
 
+def autotune_key(*parts):
+    """Cache key of a launch shape: the device architecture and a hash of the
+    workload's description (any reprs or byte strings)."""
+    import hashlib
+    import torch
+    h = hashlib.sha256()
+    for p in parts:
+        h.update(p if isinstance(p, bytes) else repr(p).encode())
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    return f"{arch}/{h.hexdigest()[:16]}"
+
+
 def autotune_cached(cache_path, key, tune):
-    """Launch shapes from a JSON cache keyed by (arch, workload); `tune()` runs
-    the autotuner on a miss and returns ((march, stage, tile), ms)."""
+    """Launch shape from a JSON cache keyed by (arch, workload); on a miss
+    `tune()` runs the autotuner and returns (shape, ms); the result is stored.
+    Returns (shape, ms, hit)."""
     import json
     cache = {}
     if os.path.exists(cache_path):

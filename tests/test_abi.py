@@ -107,6 +107,22 @@ def test_noalloc_render_refuses_more_rays_than_its_array_holds():
     assert f"#define MR_NOALLOC_MAX_RAYS {meshrf.MR_NOALLOC_MAX_RAYS}" in hdr
 
 
+def test_autotune_candidates_are_valid_launch_shapes():
+    """The autotuner's candidates (generated from the device's compute units,
+    256 without a GPU, and the queue length) are shapes mr_render accepts, and
+    the stage tiles follow the queue length."""
+    small = meshrf.mr_autotune_candidates(4096)
+    big = meshrf.mr_autotune_candidates(12_000_000)
+    for c in (small, big):
+        assert len(c) == 6 and all(1 <= len(v) <= 6 for v in c)
+        assert all(0 <= v <= 64 for v in c[0] + c[1])
+        assert all(v % 128 == 0 and 128 <= v <= 4096 for v in c[2])
+        assert all(v >= 0 for v in c[3]) and all(1 <= v <= 64 for v in c[4]) and all(v >= -1 for v in c[5])
+    assert small[2] == [128] and max(big[2]) > 128
+    with pytest.raises(meshrf.MrError):
+        meshrf.mr_autotune_candidates(-1)
+
+
 @pytest.mark.parametrize("levels,sh,layers", [(8, 4, 2), (8, 16, 1), (16, 4, 2), (16, 16, 1)])
 def test_field_layouts_without_kernels_are_refused_before_upload(levels, sh, layers):
     """Only layouts with march kernels are accepted: the others are refused

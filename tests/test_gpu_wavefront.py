@@ -51,9 +51,13 @@ def test_graph_replays_equal_eager_render():
         M.mr_graph_destroy(g)
 
 
-def test_multicamera_batch_matches_oracle_on_sampled_rays():
+@pytest.mark.parametrize("shape", [None, (0, 2, 384, 0, 8, 2)], ids=["default", "autotuned"])
+def test_multicamera_batch_matches_oracle_on_sampled_rays(shape):
     """16 cameras (256x256 .. 1920x1080, four inside the mirror box), per-camera
-    bounce limits up to 16, roulette after 3 scatters, all in one queue."""
+    bounce limits up to 16, roulette after 3 scatters, all in one queue; with
+    the default launch shape and with the one the autotuner picked for this
+    workload on the MI355X (8 rays per march grab, packets on the first two
+    segments, 2 stage blocks per CU, 384-ray stage tiles)."""
     M = mr()
     sc = sg.multicam_scene()
     cams = sg.cameras_array(sc.cameras)
@@ -64,7 +68,8 @@ def test_multicamera_batch_matches_oracle_on_sampled_rays():
     M.mr_camera_bounce_limits(ci, n, limits, mb)
     F, G = M.Field(sc.field), M.Mesh(sc.mesh)
     R = M.Renderer(n, int(limits.max()))
-    R.render(F, G, o, d, sc.lights, M.make_opts(sc), per_ray_max_bounces=mb)
+    opts = M.make_opts(sc) if shape is None else M.apply_launch(M.make_opts(sc), shape)
+    R.render(F, G, o, d, sc.lights, opts, per_ray_max_bounces=mb)
     torch.cuda.synchronize()
     bounces = host(R.bounces)
     cih = host(ci)
@@ -78,7 +83,7 @@ def test_multicamera_batch_matches_oracle_on_sampled_rays():
     r = orc.render(sc, host(o)[idx], host(d)[idx], ray_ids=idx, max_bounces=limits[cih[idx]])
     g = dict(radiance=host(R.radiance)[idx], throughput=host(R.throughput)[idx], bounces=bounces[idx],
              hit_ids=host(R.hit_ids)[idx])
-    compare_render(g, r, "multicam sample", max_tie_frac=0.1)
+    compare_render(g, r, f"multicam sample {shape}", max_tie_frac=0.1)
 
 
 def test_autotuner_picks_a_candidate_and_results_do_not_depend_on_launch_shape():
@@ -97,6 +102,41 @@ def test_autotuner_picks_a_candidate_and_results_do_not_depend_on_launch_shape()
     assert best in cands and ms > 0
     for a, b in zip(_outputs(R), ref):
         np.testing.assert_array_equal(a, b)
+
+
+def test_autotune_search_descends_over_the_library_candidates():
+    """The library's coordinate-descent search: the chosen shape takes each
+    axis from the library's candidate values (or the starting shape), every
+    timing is positive, and the outputs it leaves equal the default render."""
+    M = mr()
+    sc = sg.mid_scene(width=64, height=48, n_samples=64)
+    o, d = oracle_camera_rays(sc)
+    o, d = dev(o), dev(d)
+    F, G = M.Field(sc.field), M.Mesh(sc.mesh)
+    opts = M.make_opts(sc)
+    R = M.Renderer(o.shape[0], sc.max_bounces)
+    R.render(F, G, o, d, sc.lights, opts)
+    ref = _outputs(R)
+    shape, ms, ms0, nt = M.mr_autotune_search(F.handle, G.handle, o.shape[0], o, d, sc.max_bounces, None, sc.lights,
+                                              opts, R.out, R.workspace, R.ws_bytes, reps=1, passes=2)
+    cands = M.mr_autotune_candidates(o.shape[0])
+    start = (0, 0, 0, 0, 0, 0)
+    for k in range(6):
+        assert shape[k] in cands[k] or shape[k] == start[k], (k, shape[k], cands[k])
+    assert ms > 0 and ms0 > 0 and ms <= ms0 and nt >= 1 + sum(len(c) - 1 for c in cands)
+    got = _outputs(R)
+    if shape[5] == start[5]:
+        for a, b in zip(got, ref):
+            np.testing.assert_array_equal(a, b)
+    else:
+        # packets and the per-ray march composite in different orders (a running
+        # product per column against a prefix product): FP32 rounding apart,
+        # the same image, and the same hits and bounces
+        for a, b in zip(got, ref):
+            if a.dtype.kind == "f":
+                np.testing.assert_allclose(a, b, rtol=2e-6, atol=1e-7)
+            else:
+                np.testing.assert_array_equal(a, b)
 
 
 def test_gather_probe_runs_and_validates():
