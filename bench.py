@@ -37,7 +37,7 @@ PROPOSAL_MACS = 10 * 16 + 16 * 1        # proposal MLP 10 -> 16 -> 1 per proposa
 # counters is reported only while they are unchanged since the counters were taken.
 MARCH_SOURCES = ["march_mfma.hip", "mr_mfma.h", "mr_field_kernels.h", "mr_device.h", "mr_render.h",
                  "mr_common.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_march_mid_hbm_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_march_mid_fabric_traffic.md")
 
 
 def march_sources_sha256():
@@ -49,9 +49,9 @@ def march_sources_sha256():
 
 
 def measured_traffic():
-    """HBM bytes per march launch (FETCH_SIZE + WRITE_SIZE, each scaled by a
-    plain copy's reading) from the committed counter summary, or None when the
-    march sources have changed since it was taken."""
+    """Fabric bytes per march launch (L2-to-memory read requests counted by
+    size, 32 / 64 / 128 bytes, plus write requests) from the committed counter
+    summary, or None when the march sources have changed since it was taken."""
     try:
         kv = {}
         with open(TRAFFIC_FILE) as fh:
@@ -763,6 +763,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--train-steps", type=int, default=1000)
     ap.add_argument("--cloth-frames", type=int, default=100)
+    ap.add_argument("--segment-samples", action="store_true",
+                    help="print the headline render's field samples per bounce segment and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference dispatch for memory counters)")
     args = ap.parse_args()
@@ -791,6 +793,18 @@ def main():
         M.mr_rays_from_cameras(cams, o, d, None, n)
         R.render(F, G, o, d, sc.lights, opts)
 
+    if args.segment_samples:
+        # renders with the bounce limit raised one segment at a time: the paths
+        # are the same, so the differences are the samples of each segment
+        cum = []
+        for mb in range(sc.max_bounces + 1):
+            Rs = M.Renderer(n, mb, with_hits=False)
+            M.mr_rays_from_cameras(cams, o, d, None, n)
+            Rs.render(F, G, o, d, sc.lights, opts)
+            torch.cuda.synchronize()
+            cum.append(int(Rs.counters.cpu().numpy()[0]))
+        print(json.dumps({"samples_per_segment": [cum[0]] + [cum[i] - cum[i - 1] for i in range(1, len(cum))]}))
+        return
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -843,7 +857,7 @@ def main():
         "roofline": {"kernel": "k_march_pc (camera segment) + k_march_mfma (later segments)", "bound": "mfma", "achieved": round(tflops, 2),
                      "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(tflops / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
-                     "traffic_unit": "bytes per launch (L2 fetch + write, copy-calibrated)",
+                     "traffic_unit": "bytes per launch (L2-to-memory reads by request size + writes)",
                      "launch_ms": round(march_launch_ms, 4),
                      "launches_per_step": launches_per_step},
         "gather": {"achieved": round(gbs, 1), "unit": "GB/s", "peak_hbm": HBM_PEAK_GBS,
