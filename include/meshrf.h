@@ -225,10 +225,13 @@ typedef struct {
                                    L_e as area lights): at each diffuse hit one point on one
                                    emitting triangle, the triangle chosen with probability
                                    proportional to its summed emitted radiance and the point
-                                   uniform by area; a mesh-only shadow ray to 0.999 of the
-                                   way; the estimate (albedo/pi) L_e cos_p cos_x / d^2 A / p
-                                   (emitters two-sided).  A path that reaches an emitter
-                                   straight after a diffuse scatter then adds no L_e there.
+                                   uniform by area; a mesh shadow ray to 0.999 of the way;
+                                   the estimate (albedo/pi) L_e cos_p cos_x / d^2 A / p
+                                   (emitters two-sided) times the medium's transmittance
+                                   along that segment (the fields' density by the midpoint
+                                   rule on the march's grid, empty occupancy cells zero).
+                                   A path that reaches an emitter straight after a diffuse
+                                   scatter then adds no L_e there.
                                    0: emission only where paths reach it */
   int32_t wait_polls;           /* bound on each wait between the producer and consumer
                                    waves of the packet march, in polls (0 = 2^26, about

@@ -875,10 +875,18 @@ static int near_rel(double a, double b, double eps) {
  * cos_p = nf . l, cos_x = |n_k . l| (emitters are two-sided, as the L_e term
  * is added on either side), zero when either cosine is not positive or a
  * mesh lies between: a ray from p + 1e-4 nf toward x finds a triangle before
- * (1 - 1e-3) of the way.  As for the point lights, the shadow ray sees meshes
- * only.  Returns the tie flag of the choice and the shadow ray in *tie. */
-static void emitter_sample(const orc_mesh* m, const double p[3], const double nf[3], const float* mat,
-                           const double u[4], double tie_eps, double tie_rel, double L_add[3], tie_t* tie) {
+ * (1 - 1e-3) of the way.  The light the sample carries crosses the medium
+ * from p + 1e-4 nf to x, so the estimate is multiplied by the transmittance
+ * of that segment (shadow_transmittance); a path that reaches the emitter
+ * by its own bounce is attenuated by the same medium (Eq. 10 then Eq. 12),
+ * so both estimate the same light.  Flagged decisions of the choice, the
+ * shadow ray and the occupancy of the segment's samples go to *tie. */
+static double shadow_transmittance(const orc_opts* opt, const orc_field* f, const double so[3],
+                                   const double sd[3], double len, tie_t* tie);
+
+static void emitter_sample(const orc_mesh* m, const orc_opts* opt, const orc_field* f, const double p[3],
+                           const double nf[3], const float* mat, const double u[4], double tie_eps,
+                           double tie_rel, double L_add[3], tie_t* tie) {
   for (int c = 0; c < 3; ++c) L_add[c] = 0.0;
   double W = 0.0;
   for (int i = 0; i < m->nf; ++i) {
@@ -931,7 +939,55 @@ static void emitter_sample(const orc_mesh* m, const double p[3], const double nf
   if (any_hit(m, so, sd, (1.0 - 1e-3) * sdist, tie_eps, tie)) return;
   const float* em = m->materials + 8 * m->mat_ids[k] + 5;
   double g = cos_p * cos_x / d2 * (0.5 * a2) * (W / wk) / PI;
+  g *= shadow_transmittance(opt, f, so, sd, sdist, tie);
   for (int c = 0; c < 3; ++c) L_add[c] = (double)mat[2 + c] * (double)em[c] * g;
+}
+
+/* Optical depth of one field along [0, len] of the ray so + t sd (world):
+ * its density integrated by the midpoint rule over the march's grid
+ * (spacing (t_far - t_near)/n_samples from t = 0), each interval clipped to
+ * the segment and to the field's box; samples in empty occupancy cells count
+ * zero. */
+static double field_depth(const orc_field* f, const orc_opts* opt, const double so[3], const double sd[3],
+                          double len, tie_t* tie) {
+  double o[3], d[3], b0, b1;
+  world_to_field(f, so, sd, o, d);
+  if (!slab(f, o, d, &b0, &b1)) return 0.0;
+  double lo = fmax(0.0, b0), hi = fmin(len, b1);
+  if (!(hi > lo)) return 0.0;
+  double delta = (opt->t_far - opt->t_near) / opt->n_samples, tau = 0.0;
+  for (int k = 0;; ++k) {
+    double a = k * delta, b = (k + 1) * delta;
+    if (b <= lo) continue;
+    if (a >= hi) break;
+    a = fmax(a, lo);
+    b = fmin(b, hi);
+    double tm = 0.5 * (a + b), x[3], sigma;
+    for (int j = 0; j < 3; ++j) x[j] = o[j] + tm * d[j];
+    if (!occupied(opt, f, x, tie)) continue;
+    orc_field_eval(f, x, d, &sigma, NULL, NULL);
+    tau += sigma * (b - a);
+  }
+  return tau;
+}
+
+/* Transmittance exp(-optical depth) of the medium along a light sample's
+ * shadow segment: the field's, or with several fields the sum of each
+ * field's own depth (the medium is their summed density). */
+static double shadow_transmittance(const orc_opts* opt, const orc_field* f, const double so[3],
+                                   const double sd[3], double len, tie_t* tie) {
+  double tau = 0.0;
+  if (opt->n_fields > 0) {
+    for (int k = 0; k < opt->n_fields; ++k) {
+      orc_opts fo = *opt;
+      fo.occ = opt->field_occ ? opt->field_occ[k] : NULL;
+      fo.occ_res = opt->field_occ_res ? opt->field_occ_res[k] : 0;
+      tau += field_depth(opt->fields[k], &fo, so, sd, len, tie);
+    }
+  } else if (f) {
+    tau = field_depth(f, opt, so, sd, len, tie);
+  }
+  return exp(-tau);
 }
 
 typedef struct {
@@ -1033,7 +1089,7 @@ static void render_ray(const job_t* J, int64_t r) {
       if (opt->sample_emitters) {        /* one light sample on the emitting triangles */
         double ue[4], Le[3];
         draw(opt->seed, rid, s, RNG_EMITTER, ue);
-        emitter_sample(m, p, nf, mat, ue, opt->tie_eps, opt->tie_rel, Le, &tie);
+        emitter_sample(m, opt, J->f, p, nf, mat, ue, opt->tie_eps, opt->tie_rel, Le, &tie);
         for (int c = 0; c < 3; ++c) L[c] += T[c] * Le[c];
       }
     }

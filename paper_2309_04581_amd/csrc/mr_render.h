@@ -77,6 +77,15 @@ struct ShadeParams {
   int sample_emitters;   // light sampling toward the mesh's emitting triangles
 };
 
+// The medium a light sample's shadow segment crosses (light sampling toward
+// emitters): the fields of the render and the spacing of the march's grid.
+struct ShadowMedium {
+  int n;                        // fields (0: the light sample sees no medium)
+  float delta;                  // grid spacing (t_far - t_near) / n_samples
+  int use_occupancy;
+  FieldView f[kMaxFields];
+};
+
 // Ray queue depth word: bits 0-15 segment index (= scatter count so far),
 // bits 16-23 the ray's bounce limit, bit 24 set when the last scatter was
 // diffuse.

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "mr_device.h"
+#include "mr_mfma.h"
 #include "mr_render.h"
 
 using namespace mr;
@@ -180,11 +181,98 @@ __device__ __forceinline__ void finalize(const RenderOut& out, int rid, float tr
   out.bounces[rid] = bounces;
 }
 
+// Optical depth of one field along [0, len] of the world ray so + t sd: the
+// density at the midpoints of the march's grid intervals (spacing delta from
+// t = 0), each clipped to the segment and the field's box, times their
+// lengths; samples in empty occupancy cells count zero.  The density MLP's
+// first layer is accumulated level by level (64 hidden sums, the weights read
+// at uniform addresses), so one thread holds about a hundred registers.
+template <int NL, typename TabT>
+__device__ float field_depth(const FieldView& F, const TabT* __restrict__ tab, V3 so, V3 sd, float len, float delta,
+                             bool occ) {
+  float ox = so.x, oy = so.y, oz = so.z, dx = sd.x, dy = sd.y, dz = sd.z;
+  to_field_frame(F, ox, oy, oz, dx, dy, dz);
+  float b0, b1;
+  if (!slab_box(F, ox, oy, oz, dx, dy, dz, b0, b1)) return 0.0f;
+  const float lo = fmaxf(0.0f, b0), hi = fminf(len, b1);
+  if (!(hi > lo)) return 0.0f;
+  const size_t T = (size_t)F.table_mask + 1u;
+  // the weights are constant for the kernel and read at wave-uniform
+  // addresses: through the constant address space they are scalar loads
+  typedef const __attribute__((address_space(4))) float* ConstF;
+  const ConstF W0 = (ConstF)F.mlp;               // [64][32]
+  const ConstF W1 = (ConstF)(F.mlp + 2048);      // row 0 of [16][64]
+  float tau = 0.0f;
+  // the intervals that meet [lo, hi]: a bounded count, started one early so
+  // that FP32 rounding of k delta cannot skip the first
+  const int k0 = max(0, (int)floorf(lo / delta) - 1), k1 = (int)ceilf(hi / delta) + 1;
+#pragma unroll 1
+  for (int k = k0; k <= k1; ++k) {
+    float a = (float)k * delta, b = (float)(k + 1) * delta;
+    if (b <= lo) continue;
+    if (a >= hi) break;
+    a = fmaxf(a, lo);
+    b = fminf(b, hi);
+    const float tm = 0.5f * (a + b);
+    const float px = ox + tm * dx, py = oy + tm * dy, pz = oz + tm * dz;
+    if (occ && !occ_lookup(F, px, py, pz)) continue;
+    float xh, yh, zh;
+    to_unit(F, px, py, pz, xh, yh, zh);
+    float h[64];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) h[j] = 0.0f;
+#pragma unroll 1
+    for (int l = 0; l < NL; ++l) {
+      uint32_t idx[8];
+      float w[8];
+      level_corners(F, l, xh, yh, zh, idx, w);
+      const TabT* t = tab + (size_t)l * T * 2;
+      float f0 = 0.0f, f1 = 0.0f;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const float2 e = load_entry<TabT>(t, idx[c]);
+        f0 += w[c] * e.x;
+        f1 += w[c] * e.y;
+      }
+#pragma unroll
+      for (int j = 0; j < 64; ++j) h[j] += W0[j * 32 + 2 * l] * f0 + W0[j * 32 + 2 * l + 1] * f1;
+    }
+    float r = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 64; ++j) r += W1[j] * fmaxf(h[j], 0.0f);
+    tau += softplusf(r + F.density_offset) * (b - a);
+  }
+  return tau;
+}
+
+// Transmittance of the medium along a light sample's shadow segment (the sum
+// of the fields' optical depths): the light the sample carries crosses it, as
+// a bounce that reaches the emitter is attenuated by its own march.
+__device__ float shadow_transmittance(const ShadowMedium& SM, V3 so, V3 sd, float len) {
+  float tau = 0.0f;
+  for (int k = 0; k < SM.n; ++k) {
+    const FieldView& F = SM.f[k];
+    const bool occ = SM.use_occupancy && F.occ;
+    if (F.n_levels == 16)
+      tau += F.table_h ? field_depth<16, __half>(F, F.table_h, so, sd, len, SM.delta, occ)
+                       : field_depth<16, float>(F, F.table, so, sd, len, SM.delta, occ);
+    else
+      tau += F.table_h ? field_depth<8, __half>(F, F.table_h, so, sd, len, SM.delta, occ)
+                       : field_depth<8, float>(F, F.table, so, sd, len, SM.delta, occ);
+  }
+  return expf(-tau);
+}
+
+// MEDIUM: light samples toward emitters are attenuated by the fields in SM
+// (only launched with light sampling and a medium; the other instance
+// carries none of that code).
+template <bool MEDIUM>
 __global__ __launch_bounds__(kTraceBlock) void k_shade(RayQueue qi, const int* __restrict__ count_in,
                                                        int* __restrict__ work, int tile, RayQueue qo,
                                                        int* __restrict__ count_out, MeshView M, ShadeParams S,
                                                        RenderOut out, float span, int32_t* __restrict__ hit_ids,
-                                                       int hit_stride, unsigned long long* __restrict__ stats) {
+                                                       int hit_stride, unsigned long long* __restrict__ stats,
+                                                       ShadowMedium SM) {
   __shared__ int stack[kStack * kTraceBlock];
   __shared__ float tstack[kStack * kTraceBlock];
   __shared__ int s_base;
@@ -287,7 +375,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade(RayQueue qi, const int* _
               ++n_shadow;
               if (bvh_trace<true>(M.bvh, sr, (1.0f - 1e-3f) * sdist, th, stack + threadIdx.x, nullptr, kTraceBlock) < 0) {
                 const Material& em = M.mat[__float_as_int(a1.w)];
-                const float g = cos_p * cos_x / d2 * (0.5f * a2x) / e.y * (1.0f / 3.14159265358979323846f);
+                float g = cos_p * cos_x / d2 * (0.5f * a2x) / e.y * (1.0f / 3.14159265358979323846f);
+                if constexpr (MEDIUM) g *= shadow_transmittance(SM, so, sd, sdist);
                 lr += tr * mat.albedo[0] * em.emission[0] * g;
                 lg += tg * mat.albedo[1] * em.emission[1] * g;
                 lb += tb * mat.albedo[2] * em.emission[2] * g;
@@ -890,6 +979,16 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
   S.t_min = opts->t_min_throughput;
   S.sample_emitters = opts->sample_emitters ? 1 : 0;
 
+  // light samples toward emitters cross the render's fields
+  ShadowMedium SM;
+  std::memset(&SM, 0, sizeof(SM));
+  if (S.sample_emitters && mesh && mv.n_emit > 0) {
+    SM.delta = P.delta;
+    SM.use_occupancy = opts->use_occupancy;
+    for (int k = 0; k < n_fields; ++k)
+      if (fields[k]) SM.f[SM.n++] = fields[k]->view;
+  }
+
   RenderOut ro;
   ro.radiance = out->radiance;
   ro.throughput = out->throughput;
@@ -900,7 +999,7 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
   const int trace_blocks =
       persistent_blocks(reinterpret_cast<const void*>(k_trace), kTraceBlock, opts->stage_blocks_per_cu, tiles);
   const int shade_blocks =
-      persistent_blocks(reinterpret_cast<const void*>(k_shade), kTraceBlock, opts->stage_blocks_per_cu, tiles);
+      persistent_blocks(reinterpret_cast<const void*>(k_shade<false>), kTraceBlock, opts->stage_blocks_per_cu, tiles);
   const int packet_segments = opts->march_packets == 0 ? 1 : std::max(0, opts->march_packets);
   const int wide_blocks = (int)std::max<int64_t>(
       1, std::min<int64_t>((std::min<int64_t>(n, kTailRays) + kWideWaves - 1) / kWideWaves, (int64_t)device_cus() * 4));
@@ -954,8 +1053,14 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
     }
     {
       StageTimer tm(2, st, timed);
-      hipLaunchKernelGGL(k_shade, dim3(shade_blocks), dim3(kTraceBlock), 0, st, qi, counts + b, swork + b, tile, qo,
-                         counts + b + 1, mv, S, ro, P.span, out->hit_ids, out->hit_ids ? out->hit_stride : 0, stats);
+      if (SM.n > 0)
+        hipLaunchKernelGGL(k_shade<true>, dim3(shade_blocks), dim3(kTraceBlock), 0, st, qi, counts + b, swork + b, tile,
+                           qo, counts + b + 1, mv, S, ro, P.span, out->hit_ids, out->hit_ids ? out->hit_stride : 0, stats,
+                           SM);
+      else
+        hipLaunchKernelGGL(k_shade<false>, dim3(shade_blocks), dim3(kTraceBlock), 0, st, qi, counts + b, swork + b, tile,
+                           qo, counts + b + 1, mv, S, ro, P.span, out->hit_ids, out->hit_ids ? out->hit_stride : 0, stats,
+                           SM);
       MR_HIP(hipGetLastError());
     }
     if (b < max_bounces) {

@@ -785,6 +785,28 @@ def _fields_gpu(sc, o, d, fields=None, packets=0, use_occupancy=False, occ_res=0
                 hit_ids=host(R.hit_ids), counters=host(R.counters))
 
 
+@pytest.mark.parametrize("spacing", [2.9, 1.2], ids=["disjoint", "overlapping"])
+def test_light_samples_cross_several_fields(spacing):
+    """Light sampling toward an emitting panel above three fields (amplitude-1
+    tiny fields, turned; disjoint boxes, or 1.2 apart so that they overlap):
+    each light sample's shadow segment is attenuated by the summed optical
+    depth of the fields it crosses, against the oracle."""
+    sc = sg.fields_scene(3, 48, 27, kind="tiny", table_amp=1.0, spacing=spacing)
+    ev, ef, em = sg.emitter_quad(y=0.9, half=0.8, radiance=(6.0, 5.0, 4.0))
+    m = sc.mesh
+    sc.mesh = sg.Mesh(vertices=np.concatenate([m.vertices, ev]),
+                      indices=np.concatenate([m.indices, ef + len(m.vertices)]),
+                      mat_ids=np.concatenate([m.mat_ids, np.full(len(ef), len(m.materials), np.int32)]),
+                      materials=np.concatenate([m.materials, sg._materials([em])]))
+    o, d = oracle_camera_rays(sc)
+    r = orc.render(sc, o, d, fields=sc.fields, sample_emitters=True)
+    g = _fields_gpu(sc, o, d, sample_emitters=True)
+    compare_render(g, r, f"3 fields spacing {spacing}, light samples toward an emitter")
+    # the light samples reach the floor through the fields: some radiance comes from the panel
+    plain = _fields_gpu(sc, o, d)
+    assert (g["radiance"] != plain["radiance"]).any()
+
+
 @pytest.mark.parametrize("n_fields,packets", [(2, 0), (3, 0), (3, -1)])
 def test_several_fields_with_proposals_match_oracle(n_fields, packets):
     """Each field sampled by its own proposal (32 + 32 samples per segment,
