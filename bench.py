@@ -48,20 +48,25 @@ def march_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """Fabric bytes per march launch (L2-to-memory read requests counted by
-    size, 32 / 64 / 128 bytes, plus write requests) from the committed counter
-    summary, or None when the march sources have changed since it was taken."""
+TRAFFIC_KEYS = ("traffic_bytes_per_launch", "camera_segment_fabric_bytes", "bounce_segments_fabric_bytes")
+
+
+def measured_traffic(key="traffic_bytes_per_launch"):
+    """Fabric bytes of the march (L2-to-memory read requests counted by size,
+    32 / 64 / 128 bytes, plus write requests) from the committed counter
+    summary: per launch, or one step's bytes on the camera segment or on the
+    bounce segments; None when the march sources have changed since it was
+    taken."""
     try:
         kv = {}
         with open(TRAFFIC_FILE) as fh:
             for ln in fh:
-                if ":" in ln and ln.split(":", 1)[0].strip() in ("traffic_bytes_per_launch", "march_sources_sha256"):
+                if ":" in ln and ln.split(":", 1)[0].strip() in TRAFFIC_KEYS + ("march_sources_sha256",):
                     k, v = ln.split(":", 1)
                     kv[k.strip()] = v.strip().strip("`")
         if kv.get("march_sources_sha256") != march_sources_sha256():
             return None
-        return int(float(kv["traffic_bytes_per_launch"]))
+        return int(float(kv[key]))
     except (OSError, KeyError, ValueError):
         return None
 
@@ -825,6 +830,14 @@ def main():
     # per-stage times from a second pass of the same steps with event pairs
     # around every launch (on the stream each kernel runs on)
     stage_ms, stage_n, counters = profiled(M, step, args.steps, R)   # counters: samples, segments, shadow rays, scatters
+    # the camera segment's march alone: the same render stopped at its first surface
+    R0 = M.Renderer(n, 0, with_hits=False)
+
+    def step0():
+        M.mr_rays_from_cameras(cams, o, d, None, n)
+        R0.render(F, G, o, d, sc.lights, opts)
+    step0()
+    stage0_ms, _, counters0 = profiled(M, step0, args.steps, R0)
     ms_step = ms_total / args.steps
     rays_s = n / (ms_step / 1e3)
     samples = int(counters[0])
@@ -837,6 +850,22 @@ def main():
     flops_per_step = 2.0 * field_macs(sc.field) * samples
     tflops = flops_per_step / (march_ms_per_step / 1e3) / 1e12
     gbs = gather_bytes(sc.field) * samples / (march_ms_per_step / 1e3) / 1e9
+    # split: camera segment (k_march_pc) and bounce segments (k_march_mfma)
+    cam_ms = stage0_ms[1] / args.steps
+    cam_samples = int(counters0[0])
+    bnc_ms = march_ms_per_step - cam_ms
+    bnc_samples = samples - cam_samples
+
+    def seg_roof(ms, ns, fabric):
+        fl = 2.0 * field_macs(sc.field) * ns / (ms / 1e3) / 1e12
+        out = {"ms_per_step": round(ms, 3), "samples": ns, "ns_per_sample": round(ms * 1e6 / max(1, ns), 4),
+               "achieved_TFLOPs": round(fl, 2), "frac_fp32_mfma": round(fl / FP32_MFMA_PEAK_TFLOPS, 4),
+               "algorithmic_gather_GB_per_s": round(gather_bytes(sc.field) * ns / (ms / 1e3) / 1e9, 1)}
+        if fabric is not None:
+            out["fabric_GB_per_s"] = round(fabric / (ms / 1e3) / 1e9, 1)
+            out["fabric_frac_of_hbm_peak"] = round(fabric / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+            out["fabric_bytes_per_sample"] = round(fabric / max(1, ns), 1)
+        return out
 
     line = {
         "metric": METRIC, "value": round(rays_s, 1), "unit": "rays/s", "n_gpus": 1,
@@ -859,7 +888,11 @@ def main():
                      "frac": round(tflops / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
                      "traffic_unit": "bytes per launch (L2-to-memory reads by request size + writes)",
                      "launch_ms": round(march_launch_ms, 4),
-                     "launches_per_step": launches_per_step},
+                     "launches_per_step": launches_per_step,
+                     "camera_segment": dict(kernel="k_march_pc", **seg_roof(
+                         cam_ms, cam_samples, measured_traffic("camera_segment_fabric_bytes"))),
+                     "bounce_segments": dict(kernel="k_march_mfma", **seg_roof(
+                         bnc_ms, bnc_samples, measured_traffic("bounce_segments_fabric_bytes")))},
         "gather": {"achieved": round(gbs, 1), "unit": "GB/s", "peak_hbm": HBM_PEAK_GBS,
                    "bytes_per_sample": gather_bytes(sc.field)},
     }
