@@ -229,7 +229,8 @@ typedef struct {
                                    the estimate (albedo/pi) L_e cos_p cos_x / d^2 A / p
                                    (emitters two-sided) times the medium's transmittance
                                    along that segment (the fields' density by the midpoint
-                                   rule on the march's grid, empty occupancy cells zero).
+                                   rule on the march's grid, empty occupancy cells zero;
+                                   at most 2^20 grid intervals per field and segment).
                                    A path that reaches an emitter straight after a diffuse
                                    scatter then adds no L_e there.
                                    0: emission only where paths reach it */

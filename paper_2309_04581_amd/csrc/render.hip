@@ -203,11 +203,14 @@ __device__ float field_depth(const FieldView& F, const TabT* __restrict__ tab, V
   const ConstF W0 = (ConstF)F.mlp;               // [64][32]
   const ConstF W1 = (ConstF)(F.mlp + 2048);      // row 0 of [16][64]
   float tau = 0.0f;
-  // the intervals that meet [lo, hi]: a bounded count, started one early so
-  // that FP32 rounding of k delta cannot skip the first
-  const int k0 = max(0, (int)floorf(lo / delta) - 1), k1 = (int)ceilf(hi / delta) + 1;
+  // the intervals that meet [lo, hi], started one early so that FP32 rounding
+  // of k delta cannot skip the first; at most 2^20 per field (a box 2^20 grid
+  // intervals across), so the loop is bounded (indices clamped below 2^40)
+  const float kf0 = fminf(fmaxf(0.0f, floorf(lo / delta) - 1.0f), 1.0995e12f);
+  const float kf1 = fminf(ceilf(hi / delta) + 1.0f, kf0 + (float)(1 << 20));
+  const int64_t k0 = (int64_t)kf0, k1 = (int64_t)kf1;
 #pragma unroll 1
-  for (int k = k0; k <= k1; ++k) {
+  for (int64_t k = k0; k <= k1; ++k) {
     float a = (float)k * delta, b = (float)(k + 1) * delta;
     if (b <= lo) continue;
     if (a >= hi) break;
