@@ -153,6 +153,14 @@ def proposal_variant(M, sg, sc, F_plain, G, cams, n, plain_img, steps, warmup, t
     ms = timed(step, steps, warmup)
     img = R.radiance.cpu().numpy()
     stage_ms, stage_n, counters = profiled(M, step, steps, R)
+    # the camera segment alone (the same render stopped at its first surface)
+    R0 = M.Renderer(n, 0, with_hits=False)
+
+    def step0():
+        M.mr_rays_from_cameras(cams, o, d, None, n)
+        R0.render(F16, G, o, d, sc.lights, opts)
+    step0()
+    stage0_ms, _, counters0 = profiled(M, step0, steps, R0)
     fine = int(counters[0])
     prop = fine                             # 32 proposal intervals and 32 fine samples per marched segment
     march_s = stage_ms[1] / steps / 1e3
@@ -165,7 +173,11 @@ def proposal_variant(M, sg, sc, F_plain, G, cams, n, plain_img, steps, warmup, t
             "fine_samples_per_step": fine, "proposal_samples_per_step": prop,
             "launch_ms": round(stage_ms[1] / max(1, stage_n[1]), 4),
             "stage_ms_per_step": {"closest_hit": round(stage_ms[0] / steps, 3), "march": round(stage_ms[1] / steps, 3),
-                                  "shade": round(stage_ms[2] / steps, 3)}}
+                                  "shade": round(stage_ms[2] / steps, 3)},
+            "camera_segment": {"kernel": "k_march_prop_pk", "ms_per_step": round(stage0_ms[1] / steps, 3),
+                               "fine_samples": int(counters0[0])},
+            "bounce_segments": {"kernel": "k_march_prop", "ms_per_step": round((stage_ms[1] - stage0_ms[1]) / steps, 3),
+                                "fine_samples": fine - int(counters0[0])}}
     # the uniform sampler on the same FP16 / BF16 engine: 256 samples (the plain count) and 64
     # (the proposal's budget of 32 + 32)
     uniform = {}
