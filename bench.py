@@ -153,17 +153,10 @@ def proposal_variant(M, sg, sc, F_plain, G, cams, n, plain_img, steps, warmup, t
     ms = timed(step, steps, warmup)
     img = R.radiance.cpu().numpy()
     stage_ms, stage_n, counters = profiled(M, step, steps, R)
-    # the camera segment alone (the same render stopped at its first surface)
-    R0 = M.Renderer(n, 0, with_hits=False)
-
-    def step0():
-        M.mr_rays_from_cameras(cams, o, d, None, n)
-        R0.render(F16, G, o, d, sc.lights, opts)
-    step0()
-    stage0_ms, _, counters0 = profiled(M, step0, steps, R0)
     fine = int(counters[0])
     prop = fine                             # 32 proposal intervals and 32 fine samples per marched segment
-    march_s = stage_ms[1] / steps / 1e3
+    march_ms = stage_ms[1] + stage_ms[3]            # later segments + camera segment
+    march_s = march_ms / steps / 1e3
     flops = 2.0 * (field_macs(sc.field) * fine + PROPOSAL_MACS * prop)
     gbytes = (gather_bytes(sc.field, 2) * fine + 5 * 8 * 2 * 2 * prop) / 1e9
     roof = {"kernel": "k_march_prop_pk (camera segment) + k_march_prop (later segments)", "bound": "mfma",
@@ -171,13 +164,11 @@ def proposal_variant(M, sg, sc, F_plain, G, cams, n, plain_img, steps, warmup, t
             "frac": round(flops / march_s / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4),
             "gather_GB_per_s": round(gbytes / march_s, 1), "peak_hbm": HBM_PEAK_GBS,
             "fine_samples_per_step": fine, "proposal_samples_per_step": prop,
-            "launch_ms": round(stage_ms[1] / max(1, stage_n[1]), 4),
-            "stage_ms_per_step": {"closest_hit": round(stage_ms[0] / steps, 3), "march": round(stage_ms[1] / steps, 3),
+            "launch_ms": round(march_ms / max(1, stage_n[1] + stage_n[3]), 4),
+            "stage_ms_per_step": {"closest_hit": round(stage_ms[0] / steps, 3), "march": round(march_ms / steps, 3),
                                   "shade": round(stage_ms[2] / steps, 3)},
-            "camera_segment": {"kernel": "k_march_prop_pk", "ms_per_step": round(stage0_ms[1] / steps, 3),
-                               "fine_samples": int(counters0[0])},
-            "bounce_segments": {"kernel": "k_march_prop", "ms_per_step": round((stage_ms[1] - stage0_ms[1]) / steps, 3),
-                                "fine_samples": fine - int(counters0[0])}}
+            "camera_segment": {"kernel": "k_march_prop_pk", "ms_per_step": round(stage_ms[3] / steps, 3)},
+            "bounce_segments": {"kernel": "k_march_prop", "ms_per_step": round(stage_ms[1] / steps, 3)}}
     # the uniform sampler on the same FP16 / BF16 engine: 256 samples (the plain count) and 64
     # (the proposal's budget of 32 + 32)
     uniform = {}
@@ -852,30 +843,28 @@ def main():
     # per-stage times from a second pass of the same steps with event pairs
     # around every launch (on the stream each kernel runs on)
     stage_ms, stage_n, counters = profiled(M, step, args.steps, R)   # counters: samples, segments, shadow rays, scatters
-    # the camera segment's march alone: the same render stopped at its first surface
-    R0 = M.Renderer(n, 0, with_hits=False)
-
-    def step0():
-        M.mr_rays_from_cameras(cams, o, d, None, n)
-        R0.render(F, G, o, d, sc.lights, opts)
-    step0()
-    stage0_ms, _, counters0 = profiled(M, step0, args.steps, R0)
     ms_step = ms_total / args.steps
     rays_s = n / (ms_step / 1e3)
     samples = int(counters[0])
     segments = int(counters[1])
 
     # dominant kernel: the march (field gathers + MLPs + compositing)
-    march_ms_per_step = stage_ms[1] / args.steps
-    march_launch_ms = stage_ms[1] / max(1, stage_n[1])
-    launches_per_step = stage_n[1] / args.steps
+    # the march: stage 3 the camera segment (k_march_pc), stage 1 the later segments (k_march_mfma)
+    march_ms_per_step = (stage_ms[1] + stage_ms[3]) / args.steps
+    march_launch_ms = (stage_ms[1] + stage_ms[3]) / max(1, stage_n[1] + stage_n[3])
+    launches_per_step = (stage_n[1] + stage_n[3]) / args.steps
     flops_per_step = 2.0 * field_macs(sc.field) * samples
     tflops = flops_per_step / (march_ms_per_step / 1e3) / 1e12
     gbs = gather_bytes(sc.field) * samples / (march_ms_per_step / 1e3) / 1e9
-    # split: camera segment (k_march_pc) and bounce segments (k_march_mfma)
-    cam_ms = stage0_ms[1] / args.steps
-    cam_samples = int(counters0[0])
-    bnc_ms = march_ms_per_step - cam_ms
+    # split: camera segment (k_march_pc) and bounce segments (k_march_mfma); samples of the
+    # camera segment from the same render stopped at its first surface (the same samples)
+    R0 = M.Renderer(n, 0, with_hits=False)
+    M.mr_rays_from_cameras(cams, o, d, None, n)
+    R0.render(F, G, o, d, sc.lights, opts)
+    torch.cuda.synchronize()
+    cam_ms = stage_ms[3] / args.steps
+    cam_samples = int(R0.counters.cpu().numpy()[0])
+    bnc_ms = stage_ms[1] / args.steps
     bnc_samples = samples - cam_samples
 
     def seg_roof(ms, ns, fabric):

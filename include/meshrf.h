@@ -450,8 +450,9 @@ mr_status mr_proposal_train_step(mr_field* proposal, int64_t n, const float* ori
 /* ------------------------------------------------------------------------ */
 /* Kernel timing for measurement.  While enabled, mr_render records a HIP   */
 /* event pair on its stream around each kernel it launches.  mr_profile_read */
-/* waits for those events and returns, per stage (0 closest hit, 1 march,   */
-/* 2 shade, 3 other), the summed milliseconds and the number of launches,   */
+/* waits for those events and returns, per stage (0 closest hit, 1 march of */
+/* the later segments, 2 shade, 3 march of the camera segment), the summed  */
+/* milliseconds and the number of launches,                                 */
 /* then clears them.  Process-wide; not for use under graph capture.        */
 /* ------------------------------------------------------------------------ */
 mr_status mr_profile_enable(int32_t on);

@@ -1018,12 +1018,12 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
     }
     if (n_fields > 1 && joint) {
       // one march over the summed medium
-      StageTimer tm(1, st, timed);
+      StageTimer tm(b == 0 ? 3 : 1, st, timed);
       s = dispatch_march_fields(fields, n_fields, qi, counts + b, work + kXcds * b, P, mv.bvh, b < packet_segments,
                                 stats, opts->march_blocks_per_cu, n, st);
       if (s != MR_OK) return s;
     } else if (n_fields > 1) {
-      StageTimer tm(1, st, timed);
+      StageTimer tm(b == 0 ? 3 : 1, st, timed);
       const int fblocks = (int)std::min<int64_t>((n + 255) / 256, 65535);
       hipLaunchKernelGGL(k_fields_prep, dim3(fblocks), dim3(256), 0, st, counts + b, fscratch, n_fields, cap, fctr,
                          n_fields * kXcds);
@@ -1045,7 +1045,7 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
       hipLaunchKernelGGL(k_fields_combine, dim3(fblocks), dim3(256), 0, st, qi, counts + b, fscratch, cap, FB);
       MR_HIP(hipGetLastError());
     } else if (field) {
-      StageTimer tm(1, st, timed);
+      StageTimer tm(b == 0 ? 3 : 1, st, timed);
       if (opts->sampler == MR_SAMPLER_PROPOSAL)
         s = dispatch_march_proposal(field, opts->proposal, qi, counts + b, work + kXcds * b, P, mv.bvh, opts->n_proposal,
                                     opts->n_fine, b < packet_segments, stats, opts->march_blocks_per_cu, n, st);
