@@ -309,11 +309,14 @@ def precision_report(M, sg):
         cam = sg.cameras_array(sc.cameras)[0]
         o, d = orc.rays_from_camera(cam)
         o, d = o.astype(np.float32), d.astype(np.float32)
+        t0 = time.perf_counter()
         ref = orc.render(sc, o, d)
+        oracle_s = time.perf_counter() - t0
         scr = copy.copy(sc)
         scr.field = _rounded_field(sg, sc.field)
         ref_r = orc.render(scr, o, d)
-        res = {}
+        res = {"oracle_full_image": {"rays": len(o), "seconds": round(oracle_s, 3),
+                                     "rays_per_s": round(len(o) / oracle_s, 1), "cores": orc.n_threads_default()}}
         for name, td, md in (("fp32", M.MR_F32, M.MR_F32), ("fp16_table_bf16_mlp", M.MR_F16, M.MR_BF16)):
             F, G = M.Field(sc.field, td, md), M.Mesh(sc.mesh)
             R = M.Renderer(len(o), sc.max_bounces)
