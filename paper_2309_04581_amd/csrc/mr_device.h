@@ -218,16 +218,6 @@ __device__ __forceinline__ void density_mlp(const float* __restrict__ W, const f
   }
 }
 
-// density output alone (raw[0] of density_mlp), for paths that need no colour:
-// one accumulator instead of 16
-template <int NL>
-__device__ __forceinline__ float density_raw0(const float* __restrict__ W, const float* feat) {
-  float r = 0.0f;
-#pragma unroll 4
-  for (int j = 0; j < 64; ++j) r += W[2048 + j] * fmaxf(dot_row<2 * NL>(W + j * 32, feat), 0.0f);
-  return r;
-}
-
 // ---------------------------------------------------------------------------
 // watertight ray-triangle test (Woop, Benthin, Wald, JCGT 2013) in FP32,
 // evaluated without FMA contraction so that a shared edge gives the two

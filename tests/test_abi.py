@@ -123,6 +123,22 @@ def test_autotune_candidates_are_valid_launch_shapes():
         meshrf.mr_autotune_candidates(-1)
 
 
+def test_autotune_search_validates_before_any_launch():
+    """The launch-shape search refuses bad repetition and sweep counts and a
+    bad render before it renders anything (no GPU is needed to see it)."""
+    opts = meshrf.RenderOpts()
+    opts.t_near, opts.t_far, opts.n_samples = 0.05, 4.0, 64
+    out = meshrf.RenderOut()
+    for reps, passes, what in ((0, 1, "reps"), (1, 0, "passes"), (101, 1, "reps")):
+        with pytest.raises(meshrf.MrError) as e:
+            meshrf.mr_autotune_search(None, None, 4, None, None, 4, None, [], opts, out, None, 0, reps=reps,
+                                      passes=passes, stream=_Null())
+        assert e.value.status == meshrf.MR_ERR_INVALID_ARG and what in str(e.value)
+    with pytest.raises(meshrf.MrError) as e:
+        meshrf.mr_autotune_search(None, None, 4, None, None, 4, None, [], opts, out, None, 0, stream=_Null())
+    assert "null rays" in str(e.value)
+
+
 @pytest.mark.parametrize("levels,sh,layers", [(8, 4, 2), (8, 16, 1), (16, 4, 2), (16, 16, 1)])
 def test_field_layouts_without_kernels_are_refused_before_upload(levels, sh, layers):
     """Only layouts with march kernels are accepted: the others are refused

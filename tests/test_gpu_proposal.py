@@ -190,6 +190,30 @@ def test_proposal_render_with_sample_shadows_matches_oracle(fieldkind, packets):
     compare_render(g, r, f"proposal {fieldkind} sample shadows packets={packets}", rtol=tol, atol=1e-6)
 
 
+@pytest.mark.parametrize("table_amp", [1e-4, 1.0])
+def test_proposal_render_with_light_sampling_matches_oracle(table_amp):
+    """The emitter scene (mid meshes and field, ceiling panel) at 32x24 under
+    the proposal sampler with light sampling toward the panel: the fine
+    samples come from the seeded proposal, the light samples' transmittance
+    from the uniform grid of the march, against the oracle."""
+    M = mr()
+    sc = sg.emitter_scene(width=32, height=24)
+    if table_amp != 1e-4:
+        sc.field = sg.mid_field(2, table_amp)
+    prop = sg.make_proposal(table_amp=0.5)
+    o, d = oracle_camera_rays(sc)
+    r = orc.render(sc, o, d, proposal=prop, n_prop=32, n_fine=32, sample_emitters=True)
+    F, G = M.Field(sc.field), M.Mesh(sc.mesh)
+    P = M.Field(prop, table_dtype=M.MR_F32)
+    R = M.Renderer(len(o), sc.max_bounces)
+    R.render(F, G, dev(o), dev(d), sc.lights,
+             M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P, sample_emitters=True))
+    g = dict(radiance=host(R.radiance), throughput=host(R.throughput), bounces=host(R.bounces),
+             hit_ids=host(R.hit_ids))
+    tol = 1e-4 if table_amp < 1e-3 else 1e-3
+    compare_render(g, r, f"proposal + light sampling amp {table_amp}", rtol=tol, atol=1e-6)
+
+
 def test_proposal_fp16_full_size_sampled():
     """The benchmark's second configuration at full size: 800x800 mid scene,
     FP16 table + BF16 MLPs, FP16 proposal table, 32 + 32 samples, occupancy
