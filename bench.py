@@ -447,10 +447,22 @@ def emitters(M, sg, steps):
         M.mr_rays_from_cameras(cams, o, d, None, n)
         R.render(F, G, o, d, sc.lights, opts_ls)
     ms_ls = timed(step_ls, steps, 1)
+    mean_ls = [round(float(x), 5) for x in R.radiance.mean(0).cpu().numpy()]
+    # the same with the light samples' optical depth on a coarse grid (32 intervals per segment length)
+    opts_c = M.make_opts(sc, use_occupancy=True, sample_emitters=True, light_depth_samples=32)
+
+    def step_c():
+        M.mr_rays_from_cameras(cams, o, d, None, n)
+        R.render(F, G, o, d, sc.lights, opts_c)
+    ms_c = timed(step_c, steps, 1)
     return {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms, 3), "mean_radiance": mean,
             "with_light_sampling": {"value": round(n / (ms_ls / 1e3), 1), "unit": "rays/s",
-                                    "ms_per_step": round(ms_ls, 3),
-                                    "mean_radiance": [round(float(x), 5) for x in R.radiance.mean(0).cpu().numpy()]}}
+                                    "ms_per_step": round(ms_ls, 3), "mean_radiance": mean_ls,
+                                    "light_depth_grid": "the march's, 256 intervals per segment length"},
+            "with_light_sampling_coarse_depth": {
+                "value": round(n / (ms_c / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms_c, 3),
+                "mean_radiance": [round(float(x), 5) for x in R.radiance.mean(0).cpu().numpy()],
+                "light_depth_grid": "32 intervals per segment length"}}
 
 
 def several_fields(M, sg, steps, n_fields=3, train_steps=0):

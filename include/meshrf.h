@@ -240,6 +240,12 @@ typedef struct {
                                    its packets then miss this segment's medium and
                                    mr_render_status reports it.  Never reached in a correct
                                    run: a bound that keeps every kernel finite */
+  int32_t light_depth_samples;  /* with sample_emitters: grid intervals per segment length
+                                   for the optical depth along a light sample's shadow
+                                   segment (spacing (t_far - t_near) / this), 0..4096;
+                                   0 = n_samples, the march's own grid.  Fewer intervals
+                                   mean fewer density evaluations per light sample; the
+                                   midpoint rule is exact for a constant density */
 } mr_render_opts;
 
 /* One launch shape (the launch fields of mr_render_opts). */

@@ -945,7 +945,8 @@ static void emitter_sample(const orc_mesh* m, const orc_opts* opt, const orc_fie
 
 /* Optical depth of one field along [0, len] of the ray so + t sd (world):
  * its density integrated by the midpoint rule over the march's grid
- * (spacing (t_far - t_near)/n_samples from t = 0), each interval clipped to
+ * (spacing (t_far - t_near)/n_samples from t = 0, or /light_depth_samples
+ * when that is set), each interval clipped to
  * the segment and to the field's box; samples in empty occupancy cells count
  * zero. */
 static double field_depth(const orc_field* f, const orc_opts* opt, const double so[3], const double sd[3],
@@ -955,7 +956,8 @@ static double field_depth(const orc_field* f, const orc_opts* opt, const double 
   if (!slab(f, o, d, &b0, &b1)) return 0.0;
   double lo = fmax(0.0, b0), hi = fmin(len, b1);
   if (!(hi > lo)) return 0.0;
-  double delta = (opt->t_far - opt->t_near) / opt->n_samples, tau = 0.0;
+  int ns = opt->light_depth_samples > 0 ? opt->light_depth_samples : opt->n_samples;
+  double delta = (opt->t_far - opt->t_near) / ns, tau = 0.0;
   for (int k = 0;; ++k) {
     double a = k * delta, b = (k + 1) * delta;
     if (b <= lo) continue;

@@ -91,6 +91,9 @@ typedef struct {
    * roulette, cut-off, emitter choice, in path order) */
   const int32_t* force_hits;
   const uint32_t* flip;
+  /* with sample_emitters: grid intervals per segment length for the optical
+   * depth along a light sample's shadow segment (0 = n_samples) */
+  int32_t light_depth_samples;
 } orc_opts;
 
 typedef struct {

@@ -54,7 +54,8 @@ class _Opts(C.Structure):
                 ("sample_shadows", C.c_int32), ("shadow_mask", C.c_double),
                 ("sample_emitters", C.c_int32), ("n_fields", C.c_int32), ("fields", C.c_void_p),
                 ("field_occ", C.c_void_p), ("field_occ_res", C.c_void_p),
-                ("field_proposals", C.c_void_p), ("force_hits", C.c_void_p), ("flip", C.c_void_p)]
+                ("field_proposals", C.c_void_p), ("force_hits", C.c_void_p), ("flip", C.c_void_p),
+                ("light_depth_samples", C.c_int32)]
 
 
 class _Out(C.Structure):
@@ -217,14 +218,17 @@ def occupancy(field, res, thresh, n_threads=None):
 def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
            tie_eps=1e-5, tie_rel=1e-4, occupancy_bits=None, proposal=None, n_prop=32,
            n_fine=32, field=..., mesh=..., shadow_mask=None, sample_emitters=False, fields=None,
-           field_occupancy=None, field_proposals=None, force_hits=None, flip=None, _gmax=None):
+           field_occupancy=None, field_proposals=None, force_hits=None, flip=None, light_depth_samples=0,
+           _gmax=None):
     """Render FP32 input rays through the whole path in FP64.
 
     shadow_mask: None = no per-sample shadows; else every field sample that a
     mesh hides from a light has its emitted radiance multiplied by this value
     once per such light (Sec. 3.1 "Shadow rays").
     sample_emitters: light sampling toward emitting triangles at diffuse hits
-    (Eq. 12's L_e as area lights).
+    (Eq. 12's L_e as area lights); light_depth_samples: grid intervals per
+    segment length for the optical depth along the light samples' shadow
+    segments (0 = n_samples).
     fields: several fields marched together (the scene's own field is then
     not used); field_occupancy: per field an occupancy bit array or None;
     field_proposals: per field its proposal (the proposal sampler with
@@ -243,7 +247,8 @@ def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
     """
     call = dict(tie_eps=tie_eps, tie_rel=tie_rel, occupancy_bits=occupancy_bits, proposal=proposal,
                 n_prop=n_prop, n_fine=n_fine, field=field, mesh=mesh, shadow_mask=shadow_mask,
-                sample_emitters=sample_emitters, fields=fields, field_occupancy=field_occupancy,
+                sample_emitters=sample_emitters, light_depth_samples=light_depth_samples, fields=fields,
+                field_occupancy=field_occupancy,
                 field_proposals=field_proposals, n_threads=n_threads)
     field = scene.field if field is ... else field
     mesh = scene.mesh if mesh is ... else mesh
@@ -277,6 +282,7 @@ def render(scene, origins, dirs, ray_ids=None, max_bounces=None, n_threads=None,
     if shadow_mask is not None:
         opt.sample_shadows, opt.shadow_mask = 1, float(shadow_mask)
     opt.sample_emitters = 1 if sample_emitters else 0
+    opt.light_depth_samples = int(light_depth_samples)
     keep = []
     if fields is not None:
         if proposal is not None:

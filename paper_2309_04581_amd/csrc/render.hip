@@ -825,6 +825,8 @@ mr_status validate_render(const mr_field* field, const mr_mesh* mesh, int64_t n,
   if (opts->march_batch < 0 || opts->march_batch > 64) return fail(MR_ERR_INVALID_ARG, "march_batch must be in 0..64");
   if (opts->march_packets < -1) return fail(MR_ERR_INVALID_ARG, "march_packets must be >= -1");
   if (opts->wait_polls < 0) return fail(MR_ERR_INVALID_ARG, "wait_polls must be >= 0");
+  if (opts->light_depth_samples < 0 || opts->light_depth_samples > 4096)
+    return fail(MR_ERR_INVALID_ARG, "light_depth_samples must be in 0..4096");
   if (opts->sample_shadows && !(opts->shadow_mask >= 0.0f && opts->shadow_mask <= 1.0f))
     return fail(MR_ERR_INVALID_ARG, "shadow_mask must be in [0, 1]");
   if (opts->use_occupancy && field && !field->occ_dev)
@@ -986,7 +988,7 @@ mr_status render_impl(const mr_field* const* fields, const mr_field* const* prop
   ShadowMedium SM;
   std::memset(&SM, 0, sizeof(SM));
   if (S.sample_emitters && mesh && mv.n_emit > 0) {
-    SM.delta = P.delta;
+    SM.delta = opts->light_depth_samples > 0 ? P.span / (float)opts->light_depth_samples : P.delta;
     SM.use_occupancy = opts->use_occupancy;
     for (int k = 0; k < n_fields; ++k)
       if (fields[k]) SM.f[SM.n++] = fields[k]->view;

@@ -68,7 +68,8 @@ class RenderOpts(C.Structure):
                 ("march_blocks_per_cu", C.c_int32), ("stage_blocks_per_cu", C.c_int32),
                 ("stage_tile", C.c_int32), ("march_chunk", C.c_int32), ("march_batch", C.c_int32),
                 ("march_packets", C.c_int32), ("sample_shadows", C.c_int32), ("shadow_mask", C.c_float),
-                ("sample_emitters", C.c_int32), ("wait_polls", C.c_int32)]
+                ("sample_emitters", C.c_int32), ("wait_polls", C.c_int32),
+                ("light_depth_samples", C.c_int32)]
 
 
 class LaunchCfg(C.Structure):
@@ -355,7 +356,7 @@ class Mesh:
 
 
 def make_opts(scene, sampler=MR_SAMPLER_UNIFORM, proposal=None, n_proposal=32, n_fine=32,
-              use_occupancy=False, shadow_mask=None, sample_emitters=False):
+              use_occupancy=False, shadow_mask=None, sample_emitters=False, light_depth_samples=0):
     o = RenderOpts()
     o.t_near, o.t_far, o.n_samples = scene.t_near, scene.t_far, scene.n_samples
     o.sampler = sampler
@@ -368,6 +369,7 @@ def make_opts(scene, sampler=MR_SAMPLER_UNIFORM, proposal=None, n_proposal=32, n
     if shadow_mask is not None:
         o.sample_shadows, o.shadow_mask = 1, float(shadow_mask)
     o.sample_emitters = int(bool(sample_emitters))
+    o.light_depth_samples = int(light_depth_samples)
     return o
 
 

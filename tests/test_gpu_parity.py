@@ -698,15 +698,17 @@ def test_emitters_match_oracle(packets):
     compare_render(gpu_render(sc, o, d, packets=packets), r, f"emitters packets={packets}")
 
 
-@pytest.mark.parametrize("sample_emitters", [False, True])
-def test_emitter_scene_small_image_matches_oracle(sample_emitters):
+@pytest.mark.parametrize("sample_emitters,light_depth_samples", [(False, 0), (True, 0), (True, 32)])
+def test_emitter_scene_small_image_matches_oracle(sample_emitters, light_depth_samples):
     """The mid scene with its emitting ceiling panel at 32x24, with and
-    without light sampling toward the panel at the floor's diffuse hits."""
+    without light sampling toward the panel at the floor's diffuse hits, the
+    light samples' optical depth on the march's grid or on a coarse one (32
+    intervals per segment length)."""
     sc = sg.emitter_scene(width=32, height=24)
     o, d = oracle_camera_rays(sc)
-    r = orc.render(sc, o, d, sample_emitters=sample_emitters)
-    compare_render(gpu_render(sc, o, d, sample_emitters=sample_emitters), r,
-                   f"emitter scene 32x24 sample_emitters={sample_emitters}")
+    r = orc.render(sc, o, d, sample_emitters=sample_emitters, light_depth_samples=light_depth_samples)
+    compare_render(gpu_render(sc, o, d, sample_emitters=sample_emitters, light_depth_samples=light_depth_samples),
+                   r, f"emitter scene 32x24 sample_emitters={sample_emitters} depth={light_depth_samples}")
 
 
 # ---------------------------------------------------------------------------
