@@ -1429,6 +1429,268 @@ double orc_proposal_loss(const orc_field* p, int64_t n_seg, const float* o, cons
 }
 
 /* ------------------------------------------------------------------------- */
+/* Rounding-error tolerance of the proposal gradient (for tests; it enters   */
+/* no value above).  The gradient of orc_proposal_loss, evaluated in a       */
+/* binary format of unit roundoff u with the contributions of each element   */
+/* summed in any order, is compared with this FP64 result element by element. */
+/* Following the probabilistic rounding error analysis of Higham and Mary    */
+/* (SIAM J. Sci. Comput. 41, 2019), rounding errors are taken as independent */
+/* and of mean zero, so errors of independent terms add in quadrature:        */
+/*   tol_e = u min(n_e, lambda sqrt(n_e)) S_e                                */
+/*         + u min(sum_s b_s, lambda sqrt(sum_s b_s^2)) + Z_e,  b = K m + p,  */
+/* where each min takes the smaller of a worst-case bound and a bound that   */
+/* fails with probability at most about 2 n_e exp(-lambda^2 / 2).  Per      */
+/* element e, over its n_e contributions c_s:                                */
+/*   S_e  sum |c_s|: the final sum (Higham and Mary's bound for summation);  */
+/*   m_s  a running error bound of one contribution: every node of the chain  */
+/*        carries sum |partial| x m(operand) plus |node| (its own rounding),  */
+/*        so differences add up; K bounds the roundings folded into one node */
+/*        (dot products, the 64-lane scans, a few ulps of exp and log);     */
+/*   p_s  the same chain seeded only with the error of the trilinear weights: */
+/*        the lattice coordinate x N of the rounded sample position o + t d   */
+/*        carries N times its error, and each corner weight changes by the    */
+/*        coordinate errors times the other two weight factors;              */
+/*   Z_e  for each ReLU whose sign lies within its own bound, the whole      */
+/*        contribution that hinges on that sign.                             */
+/* Scaled by 1 / n_seg like the gradient.                                    */
+/* ------------------------------------------------------------------------- */
+
+/* lattice-coordinate error (units of u) of one sample and level, per axis,  */
+/* for a position computed as o + (lo + (j + 1/2) D) d and moved to the box */
+static void prop_lattice(const orc_field* p, const double o[3], const double d[3], double lo, double D, int j,
+                         int32_t R, int64_t v0[3], double fr[3], double dxl[3]) {
+  double tm = lo + (j + 0.5) * D;
+  double dtm = 3.0 * (j + 0.5) * D + fabs(tm);
+  for (int k = 0; k < 3; ++k) {
+    double ext = p->aabb_max[k] - p->aabb_min[k], x = o[k] + tm * d[k];
+    double xh = fmin(fmax((x - p->aabb_min[k]) / ext, 0.0), 1.0);
+    double dx = fabs(d[k]) * dtm + fabs(tm * d[k]) + fabs(x);
+    double xl = xh * R, fl = floor(xl);
+    if (fl > R - 1) fl = R - 1;
+    v0[k] = (int64_t)fl;
+    fr[k] = xl - fl;
+    dxl[k] = R * (dx + 2.0 * fabs(x - p->aabb_min[k])) / ext + xl;
+  }
+}
+
+/* corner weight, its rounding magnitude and its position-error magnitude */
+static double prop_corner(int corner, const double fr[3], const double dxl[3], double* mw, double* pw) {
+  double f3[3], ww = 1.0, pp = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    f3[k] = ((corner >> k) & 1) ? fr[k] : 1.0 - fr[k];
+    ww *= f3[k];
+  }
+  for (int k = 0; k < 3; ++k) pp += dxl[k] * f3[(k + 1) % 3] * f3[(k + 2) % 3];
+  *mw = 4.0 * ww;   /* 1 - fr, two products, own rounding */
+  *pw = pp;
+  return ww;
+}
+
+void orc_proposal_grad_bound(const orc_field* p, int64_t n_seg, const float* o_in, const float* d_in,
+                             const float* lohi, const float* target, int32_t nb, double u, double K,
+                             double lambda, double* b_table, double* b_mlp) {
+  int nin = p->n_levels * p->feats, H = p->d_hidden, DI = p->d_in;
+  int64_t TT = (int64_t)1 << p->log2_table;
+  int64_t nt = (int64_t)p->n_levels * TT * p->feats, ne = nt + (int64_t)H * DI + H;
+  /* per element: S, sum b, sum b^2, Z, n */
+  double* S = (double*)calloc(ne, sizeof(double));
+  double* B = (double*)calloc(ne, sizeof(double));
+  double* Q = (double*)calloc(ne, sizeof(double));
+  double* Z = (double*)calloc(ne, sizeof(double));
+  double* N = (double*)calloc(ne, sizeof(double));
+  /* per bin: features and hidden units with their two magnitudes */
+  double (*f)[16] = calloc(nb, sizeof *f), (*mf)[16] = calloc(nb, sizeof *mf), (*pf)[16] = calloc(nb, sizeof *pf);
+  double (*h)[32] = calloc(nb, sizeof *h), (*mh)[32] = calloc(nb, sizeof *mh), (*ph)[32] = calloc(nb, sizeof *ph);
+  /* per bin scalars: value, rounding magnitude, position magnitude */
+  double* sc = (double*)calloc((size_t)15 * (nb + 1), sizeof(double));
+  double *z = sc, *mz = z + nb + 1, *pz = mz + nb + 1, *w = pz + nb + 1, *mw = w + nb + 1, *pw = mw + nb + 1;
+  double *g = pw + nb + 1, *mg = g + nb + 1, *pg = mg + nb + 1, *T = pg + nb + 1, *mT = T + nb + 1;
+  double *pT = mT + nb + 1, *E = pT + nb + 1, *mE = E + nb + 1, *pE = mE + nb + 1;
+  const float* W1 = p->mlp;
+  const float* W2 = p->mlp + (int64_t)H * DI;
+#define ADD(e, c, m, pp)                \
+  do {                                  \
+    double b_ = K * (m) + (pp);         \
+    S[e] += fabs(c);                    \
+    B[e] += b_;                         \
+    Q[e] += b_ * b_;                    \
+    N[e] += 1.0;                        \
+  } while (0)
+  for (int64_t s = 0; s < n_seg; ++s) {
+    double o[3], d[3];
+    for (int k = 0; k < 3; ++k) { o[k] = o_in[3 * s + k]; d[k] = d_in[3 * s + k]; }
+    double lo = lohi[2 * s], hi = lohi[2 * s + 1];
+    if (!(hi > lo)) continue;
+    double D = (hi - lo) / nb;
+    T[0] = 1.0;
+    mT[0] = pT[0] = 0.0;
+    for (int j = 0; j < nb; ++j) {
+      for (int c = 0; c < 16; ++c) f[j][c] = mf[j][c] = pf[j][c] = 0.0;
+      for (int l = 0; l < p->n_levels; ++l) {
+        int64_t v0[3];
+        double fr[3], dxl[3];
+        prop_lattice(p, o, d, lo, D, j, p->res[l], v0, fr, dxl);
+        for (int corner = 0; corner < 8; ++corner) {
+          int64_t v[3];
+          for (int k = 0; k < 3; ++k) v[k] = v0[k] + ((corner >> k) & 1);
+          double mwt, pwt, ww = prop_corner(corner, fr, dxl, &mwt, &pwt);
+          uint32_t idx;
+          orc_hash_index(p->res[l], p->log2_table, v, &idx);
+          const float* e = p->table + ((int64_t)l * TT + idx) * p->feats;
+          for (int c = 0; c < p->feats; ++c) {
+            double ae = fabs((double)e[c]);
+            f[j][l * p->feats + c] += ww * e[c];
+            mf[j][l * p->feats + c] += mwt * ae + 2.0 * ww * ae;
+            pf[j][l * p->feats + c] += pwt * ae;
+          }
+        }
+      }
+      double zz = 0.0, mzz = 0.0, pzz = 0.0;
+      for (int i = 0; i < H; ++i) {
+        double hv = 0.0, m = 0.0, pp = 0.0;
+        for (int c = 0; c < nin; ++c) {
+          double a = W1[(int64_t)i * DI + c];
+          hv += a * f[j][c];
+          m += fabs(a) * mf[j][c] + fabs(a * f[j][c]);
+          pp += fabs(a) * pf[j][c];
+        }
+        h[j][i] = hv;
+        mh[j][i] = m;
+        ph[j][i] = pp;
+        if (hv > 0.0) {
+          zz += W2[i] * hv;
+          mzz += fabs(W2[i]) * m + fabs(W2[i] * hv);
+          pzz += fabs(W2[i]) * pp;
+        }
+      }
+      z[j] = zz;
+      mz[j] = mzz;
+      pz[j] = pzz;
+      double zo = zz + p->density_offset, L = 1.0 / (1.0 + exp(-zo));
+      double sg = softplus(zo), msg = L * (mzz + fabs(zo)) + 4.0 * sg, psg = L * pzz;
+      double y = sg * D, al = -expm1(-y), Ej = exp(-y);
+      double mal = Ej * (D * msg + 2.0 * y) + 2.0 * al, pal = Ej * D * psg;
+      E[j] = Ej;
+      mE[j] = Ej * (D * msg + 2.0 * y + 2.0);
+      pE[j] = pal;
+      double om = 1.0 - al, mom = mal + om;
+      w[j] = T[j] * al;
+      mw[j] = mT[j] * al + T[j] * mal + w[j];
+      pw[j] = pT[j] * al + T[j] * pal;
+      T[j + 1] = T[j] * om;
+      mT[j + 1] = mT[j] * om + T[j] * mom + T[j + 1];
+      pT[j + 1] = pT[j] * om + T[j] * pal;
+      double ht = target[s * nb + j], hd = ht + 1e-7, r = ht - w[j], mr = mw[j] + fabs(r), pr = pw[j];
+      g[j] = r > 0.0 ? -2.0 * r / hd : 0.0;
+      if (r > 0.0 || fabs(r) <= u * (K * mr + pr)) {   /* the sign of r may be rounded either way */
+        mg[j] = 2.0 * mr / hd + 2.0 * fabs(g[j]);
+        pg[j] = 2.0 * pr / hd;
+      } else {
+        mg[j] = pg[j] = 0.0;
+      }
+    }
+    /* the suffix sums come from a scan over all bins: their rounding scales
+       with the sum over all of them */
+    double sall = 0.0;
+    for (int j = 0; j < nb; ++j) sall += fabs(g[j] * w[j]);
+    double suf = 0.0, msuf = 0.0, psuf = 0.0;
+    for (int k = nb - 1; k >= 0; --k) {
+      double a1 = g[k] * T[k] * D * E[k];
+      double ma1 = (mg[k] * T[k] + fabs(g[k]) * mT[k]) * D * E[k] + fabs(g[k]) * T[k] * D * mE[k] + 4.0 * fabs(a1);
+      double pa1 = (pg[k] * T[k] + fabs(g[k]) * pT[k]) * D * E[k] + fabs(g[k]) * T[k] * D * pE[k];
+      double a2 = D * suf, ma2 = D * (msuf + sall) + 3.0 * fabs(a2), pa2 = D * psuf;
+      double dsig = a1 - a2, mds = ma1 + ma2 + fabs(dsig), pds = pa1 + pa2;
+      suf += g[k] * w[k];
+      msuf += mg[k] * w[k] + fabs(g[k]) * mw[k] + fabs(g[k] * w[k]);
+      psuf += pg[k] * w[k] + fabs(g[k]) * pw[k];
+      double zo = z[k] + p->density_offset, L = 1.0 / (1.0 + exp(-zo)), dL = L * (1.0 - L);
+      double dz = dsig * L;
+      double mdz = mds * L + fabs(dsig) * dL * (mz[k] + fabs(zo)) + 4.0 * fabs(dz);
+      double pdz = pds * L + fabs(dsig) * dL * pz[k];
+      double dh[32], mdh[32], pdh[32];
+      int tie[32];
+      for (int i = 0; i < H; ++i) {
+        int on = h[k][i] > 0.0;
+        tie[i] = fabs(h[k][i]) <= u * (K * mh[k][i] + ph[k][i]);
+        dh[i] = on ? dz * W2[i] : 0.0;
+        mdh[i] = on ? mdz * fabs(W2[i]) + fabs(dh[i]) : 0.0;
+        pdh[i] = on ? pdz * fabs(W2[i]) : 0.0;
+      }
+      double df[16] = {0}, mdf[16] = {0}, pdf[16] = {0}, zdf[16] = {0};
+      for (int i = 0; i < H; ++i)
+        for (int c = 0; c < nin; ++c) {
+          double a = W1[(int64_t)i * DI + c];
+          df[c] += dh[i] * a;
+          mdf[c] += mdh[i] * fabs(a) + fabs(dh[i] * a);
+          pdf[c] += pdh[i] * fabs(a);
+          if (tie[i]) zdf[c] += fabs(dz * W2[i] * a);
+        }
+      /* MLP elements: dz [h > 0] W2 f for W1, dz relu(h) for W2; the sums
+         over |W1 f| (inside mh) also cover the form sum_c W1 (dz f) */
+      for (int i = 0; i < H; ++i) {
+        int on = h[k][i] > 0.0;
+        for (int c = 0; c < nin; ++c) {
+          int64_t e = nt + (int64_t)i * DI + c;
+          if (on) ADD(e, dh[i] * f[k][c], mdh[i] * fabs(f[k][c]) + fabs(dh[i]) * mf[k][c] + fabs(dh[i] * f[k][c]),
+                      pdh[i] * fabs(f[k][c]) + fabs(dh[i]) * pf[k][c]);
+          if (tie[i]) Z[e] += fabs(dz * W2[i] * f[k][c]);
+        }
+        int64_t e2 = nt + (int64_t)H * DI + i;
+        if (on) ADD(e2, dz * h[k][i], mdz * mh[k][i] + 2.0 * fabs(dz) * mh[k][i], pdz * mh[k][i] + fabs(dz) * ph[k][i]);
+        if (tie[i]) Z[e2] += fabs(dz) * u * (K * mh[k][i] + ph[k][i]);
+      }
+      /* table elements: corner weight x df */
+      for (int l = 0; l < p->n_levels; ++l) {
+        int64_t v0[3];
+        double fr[3], dxl[3];
+        prop_lattice(p, o, d, lo, D, k, p->res[l], v0, fr, dxl);
+        for (int corner = 0; corner < 8; ++corner) {
+          int64_t v[3];
+          for (int q = 0; q < 3; ++q) v[q] = v0[q] + ((corner >> q) & 1);
+          double mwt, pwt, ww = prop_corner(corner, fr, dxl, &mwt, &pwt);
+          uint32_t idx;
+          orc_hash_index(p->res[l], p->log2_table, v, &idx);
+          for (int c = 0; c < p->feats; ++c) {
+            int64_t e = ((int64_t)l * TT + idx) * p->feats + c;
+            int cc = l * p->feats + c;
+            ADD(e, ww * df[cc], mwt * fabs(df[cc]) + ww * mdf[cc] + fabs(ww * df[cc]), pwt * fabs(df[cc]) + ww * pdf[cc]);
+            Z[e] += ww * zdf[cc];
+          }
+        }
+        /* a lattice coordinate within its error of a cell face: the sample
+           may land in the neighbouring cell, whose far corners then take a
+           weight of at most that error */
+        for (int q = 0; q < 3; ++q) {
+          double ed = u * dxl[q];
+          int64_t far = -1;
+          if (fr[q] <= ed && v0[q] > 0) far = v0[q] - 1;
+          if (1.0 - fr[q] <= ed && v0[q] + 2 <= p->res[l]) far = v0[q] + 2;
+          if (far < 0) continue;
+          for (int corner = 0; corner < 4; ++corner) {
+            int64_t v[3];
+            int b = 0;
+            for (int a = 0; a < 3; ++a) v[a] = a == q ? far : v0[a] + ((corner >> b++) & 1);
+            uint32_t idx;
+            orc_hash_index(p->res[l], p->log2_table, v, &idx);
+            for (int c = 0; c < p->feats; ++c)
+              Z[((int64_t)l * TT + idx) * p->feats + c] += ed * (fabs(df[l * p->feats + c]) + zdf[l * p->feats + c]);
+          }
+        }
+      }
+    }
+  }
+#undef ADD
+  double inv = n_seg > 0 ? 1.0 / n_seg : 0.0;
+  for (int64_t e = 0; e < ne; ++e) {
+    double b = u * fmin(N[e], lambda * sqrt(N[e])) * S[e] + u * fmin(B[e], lambda * sqrt(Q[e])) + Z[e];
+    b *= inv;
+    if (e < nt) b_table[e] = b; else b_mlp[e - nt] = b;
+  }
+  free(S); free(B); free(Q); free(Z); free(N);
+  free(f); free(mf); free(pf); free(h); free(mh); free(ph); free(sc);
+}
+
+/* ------------------------------------------------------------------------- */
 /* Proposal training targets: the plain marcher's weights w_i = T_i alpha_i  */
 /* on the uniform grid of the first (camera) segment, without surfaces, split */
 /* over n_bins equal bins of the clipped range [lo, hi] in proportion to the */

@@ -145,6 +145,13 @@ void orc_proposal_targets(const orc_field* f, int64_t n, const float* origins, c
 double orc_proposal_loss(const orc_field* p, int64_t n_seg, const float* o, const float* d,
                          const float* lohi, const float* target, int32_t n_bins,
                          double* g_table, double* g_mlp, int32_t n_threads);
+/* probabilistic tolerance (Higham and Mary) on the rounding error of an
+   implementation of orc_proposal_loss's gradient in a format of unit
+   roundoff u; K: roundings folded into one node of the chain, lambda: the
+   confidence parameter; for tests */
+void orc_proposal_grad_bound(const orc_field* p, int64_t n_seg, const float* o, const float* d,
+                             const float* lohi, const float* target, int32_t n_bins, double u, double K,
+                             double lambda, double* b_table, double* b_mlp);
 
 #ifdef __cplusplus
 }

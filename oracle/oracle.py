@@ -384,6 +384,30 @@ def proposal_loss(prop, o, d, lohi, target, grads=True, n_threads=None):
     return float(loss), gt, gm
 
 
+def proposal_grad_bound(prop, o, d, lohi, target, u=2.0 ** -24, K=64.0, lam=8.0):
+    """Per-element tolerance on the rounding error of the proposal gradient
+    computed in a format of unit roundoff u (FP32 by default), from a
+    probabilistic rounding error analysis (Higham and Mary, 2019): the final
+    sum over contributions, a running error bound of each contribution's
+    chain (K roundings per node), the rounding of the sample positions
+    carried into the trilinear weights, and the contributions that hinge on a
+    ReLU whose sign is within rounding.  An element exceeds it with
+    probability about 2 n exp(-lam^2 / 2) (n: its contributions).
+    Returns (bound_table [L, T, F], bound_mlp)."""
+    op = OField(prop)
+    o = np.ascontiguousarray(o, dtype=np.float32)
+    d = np.ascontiguousarray(d, dtype=np.float32)
+    lohi = np.ascontiguousarray(lohi, dtype=np.float32)
+    target = np.ascontiguousarray(target, dtype=np.float32)
+    n_seg, n_bins = target.shape
+    bt = np.zeros(prop.table.shape)
+    bm = np.zeros(prop.mlp.shape)
+    lib().orc_proposal_grad_bound(op.ptr, C.c_int64(n_seg), _p(o), _p(d), _p(lohi), _p(target),
+                                  C.c_int32(n_bins), C.c_double(u), C.c_double(K), C.c_double(lam),
+                                  _p(bt), _p(bm))
+    return bt, bm
+
+
 def scatter(mat, d, n, u):
     """One BSDF sample: returns (new direction, offset side, weight rgb, R)."""
     mat = np.ascontiguousarray(mat, dtype=np.float32)

@@ -46,28 +46,37 @@ def test_targets_match_oracle():
     np.testing.assert_allclose(host(tgt).sum(1), rt.sum(1), rtol=1e-3, atol=1e-5)
 
 
-def test_proposal_gradient_matches_oracle():
-    """GPU loss and gradient (FP32, atomics) against the FP64 analytic
+# bins per segment: the trained proposal's 32, a full 64-lane wave, and a
+# count that leaves part of the last matrix-core K group empty
+@pytest.mark.parametrize("n_bins,n", [(32, 512), (64, 3000), (20, 3000)])
+def test_proposal_gradient_matches_oracle(n_bins, n):
+    """GPU loss and gradient (FP32; MLP weight gradient accumulated on the
+    matrix cores, table gradient by atomics) against the FP64 analytic
     gradient, which is itself pinned to finite differences on the CPU."""
     M = mr()
     prop = sg.make_proposal(table_amp=0.3)
-    rng = np.random.default_rng(302)
-    n = 512
+    rng = np.random.default_rng(302 + n_bins)
     o, d = sg.random_rays(n, seed=303)
     lohi = np.stack([rng.uniform(1.4, 1.8, n), rng.uniform(3.0, 3.4, n)], 1).astype(np.float32)
-    tgt = (rng.dirichlet(np.ones(32) * 0.3, size=n) * 0.9).astype(np.float32)
+    tgt = (rng.dirichlet(np.ones(n_bins) * 0.3, size=n) * 0.9).astype(np.float32)
     P = M.Field(prop, table_dtype=M.MR_F16)
     loss = torch.zeros(1, device="cuda")
     gt = torch.zeros(prop.table.size, device="cuda")
     gm = torch.zeros(prop.mlp.size, device="cuda")
-    M.mr_proposal_grad(P.handle, n, dev(o), dev(d), dev(lohi), dev(tgt), 32, loss, gt, gm)
+    M.mr_proposal_grad(P.handle, n, dev(o), dev(d), dev(lohi), dev(tgt), n_bins, loss, gt, gm)
     rl, rgt, rgm = orc.proposal_loss(prop, o, d, lohi, tgt)
     assert float(host(loss)[0]) == pytest.approx(rl, rel=1e-4)
-    gmh = host(gm)
-    np.testing.assert_allclose(gmh, rgm, rtol=2e-3, atol=2e-5 * np.abs(rgm).max())
-    gth = host(gt).reshape(prop.table.shape)
-    scale = np.abs(rgt).max()
-    np.testing.assert_allclose(gth, rgt, rtol=2e-3, atol=2e-5 * scale)
+    # per-element FP32 rounding tolerance of this gradient (probabilistic
+    # rounding error analysis; pinned in the oracle tests)
+    bt, bm = orc.proposal_grad_bound(prop, o, d, lohi, tgt)
+    gmh = host(gm).astype(np.float64)
+    gth = host(gt).reshape(prop.table.shape).astype(np.float64)
+    for name, got, ref, tol in (("MLP", gmh, rgm, bm), ("table", gth, rgt, bt)):
+        err = np.abs(got - ref)
+        bad = np.flatnonzero(err > tol)
+        print(f"{name} gradient: largest error / rounding bound {np.max(err / np.maximum(tol, 1e-300)):.3f}")
+        assert bad.size == 0, (f"{name} gradient: {bad.size} elements beyond the rounding bound, e.g. "
+                               f"{[(int(i), got.flat[i], ref.flat[i], tol.flat[i]) for i in bad[:4]]}")
     assert (np.abs(rgt) > 0).sum() > 1000
 
 

@@ -739,6 +739,49 @@ def test_proposal_gradient_finite_differences():
         assert fd == pytest.approx(gm[k], rel=2e-2, abs=1e-7)
 
 
+def test_proposal_gradient_rounding_bound():
+    """The per-element FP32 tolerance of the proposal gradient (the GPU parity
+    tolerance) (a) covers the change of the exact gradient when every input of
+    the chain moves by one FP32 ulp, with random sign: ray origins, directions,
+    segment ranges, table entries and weights, which includes the position
+    rounding carried into the trilinear weights; (b) stays a small fraction of
+    the gradient, so an O(1) error in any term (the chain's partials, a lost
+    contribution) still exceeds it; (c) grows with the unit roundoff."""
+    prop = sg.make_proposal(table_amp=0.3)
+    o, d, lohi, tgt = _prop_batch(200, 41)
+    lohi = lohi + np.random.default_rng(43).uniform(-0.2, 0.2, lohi.shape).astype(np.float32)
+    _, gt, gm = orc.proposal_loss(prop, o, d, lohi, tgt)
+    bt, bm = orc.proposal_grad_bound(prop, o, d, lohi, tgt)
+    rng = np.random.default_rng(42)
+
+    def nudge(a):
+        a = np.asarray(a, np.float32)
+        up = rng.random(a.shape) < 0.5
+        return np.where(up, np.nextafter(a, np.float32(np.inf)), np.nextafter(a, np.float32(-np.inf)))
+
+    p2 = copy.deepcopy(prop)
+    p2.table = nudge(prop.table)
+    p2.mlp = nudge(prop.mlp)
+    _, gt2, gm2 = orc.proposal_loss(p2, nudge(o), nudge(d), nudge(lohi), tgt)
+    # one ulp is 2^-23 of the value at most: the tolerance for that unit
+    bt_ulp, bm_ulp = orc.proposal_grad_bound(prop, o, d, lohi, tgt, u=2.0 ** -23)
+    assert (np.abs(gt2 - gt) <= bt_ulp).all()
+    assert (np.abs(gm2 - gm) <= bm_ulp).all()
+    # the nudge is felt: it moves a share of the table gradient by more than
+    # a hundredth of the tolerance
+    assert (np.abs(gt2 - gt) > 0.01 * bt_ulp).mean() > 0.05
+    nz = np.abs(gt) > 0
+    assert np.median(bt[nz] / np.abs(gt[nz])) < 0.03
+    assert np.median(bm / np.abs(gm)) < 0.03
+    # one segment's contribution left out exceeds the tolerance somewhere
+    _, gt1, gm1 = orc.proposal_loss(prop, o[1:], d[1:], lohi[1:], tgt[1:])
+    n = len(o)
+    assert (np.abs(gt1 * (n - 1) / n - gt) > bt).any()
+    assert (np.abs(gm1 * (n - 1) / n - gm) > bm).any()
+    bt2, bm2 = orc.proposal_grad_bound(prop, o, d, lohi, tgt, u=2.0 ** -11)
+    assert (bt2 >= bt).all() and (bm2 > bm).all()
+
+
 def test_proposal_loss_zero_when_proposal_dominates():
     prop = sg.make_proposal(table_amp=0.3)
     o, d, lohi, tgt = _prop_batch(4, 23)
