@@ -511,6 +511,15 @@ __global__ __launch_bounds__(256) void k_prop_targets(FieldView F, const TabT* _
 // block and added to the global gradient once per block: every sample hits
 // that level, and the samples of one segment share most of its corners.
 constexpr int kPropL0Lds = 2 * 17 * 17 * 17;
+// The MLP has no biases and h_i = sum_c W1[i][c] f_c, so both weight
+// gradients follow from one 16 x 10 matrix per batch,
+//   M[i][c] = sum_s dz(s) [h_i(s) > 0] f_c(s):
+//   dL/dW1[i][c] = W2[i] M[i][c],   dL/dW2[i] = sum_c W1[i][c] M[i][c].
+// Each wave accumulates M on the matrix cores over the segments it takes
+// (K = the 64 bins of a segment, four per step); the per-lane factors go
+// through a per-wave LDS stage whose row strides (17, 11) keep both the
+// row-wise writes and the column-wise operand reads free of bank conflicts.
+constexpr int kStA = 17, kStF = 11, kStageWave = 64 * (kStA + kStF);
 
 __global__ __launch_bounds__(256) void k_prop_grad(FieldView P, const float* __restrict__ table,
                                                    const float* __restrict__ mlp, int64_t n,
@@ -519,20 +528,22 @@ __global__ __launch_bounds__(256) void k_prop_grad(FieldView P, const float* __r
                                                    int n_bins, float inv_n, float* __restrict__ g_table,
                                                    float* __restrict__ g_mlp, float* __restrict__ loss) {
   __shared__ float sW[kPropMlp];
-  __shared__ float sG[kPropMlp];
+  __shared__ float sM[16 * 16];
   __shared__ float sL0[kPropL0Lds];
-  for (int i = threadIdx.x; i < kPropMlp; i += blockDim.x) {
-    sW[i] = mlp[i];
-    sG[i] = 0.0f;
-  }
+  __shared__ float sStage[4 * kStageWave];
+  for (int i = threadIdx.x; i < kPropMlp; i += blockDim.x) sW[i] = mlp[i];
+  for (int i = threadIdx.x; i < 16 * 16; i += blockDim.x) sM[i] = 0.0f;
   const int n1 = P.res[0] + 1;
   const int n_l0 = (P.dense_mask & 1u) && 2 * n1 * n1 * n1 <= kPropL0Lds ? 2 * n1 * n1 * n1 : 0;
   for (int i = threadIdx.x; i < n_l0; i += blockDim.x) sL0[i] = 0.0f;
   __syncthreads();
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+  float* sA = sStage + (threadIdx.x >> 6) * kStageWave;
+  float* sF = sA + 64 * kStA;
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
   const size_t T = (size_t)P.table_mask + 1u;
   float wave_loss = 0.0f;
+  f4v accM = {0.0f, 0.0f, 0.0f, 0.0f};
   for (int64_t s = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); s < n; s += waves) {
     const float lo = lohi[2 * s], hi = lohi[2 * s + 1];
     if (!(hi > lo)) continue;
@@ -563,24 +574,36 @@ __global__ __launch_bounds__(256) void k_prop_grad(FieldView P, const float* __r
     const float gw = gl * w;
     const float incl_gw = wscan_add(gw, lane);
     const float suffix = __shfl(incl_gw, 63, 64) - incl_gw;
-    if (!act) continue;
-    const float dsig = gl * Tj * D * expf(-sigma * D) - D * suffix;
-    const float dz = dsig / (1.0f + expf(-(z + P.density_offset)));
+    float dz = 0.0f;
+    if (act) {
+      const float dsig = gl * Tj * D * expf(-sigma * D) - D * suffix;
+      dz = dsig / (1.0f + expf(-(z + P.density_offset)));
+    }
+    if (__ballot(dz != 0.0f) == 0ull) continue;
+    // M += A B with A[i][s] = dz(s) [h_i(s) > 0], B[s][c] = f_c(s)
+#pragma unroll
+    for (int i = 0; i < kPropHidden; ++i) sA[lane * kStA + i] = (dz != 0.0f && hpre[i] > 0.0f) ? dz : 0.0f;
+#pragma unroll
+    for (int c = 0; c < kPropIn; ++c) sF[lane * kStF + c] = dz != 0.0f ? feat[c] : 0.0f;
+    wave_lds_sync();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int r = 16 * g + t;   // bin of K row g in step t
+      const float a = sA[r * kStA + j];
+      const float b = j < kPropIn ? sF[r * kStF + j] : 0.0f;
+      accM = mma(a, b, accM);
+    }
+    wave_lds_sync();
     if (dz == 0.0f) continue;
     float df[kPropIn];
 #pragma unroll
     for (int c = 0; c < kPropIn; ++c) df[c] = 0.0f;
 #pragma unroll
     for (int i = 0; i < kPropHidden; ++i) {
-      const float a = fmaxf(hpre[i], 0.0f);
-      atomicAdd(&sG[kPropIn * kPropHidden + i], dz * a);
       if (hpre[i] > 0.0f) {
         const float dh = dz * sW[kPropIn * kPropHidden + i];
 #pragma unroll
-        for (int c = 0; c < kPropIn; ++c) {
-          atomicAdd(&sG[i * kPropIn + c], dh * feat[c]);
-          df[c] += dh * sW[i * kPropIn + c];
-        }
+        for (int c = 0; c < kPropIn; ++c) df[c] += dh * sW[i * kPropIn + c];
       }
     }
     // scatter to the table entries of the 8 corners of every level
@@ -591,19 +614,41 @@ __global__ __launch_bounds__(256) void k_prop_grad(FieldView P, const float* __r
       uint32_t idx[8];
       float wc[8];
       level_corners(P, l, xh, yh, zh, idx, wc);
-      float* gt = (l == 0 && n_l0) ? sL0 : g_table + (size_t)l * T * 2;
+      if (l == 0 && n_l0) {
+        // two branches rather than one pointer, so these stay LDS atomics
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        atomicAdd(gt + 2 * (size_t)idx[c], wc[c] * df[2 * l]);
-        atomicAdd(gt + 2 * (size_t)idx[c] + 1, wc[c] * df[2 * l + 1]);
+        for (int c = 0; c < 8; ++c) {
+          atomicAdd(sL0 + 2 * idx[c], wc[c] * df[0]);
+          atomicAdd(sL0 + 2 * idx[c] + 1, wc[c] * df[1]);
+        }
+      } else {
+        float* gt = g_table + (size_t)l * T * 2;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          atomicAdd(gt + 2 * (size_t)idx[c], wc[c] * df[2 * l]);
+          atomicAdd(gt + 2 * (size_t)idx[c] + 1, wc[c] * df[2 * l + 1]);
+        }
       }
     }
   }
   wave_loss = wsum(wave_loss);
-  if ((threadIdx.x & 63) == 0 && wave_loss != 0.0f) atomicAdd(loss, wave_loss * inv_n);
+  if (lane == 0 && wave_loss != 0.0f) atomicAdd(loss, wave_loss * inv_n);
+  // accumulator register v of lane (g, j) holds M[4 g + v][j]
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    if (j < kPropIn && accM[v] != 0.0f) atomicAdd(&sM[(4 * g + v) * 16 + j], accM[v]);
   __syncthreads();
-  for (int i = threadIdx.x; i < kPropMlp; i += blockDim.x)
-    if (sG[i] != 0.0f) atomicAdd(g_mlp + i, sG[i]);
+  for (int i = threadIdx.x; i < kPropMlp; i += blockDim.x) {
+    float gv = 0.0f;
+    if (i < kPropIn * kPropHidden) {
+      gv = sW[kPropIn * kPropHidden + i / kPropIn] * sM[(i / kPropIn) * 16 + i % kPropIn];
+    } else {
+      const int u = i - kPropIn * kPropHidden;
+#pragma unroll
+      for (int c = 0; c < kPropIn; ++c) gv += sW[u * kPropIn + c] * sM[u * 16 + c];
+    }
+    if (gv != 0.0f) atomicAdd(g_mlp + i, gv);
+  }
   for (int i = threadIdx.x; i < n_l0; i += blockDim.x)
     if (sL0[i] != 0.0f) atomicAdd(g_table + i, sL0[i]);
 }
