@@ -46,9 +46,10 @@ def test_targets_match_oracle():
     np.testing.assert_allclose(host(tgt).sum(1), rt.sum(1), rtol=1e-3, atol=1e-5)
 
 
-# bins per segment: the trained proposal's 32, a full 64-lane wave, and a
-# count that leaves part of the last matrix-core K group empty
-@pytest.mark.parametrize("n_bins,n", [(32, 512), (64, 3000), (20, 3000)])
+# bins per segment: the trained proposal's 32 (also at the training batch of
+# 2^14 segments, in the launch shape the training step uses), a full 64-lane
+# wave, and a count that leaves part of the last matrix-core K group empty
+@pytest.mark.parametrize("n_bins,n", [(32, 512), (32, 1 << 14), (64, 3000), (20, 3000)])
 def test_proposal_gradient_matches_oracle(n_bins, n):
     """GPU loss and gradient (FP32; MLP weight gradient accumulated on the
     matrix cores, table gradient by atomics) against the FP64 analytic
