@@ -33,8 +33,10 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X published dense BF16 matrix peak
 PROPOSAL_MACS = 10 * 16 + 16 * 1        # proposal MLP 10 -> 16 -> 1 per proposal sample
 
 
-# Sources that make up the march kernel: HBM traffic taken with rocprofv3
-# counters is reported only while they are unchanged since the counters were taken.
+# Sources that make up the march kernels and their launches: the fabric traffic
+# taken with rocprofv3 counters is reported only while they are unchanged since
+# the counters were taken.  (The public header only declares the C ABI; the
+# march takes nothing from it but enum constants.)
 MARCH_SOURCES = ["march_mfma.hip", "mr_mfma.h", "mr_field_kernels.h", "mr_device.h", "mr_render.h",
                  "mr_common.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_march_mid_fabric_traffic.md")
@@ -42,7 +44,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_march_mid_fabric_traffic.md")
 
 def march_sources_sha256():
     h = hashlib.sha256()
-    for f in MARCH_SOURCES + ["../../include/meshrf.h"]:
+    for f in MARCH_SOURCES:
         with open(os.path.join(ROOT, "paper_2309_04581_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -98,6 +100,19 @@ def gather_probe(M, sg, F_mid):
         ms, loads = M.mr_probe_gather(F.handle, 1 << 28, 12, sink)
         out[name] = {"GB_per_s": round(loads * eb / (ms / 1e3) / 1e9, 1),
                      "Gloads_per_s": round(loads / (ms / 1e3) / 1e9, 2), "entry_bytes": eb}
+    # the same loads confined to a region of the mid table, shared by every die
+    # or one region per die (blocks go to the eight dies in turn): the rate as
+    # a function of what each die's L2 has to hold
+    reg = {}
+    for lg in (17, 19, 20, 21):
+        for per_die in (False, True):
+            if per_die and lg + 3 > 23:
+                continue
+            M.mr_probe_gather_region(F_mid.handle, lg, per_die, 1 << 25, 13, sink)
+            ms, loads = M.mr_probe_gather_region(F_mid.handle, lg, per_die, 1 << 27, 14, sink)
+            key = f"{(8 << lg) >> 20}MiB_{'per_die' if per_die else 'shared'}"
+            reg[key] = round(loads / (ms / 1e3) / 1e9, 2)
+    out["mid_fp32_region_Gloads_per_s"] = reg
     return out
 
 
@@ -882,6 +897,12 @@ def main():
     bnc_ms = stage_ms[1] / args.steps
     bnc_samples = samples - cam_samples
 
+    # random single-entry loads from this table (every load a line lookup, eight
+    # independent ones per lane): the rate at which the memory side serves
+    # incoherent 128-byte lines, the ceiling of a march whose gathers share no line
+    probe = gather_probe(M, sg, F)
+    line_ceiling = probe["mid_fp32_64MiB"]["Gloads_per_s"]
+
     def seg_roof(ms, ns, fabric):
         fl = 2.0 * field_macs(sc.field) * ns / (ms / 1e3) / 1e12
         out = {"ms_per_step": round(ms, 3), "samples": ns, "ns_per_sample": round(ms * 1e6 / max(1, ns), 4),
@@ -891,6 +912,11 @@ def main():
             out["fabric_GB_per_s"] = round(fabric / (ms / 1e3) / 1e9, 1)
             out["fabric_frac_of_hbm_peak"] = round(fabric / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
             out["fabric_bytes_per_sample"] = round(fabric / max(1, ns), 1)
+            # the march's reads are 128-byte requests (profiles/): lines per second
+            # against the random-line ceiling measured on the same table
+            lines = fabric / 128.0 / (ms / 1e3) / 1e9
+            out["fabric_lines_G_per_s"] = round(lines, 2)
+            out["frac_of_random_line_ceiling"] = round(lines / line_ceiling, 4)
         return out
 
     line = {
@@ -922,7 +948,6 @@ def main():
         "gather": {"achieved": round(gbs, 1), "unit": "GB/s", "peak_hbm": HBM_PEAK_GBS,
                    "bytes_per_sample": gather_bytes(sc.field)},
     }
-    probe = gather_probe(M, sg, F)
     line["gather"]["probe_random_gather"] = probe
     # the march's gathers are coherent (packets, consecutive samples); these are
     # its rates relative to fully random loads from the same table and from an

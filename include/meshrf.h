@@ -476,6 +476,17 @@ mr_status mr_profile_read(double* ms /*[4]*/, int64_t* launches /*[4]*/);
 mr_status mr_probe_gather(const mr_field* f, int64_t n_loads, uint32_t seed, uint32_t* sink, float* ms_out,
                           int64_t* loads_out, void* stream);
 
+/* The same probe confined to 2^log2_region table entries (8 <= log2_region;
+ * the region must lie in the power-of-two prefix of the table).  per_die = 0:
+ * every block reads entries [0, 2^log2_region); per_die != 0: block b reads
+ * region (b mod 8) of that size, so with workgroups dealt to the eight dies
+ * in turn each die reads a region of its own (8 regions must fit).  Gives the
+ * gather rate as a function of the working set of each die's L2.  Same
+ * outputs and errors as mr_probe_gather, plus MR_ERR_INVALID_ARG for a region
+ * that does not fit. */
+mr_status mr_probe_gather_region(const mr_field* f, int32_t log2_region, int32_t per_die, int64_t n_loads,
+                                 uint32_t seed, uint32_t* sink, float* ms_out, int64_t* loads_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,7 @@ EXPORTED = [
     "mr_autotune_candidates", "mr_autotune_render", "mr_autotune_search", "mr_camera_bounce_limits", "mr_field_build_occupancy", "mr_field_create",
     "mr_field_destroy", "mr_field_params", "mr_field_query", "mr_field_set_pose", "mr_graph_destroy",
     "mr_graph_launch", "mr_last_error", "mr_mesh_build_bvh", "mr_mesh_closest_hit", "mr_mesh_destroy",
-    "mr_mesh_info", "mr_mesh_refit", "mr_probe_gather", "mr_profile_enable", "mr_profile_read",
+    "mr_mesh_info", "mr_mesh_refit", "mr_probe_gather", "mr_probe_gather_region", "mr_profile_enable", "mr_profile_read",
     "mr_proposal_grad", "mr_proposal_targets", "mr_proposal_train_step", "mr_rays_from_cameras", "mr_render",
     "mr_render_fields", "mr_render_fields_workspace_size", "mr_render_graph_create",
     "mr_render_noalloc", "mr_render_status",
@@ -461,6 +461,17 @@ def mr_probe_gather(field, n_loads, seed, sink, stream=None):
     loads = C.c_int64()
     _check(lib().mr_probe_gather(field, C.c_int64(n_loads), C.c_uint32(seed), _ptr(sink), C.byref(ms),
                                  C.byref(loads), _stream(stream)))
+    return ms.value, loads.value
+
+
+def mr_probe_gather_region(field, log2_region, per_die, n_loads, seed, sink, stream=None):
+    """The random-gather probe confined to 2^log2_region entries, shared by
+    every block or one region per die: returns (ms, loads issued)."""
+    ms = C.c_float()
+    loads = C.c_int64()
+    _check(lib().mr_probe_gather_region(field, C.c_int32(log2_region), C.c_int32(1 if per_die else 0),
+                                        C.c_int64(n_loads), C.c_uint32(seed), _ptr(sink), C.byref(ms),
+                                        C.byref(loads), _stream(stream)))
     return ms.value, loads.value
 
 

@@ -150,3 +150,14 @@ def test_gather_probe_runs_and_validates():
     assert ms > 0 and (1 << 21) <= loads <= (1 << 23)
     with pytest.raises(M.MrError):
         M.mr_probe_gather(F.handle, 4, 3, sink)
+    # confined to a region, shared or one per die; regions beyond the table refused
+    lg = int(np.floor(np.log2(F.src.table.shape[0] * F.src.table.shape[1])))
+    for per_die in (False, True):
+        ms, loads = M.mr_probe_gather_region(F.handle, lg - 3, per_die, 1 << 22, 3, sink)
+        assert ms > 0 and (1 << 21) <= loads <= (1 << 23)
+    with pytest.raises(M.MrError):
+        M.mr_probe_gather_region(F.handle, lg - 2, True, 1 << 22, 3, sink)
+    with pytest.raises(M.MrError):
+        M.mr_probe_gather_region(F.handle, lg + 1, False, 1 << 22, 3, sink)
+    with pytest.raises(M.MrError):
+        M.mr_probe_gather_region(F.handle, 7, False, 1 << 22, 3, sink)
