@@ -82,6 +82,15 @@ def field_macs(f):
     return macs
 
 
+def split_macs(f):
+    """Multiply-accumulates per sample that run on the matrix cores as FP32
+    split into three BF16 pieces (six BF16 products each): the density layers
+    and the hidden colour layers; the SH columns of colour layer 1 are a
+    per-ray FP32 product and the 3-wide output layer runs on the vector units."""
+    nfeat = f.n_levels * f.feats
+    return nfeat * f.d_hidden + f.d_hidden * f.d_out + f.d_out * f.c_hidden + (f.c_layers - 1) * f.c_hidden * f.c_hidden
+
+
 def gather_bytes(f, bytes_per_value=4):
     return f.n_levels * 8 * f.feats * bytes_per_value
 
@@ -885,6 +894,7 @@ def main():
     launches_per_step = (stage_n[1] + stage_n[3]) / args.steps
     flops_per_step = 2.0 * field_macs(sc.field) * samples
     tflops = flops_per_step / (march_ms_per_step / 1e3) / 1e12
+    bf16_tflops = 6 * 2.0 * split_macs(sc.field) * samples / (march_ms_per_step / 1e3) / 1e12
     gbs = gather_bytes(sc.field) * samples / (march_ms_per_step / 1e3) / 1e9
     # split: camera segment (k_march_pc) and bounce segments (k_march_mfma); samples of the
     # camera segment from the same render stopped at its first surface (the same samples)
@@ -905,8 +915,10 @@ def main():
 
     def seg_roof(ms, ns, fabric):
         fl = 2.0 * field_macs(sc.field) * ns / (ms / 1e3) / 1e12
+        bfl = 6 * 2.0 * split_macs(sc.field) * ns / (ms / 1e3) / 1e12
         out = {"ms_per_step": round(ms, 3), "samples": ns, "ns_per_sample": round(ms * 1e6 / max(1, ns), 4),
-               "achieved_TFLOPs": round(fl, 2), "frac_fp32_mfma": round(fl / FP32_MFMA_PEAK_TFLOPS, 4),
+               "fp32_TFLOPs": round(fl, 2), "frac_of_fp32_mfma_peak": round(fl / FP32_MFMA_PEAK_TFLOPS, 4),
+               "bf16_instruction_TFLOPs": round(bfl, 2), "frac_of_bf16_mfma_peak": round(bfl / BF16_MFMA_PEAK_TFLOPS, 4),
                "algorithmic_gather_GB_per_s": round(gather_bytes(sc.field) * ns / (ms / 1e3) / 1e9, 1)}
         if fabric is not None:
             out["fabric_GB_per_s"] = round(fabric / (ms / 1e3) / 1e9, 1)
@@ -929,18 +941,32 @@ def main():
                                "density 0.01, 256 samples/segment, 20 494 triangles, 1 point light, "
                                "8 bounces",
                    "rays": n, "samples_per_step": samples, "segments_per_step": segments,
-                   "sampler": "uniform", "precision": "fp32"},
+                   "sampler": "uniform",
+                   "precision": "fp32 (MLP products on FP32 values split into three exact BF16 pieces, FP32 "
+                                "accumulation; error against the FP64 oracle in error_vs_fp64_oracle)"},
         "segments_per_s": round(segments / (ms_step / 1e3), 1),
         "stage_ms_per_step": {"closest_hit": round(stage_ms[0] / args.steps, 3),
                               "march": round(march_ms_per_step, 3),
                               "shade": round(stage_ms[2] / args.steps, 3),
                               "note": "a second pass of the same steps with event pairs around each launch"},
-        "roofline": {"kernel": "k_march_pc (camera segment) + k_march_mfma (later segments)", "bound": "mfma", "achieved": round(tflops, 2),
-                     "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(tflops / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
+        # the march's bound: the memory side serving the hash gathers (the 64 MiB
+        # table sits in the Infinity Cache in front of HBM); achieved = the
+        # algorithmic gather bytes (16 levels x 8 corners x 2 FP32) per second
+        "roofline": {"kernel": "k_march_pc (camera segment) + k_march_mfma (later segments)", "bound": "hbm",
+                     "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "traffic_unit": "bytes per launch (L2-to-memory reads by request size + writes)",
                      "launch_ms": round(march_launch_ms, 4),
                      "launches_per_step": launches_per_step,
+                     "algorithmic_bytes_per_sample": gather_bytes(sc.field),
+                     "matrix_cores": {
+                         "instructions": "v_mfma_f32_16x16x32_bf16 / 16x16x16bf16 on FP32 operands split into "
+                                         "three exact BF16 pieces, six piece products per multiply-add, FP32 "
+                                         "accumulation",
+                         "fp32_TFLOPs": round(tflops, 2),
+                         "frac_of_fp32_mfma_peak": round(tflops / FP32_MFMA_PEAK_TFLOPS, 4),
+                         "bf16_instruction_TFLOPs": round(bf16_tflops, 2),
+                         "frac_of_bf16_mfma_peak": round(bf16_tflops / BF16_MFMA_PEAK_TFLOPS, 4)},
                      "camera_segment": dict(kernel="k_march_pc", **seg_roof(
                          cam_ms, cam_samples, measured_traffic("camera_segment_fabric_bytes"))),
                      "bounce_segments": dict(kernel="k_march_mfma", **seg_roof(

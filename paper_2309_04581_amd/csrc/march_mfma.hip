@@ -3,7 +3,7 @@
 // Quadrature of Eq. 10-11 (alpha compositing of midpoint samples on the
 // fixed interval grid, Eq. 8-9).  Each lane gathers the hash features of one
 // level group for one sample (mr_mfma.h) and the density and colour MLPs run
-// as 16x16 MFMA tiles (FP32, or BF16 with FP32 accumulation) whose 16 columns
+// as 16x16 MFMA tiles (FP32 as exact BF16 splits, or BF16; FP32 accumulation) whose 16 columns
 // are 16 samples.  Two ways to fill the columns:
 //   packets  - a wave takes 16 consecutive queue rays and steps them through
 //              the same sample index together (column j = ray j); neighbouring
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(256) void k_query_mfma(FieldView F, const TabT* __r
     }
     if (feat_out)
 #pragma unroll
-      for (int k = 0; k < LY::NF; ++k) feat_out[p * 2 * NL + frag_k(0, false, LY::NF, k, g, 0)] = fe[k];
+      for (int k = 0; k < LY::NF; ++k) feat_out[p * 2 * NL + frag_k(0, LY::NF, 0, g, k)] = fe[k];
     if (raw_out)
 #pragma unroll
       for (int v = 0; v < 4; ++v) raw_out[p * 16 + 4 * g + v] = raw[v];
@@ -521,12 +521,14 @@ namespace mr {
 std::vector<uint32_t> build_fragments(const mr_field_desc& d, const float* mlp, bool bf) {
   const int NL = d.n_levels, SH = d.sh_components, CL = d.color_hidden_layers;
   const int NF = NL / 2;
-  // K values per lane and words per lane of each layer kind (FragLayout)
-  const int KP1 = bf ? bf_kpl(0, NF) : 1, KP2 = bf ? bf_kpl(1, NF) : 1, KPC = bf ? bf_kpl(2, NF) : 1;
+  // FragLayout: BF16 fragment shape; BF16 weights one piece, FP32 weights three
+  const int NP = bf ? 1 : 3;
+  const int KP1 = bf_kpl(0, NF), KP2 = bf_kpl(1, NF), KPC = bf_kpl(2, NF);
   const int KS1 = NF / KP1, KS2 = 16 / KP2, KSC = 4 / KPC;
-  const int WL1 = bf ? KP1 / 2 : 1, WL2 = bf ? KP2 / 2 : 1, WLC = bf ? KPC / 2 : 1;
-  const int L1 = 0, L2 = L1 + 4 * KS1 * 64 * WL1, C1 = L2 + KS2 * 64 * WL2, C2 = C1 + 4 * KSC * 64 * WLC;
-  const int OUT = C2 + (CL == 2 ? 4 * KS2 * 64 * WL2 : 0), SHW = OUT + 192, TOTAL = SHW + 64 * SH;
+  const int WL1 = KP1 / 2, WL2 = KP2 / 2, WLC = KPC / 2;
+  const int P1 = 4 * KS1 * 64 * WL1, P2 = KS2 * 64 * WL2, PC = 4 * KSC * 64 * WLC, PC2 = 4 * KS2 * 64 * WL2;
+  const int L1 = 0, L2 = L1 + NP * P1, C1 = L2 + NP * P2, C2 = C1 + NP * PC;
+  const int OUT = C2 + (CL == 2 ? NP * PC2 : 0), SHW = OUT + 192, TOTAL = SHW + 64 * SH;
   std::vector<uint32_t> w(TOTAL, 0u);
   const float* W1 = mlp;
   const float* W2 = W1 + 64 * d.density_in;
@@ -538,36 +540,47 @@ std::vector<uint32_t> build_fragments(const mr_field_desc& d, const float* mlp, 
     std::memcpy(&u, &f, 4);
     return u;
   };
+  auto from_bits = [](uint32_t u) {
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+  };
   auto bf16 = [&](float f) {
     const uint32_t u = bits(f);
     return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
   };
-  auto put = [&](int base, int mt, int ks, int nks, const float* M, int in_dim, int rows, int kind) {
-    const int kp = bf ? bf_kpl(kind, NF) : 1;
-    for (int lane = 0; lane < 64; ++lane) {
-      const int g = lane / 16, row = mt * 16 + lane % 16;
-      const int slot = (mt * nks + ks) * 64 + lane;
-      if (!bf) {
-        const int k = frag_k(kind, false, NF, ks, g, 0);
-        w[base + slot] = row < rows ? bits(M[row * in_dim + k]) : 0u;
-      } else {
-        // kp bf16 values per lane, kp / 2 words, element 0 in the low half
+  // piece q of a weight: BF16 of the residual left by the pieces before it
+  auto piece = [&](float v, int q) {
+    uint32_t b = bf16(v);
+    for (int i = 0; i < q; ++i) {
+      v -= from_bits(b << 16);
+      b = bf16(v);
+    }
+    return b;
+  };
+  // one fragment of every piece: kp bf16 values per lane, kp / 2 words,
+  // element 0 in the low half; piece q at base + q * psize
+  auto put = [&](int base, int psize, int mt, int ks, int nks, const float* M, int in_dim, int rows, int kind) {
+    const int kp = bf_kpl(kind, NF);
+    for (int q = 0; q < NP; ++q)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int g = lane / 16, row = mt * 16 + lane % 16;
+        const int slot = (mt * nks + ks) * 64 + lane;
         for (int e = 0; e < kp; ++e) {
-          const int k = frag_k(kind, true, NF, ks, g, e);
-          const uint32_t v = row < rows ? bf16(M[row * in_dim + k]) : 0u;
-          w[base + (kp / 2) * slot + e / 2] |= v << (16 * (e % 2));
+          const int k = frag_k(kind, NF, ks, g, e);
+          const uint32_t v = row < rows ? piece(M[row * in_dim + k], q) : 0u;
+          w[base + q * psize + (kp / 2) * slot + e / 2] |= v << (16 * (e % 2));
         }
       }
-    }
   };
   for (int mt = 0; mt < 4; ++mt)
-    for (int ks = 0; ks < KS1; ++ks) put(L1, mt, ks, KS1, W1, d.density_in, 64, 0);
-  for (int ks = 0; ks < KS2; ++ks) put(L2, 0, ks, KS2, W2, 64, 16, 1);
+    for (int ks = 0; ks < KS1; ++ks) put(L1, P1, mt, ks, KS1, W1, d.density_in, 64, 0);
+  for (int ks = 0; ks < KS2; ++ks) put(L2, P2, 0, ks, KS2, W2, 64, 16, 1);
   for (int mt = 0; mt < 4; ++mt)
-    for (int ks = 0; ks < KSC; ++ks) put(C1, mt, ks, KSC, Wc1, d.color_in, 64, 2);
+    for (int ks = 0; ks < KSC; ++ks) put(C1, PC, mt, ks, KSC, Wc1, d.color_in, 64, 2);
   if (CL == 2)
     for (int mt = 0; mt < 4; ++mt)
-      for (int ks = 0; ks < KS2; ++ks) put(C2, mt, ks, KS2, Wc2, 64, 64, 1);
+      for (int ks = 0; ks < KS2; ++ks) put(C2, PC2, mt, ks, KS2, Wc2, 64, 64, 1);
   for (int i = 0; i < 192; ++i) w[OUT + i] = bits(Wout[i]);
   // SH columns of colour layer 1 as FP32 fragments [4 mt][SH/4][64]: lane
   // (g, j) of step ks holds row mt*16 + j, SH component 4 ks + g

@@ -3,14 +3,22 @@
 // One wave evaluates 16 samples at a time.  Lane l serves sample j = l % 16
 // and, for the hash encoding, the level group g = l / 16 (levels
 // g*NL/4 .. (g+1)*NL/4 - 1).  The features a lane gathers are exactly the
-// B-operand values it owns in v_mfma_f32_16x16x4f32 (one K value per lane),
-// v_mfma_f32_16x16x32_bf16 (eight K values per lane, lane l holding
-// k = 8 (l / 16) .. 8 (l / 16) + 7) or, where a layer's K is 16,
-// v_mfma_f32_16x16x16bf16 (four K values per lane) for the product
+// B-operand values it owns in v_mfma_f32_16x16x32_bf16 (eight K values per
+// lane, lane l holding k = 8 (l / 16) .. 8 (l / 16) + 7) or, where a layer's
+// K is 16, v_mfma_f32_16x16x16bf16 (four K values per lane) for the product
 // W (M = output rows) x X^T (N = 16 samples).  A 16x16 accumulator leaves
 // row 4g + v, column j in register v of lane l, which is again the B layout of
 // the next layer up to a fixed permutation of K; the weight fragments staged
 // in LDS are written in that permuted order once, on the host.
+//
+// Two MLP precisions share that shape.  BF16: operands rounded to BF16, FP32
+// accumulation.  FP32: every FP32 weight and input is held as three BF16
+// pieces that add up to it exactly, and six of the nine piece products are
+// accumulated in FP32; what is dropped is at most 2^-26 of each product,
+// below the 2^-24 rounding of an FP32 multiply, so the result has FP32
+// accuracy at the BF16 instruction rate (six BF16 instructions in place of
+// the eight v_mfma_f32_16x16x4f32 a K of 32 takes, each of those twice as
+// long).  The per-ray SH product (sh_rows) stays on v_mfma_f32_16x16x4f32.
 #pragma once
 #include "mr_device.h"
 
@@ -25,31 +33,39 @@ typedef short s4v __attribute__((ext_vector_type(4)));
 // where a step can take 32 K values, 4 (16x16x16) where the layer's K is 16.
 __host__ __device__ constexpr int bf_kpl(int kind, int nf) { return kind == 2 ? 4 : (kind == 0 && nf % 8 ? 4 : 8); }
 
-// Fragment layout sizes (in 32-bit words) for a field shape.
+// Fragment layout sizes (in 32-bit words) for a field shape.  Both MLP
+// precisions use the BF16 fragment shape; BF16 weights are one piece, FP32
+// weights three BF16 pieces w = w0 + w1 + w2 (exact: each residual has at
+// most 16, then 8, significant bits), stored one after the other per layer.
 template <int NL, int SH, int CL, bool BF>
 struct FragLayout {
   static constexpr int NF = NL / 2;                          // features per lane (2 per level, NL/4 levels)
-  static constexpr int KP1 = BF ? bf_kpl(0, NF) : 1;         // K values per lane, density layer 1
-  static constexpr int KP2 = BF ? bf_kpl(1, NF) : 1;         // over 64 hidden units
-  static constexpr int KPC = BF ? bf_kpl(2, NF) : 1;         // over the 16 raw outputs
+  static constexpr int NP = BF ? 1 : 3;                      // BF16 pieces per weight
+  static constexpr int KP1 = bf_kpl(0, NF);                  // K values per lane, density layer 1
+  static constexpr int KP2 = bf_kpl(1, NF);                  // over 64 hidden units
+  static constexpr int KPC = bf_kpl(2, NF);                  // over the 16 raw outputs
   static constexpr int KS1 = NF / KP1;                       // K steps, density layer 1
   static constexpr int KS2 = 16 / KP2;                       // K steps over 64 hidden units
   static constexpr int KSC = 4 / KPC;                        // K steps over the 16 raw outputs
-  static constexpr int W1 = BF ? KP1 / 2 : 1;                // words per lane per fragment
-  static constexpr int W2 = BF ? KP2 / 2 : 1;
-  static constexpr int WC = BF ? KPC / 2 : 1;
-  static constexpr int L1 = 0;                               // [4 mt][KS1] fragments
-  static constexpr int L2 = L1 + 4 * KS1 * 64 * W1;          // [KS2]
-  static constexpr int C1 = L2 + KS2 * 64 * W2;              // [4 mt][KSC]
-  static constexpr int C2 = C1 + 4 * KSC * 64 * WC;          // [4 mt][KS2] (two hidden colour layers)
-  static constexpr int OUT = C2 + (CL == 2 ? 4 * KS2 * 64 * W2 : 0);  // FP32 [3][64]
+  static constexpr int W1 = KP1 / 2;                         // words per lane per fragment
+  static constexpr int W2 = KP2 / 2;
+  static constexpr int WC = KPC / 2;
+  static constexpr int P1 = 4 * KS1 * 64 * W1;               // words of one piece of each layer
+  static constexpr int P2 = KS2 * 64 * W2;
+  static constexpr int PC = 4 * KSC * 64 * WC;
+  static constexpr int PC2 = 4 * KS2 * 64 * W2;
+  static constexpr int L1 = 0;                               // [piece][4 mt][KS1] fragments
+  static constexpr int L2 = L1 + NP * P1;                    // [piece][KS2]
+  static constexpr int C1 = L2 + NP * P2;                    // [piece][4 mt][KSC]
+  static constexpr int C2 = C1 + NP * PC;                    // [piece][4 mt][KS2] (two hidden colour layers)
+  static constexpr int OUT = C2 + (CL == 2 ? NP * PC2 : 0);  // FP32 [3][64]
   static constexpr int SHW = OUT + 192;                      // FP32 [4 mt][SH/4][64]: SH columns of colour layer 1
   static constexpr int TOTAL = SHW + 64 * SH;
 };
 
 // K index carried by (step ks, lane group g, element e) for each layer kind.
-__host__ __device__ inline int frag_k(int kind, bool bf, int nf, int ks, int g, int e) {
-  const int kp = bf ? bf_kpl(kind, nf) : 1;
+__host__ __device__ inline int frag_k(int kind, int nf, int ks, int g, int e) {
+  const int kp = bf_kpl(kind, nf);
   if (kind == 0) {
     // lane group g holds levels g, g + 4, g + 8, ... (register r: level 4 (r / 2) + g, feature r % 2)
     const int r = kp * ks + e;
@@ -92,6 +108,40 @@ __device__ __forceinline__ uint2 pack_bf16(float a, float b, float c, float d) {
 __device__ __forceinline__ uint4 pack_bf16(const f4v& lo, const f4v& hi) {
   return make_uint4(pack2_bf16(lo[0], lo[1]), pack2_bf16(lo[2], lo[3]), pack2_bf16(hi[0], hi[1]),
                     pack2_bf16(hi[2], hi[3]));
+}
+
+// FP32 values as three BF16 pieces, x = x0 + x1 + x2 exactly (each step
+// rounds to nearest even, and a residual has at most 16, then 8, significant
+// bits).  A product of two split values keeps the six piece products down to
+// 2^-16 of its size and drops at most 2^-26 of it, under the 2^-24 rounding
+// of an FP32 product; the matrix cores form each BF16 product exactly and sum
+// in FP32 (the bf16x6 scheme of Henry, Tang and Heinecke, ARITH 2019).
+__device__ __forceinline__ void split3(float a, float b, uint32_t& p0, uint32_t& p1, uint32_t& p2) {
+  p0 = pack2_bf16(a, b);
+  const float ra = a - __uint_as_float(p0 << 16), rb = b - __uint_as_float(p0 & 0xFFFF0000u);
+  p1 = pack2_bf16(ra, rb);
+  p2 = pack2_bf16(ra - __uint_as_float(p1 << 16), rb - __uint_as_float(p1 & 0xFFFF0000u));
+}
+__device__ __forceinline__ void split3(float a, float b, float c, float d, uint2& p0, uint2& p1, uint2& p2) {
+  split3(a, b, p0.x, p1.x, p2.x);
+  split3(c, d, p0.y, p1.y, p2.y);
+}
+__device__ __forceinline__ void split3(const f4v& lo, const f4v& hi, uint4& p0, uint4& p1, uint4& p2) {
+  split3(lo[0], lo[1], p0.x, p1.x, p2.x);
+  split3(lo[2], lo[3], p0.y, p1.y, p2.y);
+  split3(hi[0], hi[1], p0.z, p1.z, p2.z);
+  split3(hi[2], hi[3], p0.w, p1.w, p2.w);
+}
+// acc + W X over the six piece products of order <= 2, smallest first
+template <typename V>
+__device__ __forceinline__ f4v mma6(const V& w0, const V& w1, const V& w2, const V& x0, const V& x1, const V& x2,
+                                    f4v acc) {
+  acc = mma(w0, x2, acc);
+  acc = mma(w2, x0, acc);
+  acc = mma(w1, x1, acc);
+  acc = mma(w0, x1, acc);
+  acc = mma(w1, x0, acc);
+  return mma(w0, x0, acc);
 }
 
 // ReLU on the bit pattern: positive floats order like positive integers and
@@ -167,50 +217,66 @@ __device__ __forceinline__ void mlp_tile(const uint32_t* __restrict__ W, const f
   const f4v zero = {0.0f, 0.0f, 0.0f, 0.0f};
   // density layer 1: 64 hidden x 16 samples
   f4v h[4] = {zero, zero, zero, zero};
-  if constexpr (!BF) {
-    const float* Wf = reinterpret_cast<const float*>(W);
-#pragma unroll
-    for (int ks = 0; ks < LY::KS1; ++ks)
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt) h[mt] = mma(Wf[LY::L1 + (mt * LY::KS1 + ks) * 64 + lane], fe[ks], h[mt]);
-  } else if constexpr (LY::KP1 == 8) {
+  if constexpr (LY::KP1 == 8) {
     const uint4* Wb = reinterpret_cast<const uint4*>(W);
 #pragma unroll
     for (int ks = 0; ks < LY::KS1; ++ks) {
       const f4v lo = {fe[8 * ks], fe[8 * ks + 1], fe[8 * ks + 2], fe[8 * ks + 3]};
       const f4v hi = {fe[8 * ks + 4], fe[8 * ks + 5], fe[8 * ks + 6], fe[8 * ks + 7]};
-      const uint4 b = pack_bf16(lo, hi);
+      if constexpr (BF) {
+        const uint4 b = pack_bf16(lo, hi);
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt) h[mt] = mma(Wb[LY::L1 / 4 + (mt * LY::KS1 + ks) * 64 + lane], b, h[mt]);
+        for (int mt = 0; mt < 4; ++mt) h[mt] = mma(Wb[LY::L1 / 4 + (mt * LY::KS1 + ks) * 64 + lane], b, h[mt]);
+      } else {
+        uint4 x0, x1, x2;
+        split3(lo, hi, x0, x1, x2);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+          const int o = LY::L1 / 4 + (mt * LY::KS1 + ks) * 64 + lane;
+          h[mt] = mma6(Wb[o], Wb[o + LY::P1 / 4], Wb[o + LY::P1 / 2], x0, x1, x2, h[mt]);
+        }
+      }
     }
   } else {
     const uint2* Wb = reinterpret_cast<const uint2*>(W);
 #pragma unroll
     for (int ks = 0; ks < LY::KS1; ++ks) {
-      const uint2 b = pack_bf16(fe[4 * ks], fe[4 * ks + 1], fe[4 * ks + 2], fe[4 * ks + 3]);
+      if constexpr (BF) {
+        const uint2 b = pack_bf16(fe[4 * ks], fe[4 * ks + 1], fe[4 * ks + 2], fe[4 * ks + 3]);
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt) h[mt] = mma(Wb[LY::L1 / 2 + (mt * LY::KS1 + ks) * 64 + lane], b, h[mt]);
+        for (int mt = 0; mt < 4; ++mt) h[mt] = mma(Wb[LY::L1 / 2 + (mt * LY::KS1 + ks) * 64 + lane], b, h[mt]);
+      } else {
+        uint2 x0, x1, x2;
+        split3(fe[4 * ks], fe[4 * ks + 1], fe[4 * ks + 2], fe[4 * ks + 3], x0, x1, x2);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+          const int o = LY::L1 / 2 + (mt * LY::KS1 + ks) * 64 + lane;
+          h[mt] = mma6(Wb[o], Wb[o + LY::P1 / 2], Wb[o + LY::P1], x0, x1, x2, h[mt]);
+        }
+      }
     }
   }
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
     for (int v = 0; v < 4; ++v) h[mt][v] = relu(h[mt][v]);
-  // density layer 2: 16 raw outputs
-  // four independent accumulator chains (one per hidden tile), summed at the end
-  f4v rp[4] = {zero, zero, zero, zero};
-  if constexpr (!BF) {
-    const float* Wf = reinterpret_cast<const float*>(W);
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt) rp[mt] = mma(Wf[LY::L2 + (mt * 4 + v) * 64 + lane], h[mt][v], rp[mt]);
-  } else {
+  // density layer 2: 16 raw outputs, two K steps of 32 hidden units
+  f4v rp[2] = {zero, zero};
+  {
     const uint4* Wb = reinterpret_cast<const uint4*>(W);
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) rp[ks] = mma(Wb[LY::L2 / 4 + ks * 64 + lane], pack_bf16(h[2 * ks], h[2 * ks + 1]), rp[ks]);
+    for (int ks = 0; ks < 2; ++ks) {
+      const int o = LY::L2 / 4 + ks * 64 + lane;
+      if constexpr (BF) {
+        rp[ks] = mma(Wb[o], pack_bf16(h[2 * ks], h[2 * ks + 1]), rp[ks]);
+      } else {
+        uint4 x0, x1, x2;
+        split3(h[2 * ks], h[2 * ks + 1], x0, x1, x2);
+        rp[ks] = mma6(Wb[o], Wb[o + LY::P2 / 4], Wb[o + LY::P2 / 2], x0, x1, x2, rp[ks]);
+      }
+    }
   }
-  raw = (rp[0] + rp[1]) + (rp[2] + rp[3]);
+  raw = rp[0] + rp[1];
   sigma = softplusf(__shfl(raw[0], j, 64) + density_offset);
   // colour layer 1: SH part precomputed in u, raw part on the matrix cores
   f4v c[4];
@@ -218,17 +284,21 @@ __device__ __forceinline__ void mlp_tile(const uint32_t* __restrict__ W, const f
   for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
     for (int v = 0; v < 4; ++v) c[mt][v] = u[mt][v];
-  if constexpr (!BF) {
-    const float* Wf = reinterpret_cast<const float*>(W);
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt) c[mt] = mma(Wf[LY::C1 + (mt * 4 + ks) * 64 + lane], raw[ks], c[mt]);
-  } else {
+  {
     const uint2* Wb = reinterpret_cast<const uint2*>(W);
-    const uint2 b = pack_bf16(raw[0], raw[1], raw[2], raw[3]);
+    if constexpr (BF) {
+      const uint2 b = pack_bf16(raw[0], raw[1], raw[2], raw[3]);
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) c[mt] = mma(Wb[LY::C1 / 2 + mt * 64 + lane], b, c[mt]);
+      for (int mt = 0; mt < 4; ++mt) c[mt] = mma(Wb[LY::C1 / 2 + mt * 64 + lane], b, c[mt]);
+    } else {
+      uint2 x0, x1, x2;
+      split3(raw[0], raw[1], raw[2], raw[3], x0, x1, x2);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        const int o = LY::C1 / 2 + mt * 64 + lane;
+        c[mt] = mma6(Wb[o], Wb[o + LY::PC / 2], Wb[o + LY::PC], x0, x1, x2, c[mt]);
+      }
+    }
   }
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt)
@@ -236,19 +306,21 @@ __device__ __forceinline__ void mlp_tile(const uint32_t* __restrict__ W, const f
     for (int v = 0; v < 4; ++v) c[mt][v] = relu(c[mt][v]);
   if constexpr (CL == 2) {
     f4v c2[4] = {zero, zero, zero, zero};
-    if constexpr (!BF) {
-      const float* Wf = reinterpret_cast<const float*>(W);
+    const uint4* Wb = reinterpret_cast<const uint4*>(W);
 #pragma unroll
-      for (int ks = 0; ks < 16; ++ks)
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) c2[mt] = mma(Wf[LY::C2 + (mt * 16 + ks) * 64 + lane], c[ks / 4][ks % 4], c2[mt]);
-    } else {
-      const uint4* Wb = reinterpret_cast<const uint4*>(W);
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
+    for (int ks = 0; ks < 2; ++ks) {
+      if constexpr (BF) {
         const uint4 b = pack_bf16(c[2 * ks], c[2 * ks + 1]);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) c2[mt] = mma(Wb[LY::C2 / 4 + (mt * 2 + ks) * 64 + lane], b, c2[mt]);
+      } else {
+        uint4 x0, x1, x2;
+        split3(c[2 * ks], c[2 * ks + 1], x0, x1, x2);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+          const int o = LY::C2 / 4 + (mt * 2 + ks) * 64 + lane;
+          c2[mt] = mma6(Wb[o], Wb[o + LY::PC2 / 4], Wb[o + LY::PC2 / 2], x0, x1, x2, c2[mt]);
+        }
       }
     }
 #pragma unroll
