@@ -101,6 +101,20 @@ mr_status mr_field_create(const mr_field_desc* desc, const float* host_table,
                           const float* host_mlp, void* stream, mr_field** out);
 mr_status mr_field_destroy(mr_field* f);
 
+/* The MLP weight fragments that mr_field_create stages for the matrix cores
+ * (host only: no device is touched).  desc/host_mlp as for mr_field_create
+ * (a radiance field).  bf16 != 0: the BF16 engine's fragments (one BF16
+ * piece per weight, round to nearest even); bf16 == 0: the FP32 engine's,
+ * each weight as three BF16 pieces w0 + w1 + w2 equal to it exactly, stored
+ * piece after piece per layer, followed by the FP32 output layer and the
+ * FP32 SH columns of colour layer 1.  *words receives the size in 32-bit
+ * words; out == NULL asks for the size only.  Otherwise out (host memory of
+ * capacity_words words) receives the fragments, or MR_ERR_INVALID_ARG when
+ * it is too small.  MR_ERR_UNSUPPORTED for a layout mr_field_create
+ * refuses. */
+mr_status mr_mlp_fragments(const mr_field_desc* desc, const float* host_mlp, int32_t bf16, uint32_t* out,
+                           int64_t capacity_words, int64_t* words);
+
 /* Evaluate the field at n points (device arrays).
  * x, dirs: (n, 3) in world coordinates (mapped into the field's frame when it
  * has a pose); sigma: (n); rgb: (n, 3) or NULL; feat: (n, n_levels*feats)

@@ -112,6 +112,22 @@ bool field_supported(const mr_field_desc& d, std::string& why) {
 
 }  // namespace mr
 
+extern "C" mr_status mr_mlp_fragments(const mr_field_desc* desc, const float* host_mlp, int32_t bf16,
+                                      uint32_t* out, int64_t capacity_words, int64_t* words) {
+  if (!desc || !host_mlp || !words) return fail(MR_ERR_INVALID_ARG, "null argument");
+  const mr_field_desc& d = *desc;
+  if (d.color_hidden_layers < 1) return fail(MR_ERR_INVALID_ARG, "a radiance field (colour layers >= 1) has fragments");
+  if (d.feats_per_level != 2) return fail(MR_ERR_UNSUPPORTED, "feats_per_level must be 2");
+  std::string why;
+  if (!field_supported(d, why)) return fail(MR_ERR_UNSUPPORTED, why);
+  const std::vector<uint32_t> fr = build_fragments(d, host_mlp, bf16 != 0);
+  *words = (int64_t)fr.size();
+  if (!out) return MR_OK;
+  if (capacity_words < (int64_t)fr.size()) return fail(MR_ERR_INVALID_ARG, "capacity below the fragment size");
+  std::memcpy(out, fr.data(), fr.size() * sizeof(uint32_t));
+  return MR_OK;
+}
+
 extern "C" mr_status mr_field_create(const mr_field_desc* desc, const float* host_table,
                                      const float* host_mlp, void* stream, mr_field** out) {
   if (!desc || !host_table || !host_mlp || !out) return fail(MR_ERR_INVALID_ARG, "null argument");

@@ -26,7 +26,7 @@ EXPORTED = [
     "mr_autotune_candidates", "mr_autotune_render", "mr_autotune_search", "mr_camera_bounce_limits", "mr_field_build_occupancy", "mr_field_create",
     "mr_field_destroy", "mr_field_params", "mr_field_query", "mr_field_set_pose", "mr_graph_destroy",
     "mr_graph_launch", "mr_last_error", "mr_mesh_build_bvh", "mr_mesh_closest_hit", "mr_mesh_destroy",
-    "mr_mesh_info", "mr_mesh_refit", "mr_probe_gather", "mr_probe_gather_region", "mr_profile_enable", "mr_profile_read",
+    "mr_mesh_info", "mr_mesh_refit", "mr_probe_gather", "mr_probe_gather_region", "mr_mlp_fragments", "mr_profile_enable", "mr_profile_read",
     "mr_proposal_grad", "mr_proposal_targets", "mr_proposal_train_step", "mr_rays_from_cameras", "mr_render",
     "mr_render_fields", "mr_render_fields_workspace_size", "mr_render_graph_create",
     "mr_render_noalloc", "mr_render_status",
@@ -270,25 +270,48 @@ def mr_rays_from_cameras(host_cams, origins, dirs, cam_index=None, capacity=None
 # owners of handles (allocation and bookkeeping only)
 # ---------------------------------------------------------------------------
 
+def field_desc(f, table_dtype=MR_F32, mlp_dtype=MR_F32):
+    """The mr_field_desc of a parameter set; returns (desc, resolutions array
+    the desc points into, to be kept alive with it)."""
+    d = FieldDesc()
+    res = np.ascontiguousarray(f.resolutions, dtype=np.int32)
+    d.n_levels, d.feats_per_level, d.log2_table_size = f.n_levels, f.feats, f.log2_table
+    d.host_resolutions = res.ctypes.data
+    d.table_dtype, d.mlp_dtype = table_dtype, mlp_dtype
+    if hasattr(f, "d_hidden"):
+        d.density_in, d.density_hidden, d.density_out = f.d_in, f.d_hidden, f.d_out
+        d.color_in, d.color_hidden = f.c_in, f.c_hidden
+        d.color_hidden_layers, d.sh_components = f.c_layers, f.sh
+    else:
+        d.density_in, d.density_hidden, d.density_out = f.n_levels * f.feats, f.hidden, 1
+    d.density_offset = float(f.density_offset)
+    d.aabb_min = (C.c_float * 3)(*f.aabb_min)
+    d.aabb_max = (C.c_float * 3)(*f.aabb_max)
+    return d, res
+
+
+def mr_mlp_fragments(f, bf16):
+    """The MLP weight fragments mr_field_create stages for a radiance field
+    (host only, no device): uint32 words, FP32 weights as three BF16 pieces
+    (bf16 False) or one BF16 piece (bf16 True)."""
+    d, res = field_desc(f, MR_F32, MR_BF16 if bf16 else MR_F32)
+    mlp = np.ascontiguousarray(f.mlp, dtype=np.float32)
+    words = C.c_int64()
+    _check(lib().mr_mlp_fragments(C.byref(d), _ptr(mlp), C.c_int32(1 if bf16 else 0), None, C.c_int64(0),
+                                  C.byref(words)))
+    out = np.zeros(words.value, dtype=np.uint32)
+    _check(lib().mr_mlp_fragments(C.byref(d), _ptr(mlp), C.c_int32(1 if bf16 else 0), _ptr(out),
+                                  C.c_int64(out.size), C.byref(words)))
+    del res
+    return out
+
+
 class Field:
     """A field handle created from a seeded parameter set (scene generator
     objects or anything with the same attributes)."""
 
     def __init__(self, f, table_dtype=MR_F32, mlp_dtype=MR_F32, stream=None):
-        d = FieldDesc()
-        self._res = np.ascontiguousarray(f.resolutions, dtype=np.int32)
-        d.n_levels, d.feats_per_level, d.log2_table_size = f.n_levels, f.feats, f.log2_table
-        d.host_resolutions = self._res.ctypes.data
-        d.table_dtype, d.mlp_dtype = table_dtype, mlp_dtype
-        if hasattr(f, "d_hidden"):
-            d.density_in, d.density_hidden, d.density_out = f.d_in, f.d_hidden, f.d_out
-            d.color_in, d.color_hidden = f.c_in, f.c_hidden
-            d.color_hidden_layers, d.sh_components = f.c_layers, f.sh
-        else:
-            d.density_in, d.density_hidden, d.density_out = f.n_levels * f.feats, f.hidden, 1
-        d.density_offset = float(f.density_offset)
-        d.aabb_min = (C.c_float * 3)(*f.aabb_min)
-        d.aabb_max = (C.c_float * 3)(*f.aabb_max)
+        d, self._res = field_desc(f, table_dtype, mlp_dtype)
         self.desc = d
         self.src = f
         self.handle = mr_field_create(d, np.ascontiguousarray(f.table, dtype=np.float32),
