@@ -272,8 +272,17 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Waves per SIMD of the packet march: three where the registers allow it
+// without spilling (FP16 tables, BF16 MLPs, no shadow mask: 168 registers,
+// and 47 KB of LDS lets three blocks share a compute unit), two elsewhere.
+// The camera segment of the mid frame took 3.59 ms at two and 3.00 at three.
+template <typename TabT, bool BF, typename PTabT, bool SHADOW>
+constexpr int prop_pk_waves() {
+  return (sizeof(TabT) == 2 && BF && sizeof(PTabT) == 2 && !SHADOW) ? 3 : 2;
+}
+
 template <int NL, int SH, int CL, typename TabT, bool BF, typename PTabT, bool SHADOW>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_march_prop_pk(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(prop_pk_waves<TabT, BF, PTabT, SHADOW>()))) void k_march_prop_pk(
     RayQueue q, const int* __restrict__ count, int* __restrict__ work, FieldView F, const TabT* __restrict__ table,
     const uint32_t* __restrict__ frags, FieldView Pf, const PTabT* __restrict__ ptable, MarchParams P, BvhView B,
     int n_fine, unsigned long long* __restrict__ stats) {
