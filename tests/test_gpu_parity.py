@@ -232,6 +232,29 @@ def test_field_query_matches_oracle(kind, amp):
     assert_close_rel(host(out["rgb"]), ref["rgb"], 1e-4, 1e-7, "rgb")
 
 
+@pytest.mark.parametrize("k", [-20, 20])
+def test_fp32_engine_scales_exactly_with_power_of_two_weights(k):
+    """The FP32 engine holds weights and layer inputs as exact BF16 splits.
+    Scaling the density layer-1 weights by 2^k scales every piece, product and
+    FP32 partial sum by 2^k, and ReLU and the second layer are positively
+    homogeneous, so the raw density outputs scale by exactly 2^k (bit for
+    bit), and at 2^k they still match the FP64 oracle at the FP32 tolerance
+    (raw outputs 1e-4 relative + 1e-5 of their range)."""
+    M = mr()
+    f = sg.mid_field(table_amp=1.0)
+    x, d = lattice_points(f, 4000, seed=131)
+    base = M.Field(f).query(dev(x), dev(d), want_feat=False, want_raw=True)
+    mlp = f.mlp.astype(np.float32).copy()
+    mlp[:64 * f.d_in] *= np.float32(2.0 ** k)
+    f2 = copy.copy(f)
+    f2.mlp = mlp
+    out = M.Field(f2).query(dev(x), dev(d), want_feat=False, want_raw=True)
+    np.testing.assert_array_equal(host(out["raw"]), host(base["raw"]) * np.float32(2.0 ** k))
+    ref = orc.field_batch(f2, x, d)
+    raw_scale = np.abs(ref["raw"]).max()
+    assert_close_rel(host(out["raw"]), ref["raw"], 1e-4, 1e-5 * raw_scale, f"raw density outputs at 2^{k}")
+
+
 @pytest.mark.parametrize("offset", [-9.0, -5.0, 5.0])
 def test_field_query_sigma_over_the_softplus_range(offset):
     """Amplitude-1 tiny field with its density offset moved so that sigma
