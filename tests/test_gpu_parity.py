@@ -255,6 +255,34 @@ def test_fp32_engine_scales_exactly_with_power_of_two_weights(k):
     assert_close_rel(host(out["raw"]), ref["raw"], 1e-4, 1e-5 * raw_scale, f"raw density outputs at 2^{k}")
 
 
+def test_largest_table_query_and_render_match_oracle():
+    """The largest table mr_field_create accepts: 2^24 entries per level and
+    16 levels, 2 GiB of FP32, so byte offsets into it pass 2^31.  Features,
+    raw outputs, sigma and rgb on lattice points (tolerances as in
+    test_field_query_matches_oracle; a wrong index would move a feature by
+    the table amplitude), and a 24x20 render of the mid scene with that field
+    against the FP64 oracle."""
+    M = mr()
+    f = sg.make_field(n_levels=16, feats=2, log2_table=24, n_min=16, n_max=2048, d_hidden=64, d_out=16,
+                      c_hidden=64, c_layers=2, sh=16, seed=9, table_amp=1e-4)
+    assert f.table.nbytes == 2 << 30
+    x, d = lattice_points(f, 4000, seed=141)
+    F = M.Field(f)
+    out = F.query(dev(x), dev(d), want_feat=True, want_raw=True)
+    ref = orc.field_batch(f, x, d)
+    assert_close_rel(host(out["feat"]), ref["feat"], 1e-5, 16 * U32 * 1e-4, "features")
+    raw_scale = np.abs(ref["raw"]).max()
+    assert_close_rel(host(out["raw"]), ref["raw"], 1e-4, 1e-5 * raw_scale, "raw density outputs")
+    assert_close_rel(host(out["sigma"]), ref["sigma"], 2e-5, 1e-7, "sigma")
+    assert_close_rel(host(out["rgb"]), ref["rgb"], 1e-4, 1e-7, "rgb")
+    sc = sg.mid_scene(width=24, height=20)
+    sc.field = f
+    o, dd = oracle_camera_rays(sc)
+    r = orc.render(sc, o, dd)
+    g = gpu_render(sc, o, dd, field=F)
+    compare_render(g, r, "mid 24x20, 2^24-entry table")
+
+
 @pytest.mark.parametrize("offset", [-9.0, -5.0, 5.0])
 def test_field_query_sigma_over_the_softplus_range(offset):
     """Amplitude-1 tiny field with its density offset moved so that sigma
