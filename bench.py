@@ -822,6 +822,8 @@ def main():
     ap.add_argument("--cloth-frames", type=int, default=100)
     ap.add_argument("--segment-samples", action="store_true",
                     help="print the headline render's field samples per bounce segment and exit")
+    ap.add_argument("--proposal-only", action="store_true",
+                    help="only the proposal + FP16/BF16 frame (for profiler passes)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference dispatch for memory counters)")
     args = ap.parse_args()
@@ -861,6 +863,14 @@ def main():
             torch.cuda.synchronize()
             cum.append(int(Rs.counters.cpu().numpy()[0]))
         print(json.dumps({"samples_per_segment": [cum[0]] + [cum[i] - cum[i - 1] for i in range(1, len(cum))]}))
+        return
+    if args.proposal_only:
+        # the proposal + FP16/BF16 frame alone (with its training), for counter passes
+        step()
+        torch.cuda.synchronize()
+        out = proposal_variant(M, sg, sc, F, G, cams, n, R.radiance.cpu().numpy(), args.steps, args.warmup,
+                               args.train_steps)
+        print(json.dumps({"proposal_fp16": out}))
         return
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
