@@ -25,36 +25,48 @@ using namespace mr;
 
 namespace {
 
-// One ray per wave: lane j takes sample kb + j of each 16-sample tile, and
-// transmittance is a 16-lane prefix product carried from tile to tile.
+// A ray's segment in the field: origin and direction in the field frame,
+// the range [lo, hi] it marches and the sample indices k0 .. k1 that cover it.
+struct RaySeg {
+  float ox, oy, oz, dx, dy, dz, t_a, lo, hi;
+  int k0, k1;
+};
+
+__device__ __forceinline__ bool ray_seg(const RayQueue& q, int r, const FieldView& F, const MarchParams& P,
+                                        RaySeg& S) {
+  S.ox = q.ox[r]; S.oy = q.oy[r]; S.oz = q.oz[r];
+  S.dx = q.dx[r]; S.dy = q.dy[r]; S.dz = q.dz[r];
+  to_field_frame(F, S.ox, S.oy, S.oz, S.dx, S.dy, S.dz);
+  S.t_a = (q.depth[r] & 0xFFFF) == 0 ? P.t_near : 0.0f;
+  float box0, box1;
+  if (!slab_box(F, S.ox, S.oy, S.oz, S.dx, S.dy, S.dz, box0, box1)) return false;
+  S.lo = fmaxf(S.t_a, box0);
+  S.hi = fminf(fminf(S.t_a + P.span, q.hit_t[r]), box1);
+  if (!(S.hi > S.lo)) return false;
+  S.k0 = max(0, (int)floorf((S.lo - S.t_a) / P.delta) - 1);
+  S.k1 = min(P.n_samples, (int)ceilf((S.hi - S.t_a) / P.delta) + 1);
+  return true;
+}
+
+// Samples kb0 .. kb1 - 1 of the segment, one wave: lane j takes sample kb + j
+// of each 16-sample tile, and transmittance is a 16-lane prefix product
+// carried from tile to tile in Tseg (radiance in acc, both per wave).
 template <int NL, int SH, int CL, typename TabT, bool BF, bool SHADOW>
-__device__ __forceinline__ void march_ray(const RayQueue& q, int r, const FieldView& F, const TabT* __restrict__ table,
-                                          const uint32_t* __restrict__ sW, const MarchParams& P, const BvhView& B,
-                                          int* sstack, bool use_occ, int lane, unsigned long long& nsamp) {
+__device__ __forceinline__ void march_tiles(const RaySeg& S, int kb0, int kb1, const FieldView& F,
+                                            const TabT* __restrict__ table, const uint32_t* __restrict__ sW,
+                                            const MarchParams& P, const BvhView& B, int* sstack, bool use_occ,
+                                            int lane, const float (&u)[4][4], float& Tseg, float& acc0, float& acc1,
+                                            float& acc2, unsigned long long& nsamp) {
   using LY = FragLayout<NL, SH, CL, BF>;
   const int g = lane >> 4, j = lane & 15;
   const float delta = P.delta;
-  float ox = q.ox[r], oy = q.oy[r], oz = q.oz[r];
-  float dx = q.dx[r], dy = q.dy[r], dz = q.dz[r];
-  to_field_frame(F, ox, oy, oz, dx, dy, dz);
-  const float t_a = (q.depth[r] & 0xFFFF) == 0 ? P.t_near : 0.0f;
-  float box0, box1;
-  if (!slab_box(F, ox, oy, oz, dx, dy, dz, box0, box1)) return;
-  const float lo = fmaxf(t_a, box0);
-  const float hi = fminf(fminf(t_a + P.span, q.hit_t[r]), box1);
-  if (!(hi > lo)) return;
-  const int k0 = max(0, (int)floorf((lo - t_a) / delta) - 1);
-  const int k1 = min(P.n_samples, (int)ceilf((hi - t_a) / delta) + 1);
-  float u[4][4];
-  sh_rows<NL, SH, CL, BF>(sW, dx, dy, dz, lane, u);
-  float Tseg = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
-  for (int kb = k0; kb < k1; kb += 16) {
+  for (int kb = kb0; kb < kb1; kb += 16) {
     const int k = kb + j;
-    const float a = fmaxf(t_a + (float)k * delta, lo);
-    const float b = fminf(t_a + (float)(k + 1) * delta, hi);
-    bool valid = k < k1 && b > a;
+    const float a = fmaxf(S.t_a + (float)k * delta, S.lo);
+    const float b = fminf(S.t_a + (float)(k + 1) * delta, S.hi);
+    bool valid = k < kb1 && b > a;
     const float tm = 0.5f * (a + b), D = b - a;
-    const float px = ox + tm * dx, py = oy + tm * dy, pz = oz + tm * dz;
+    const float px = S.ox + tm * S.dx, py = S.oy + tm * S.dy, pz = S.oz + tm * S.dz;
     if (valid && use_occ) valid = occ_lookup(F, px, py, pz);
     if (__ballot(valid) == 0ull) continue;
     float fe[LY::NF];
@@ -75,18 +87,79 @@ __device__ __forceinline__ void march_ray(const RayQueue& q, int r, const FieldV
     Tseg *= __shfl(incl, 15, 16);
     if (g == 0 && valid) ++nsamp;
   }
+}
+
+__device__ __forceinline__ void ray_update(const RayQueue& q, int r, float T, float l0, float l1, float l2) {
+  const float tr = q.tr[r], tg = q.tg[r], tb = q.tb[r];
+  q.lr[r] += tr * l0;
+  q.lg[r] += tg * l1;
+  q.lb[r] += tb * l2;
+  q.tr[r] = tr * T;
+  q.tg[r] = tg * T;
+  q.tb[r] = tb * T;
+}
+
+// One ray per wave, all of its tiles in order.
+template <int NL, int SH, int CL, typename TabT, bool BF, bool SHADOW>
+__device__ __forceinline__ void march_ray(const RayQueue& q, int r, const FieldView& F, const TabT* __restrict__ table,
+                                          const uint32_t* __restrict__ sW, const MarchParams& P, const BvhView& B,
+                                          int* sstack, bool use_occ, int lane, unsigned long long& nsamp) {
+  RaySeg S;
+  if (!ray_seg(q, r, F, P, S)) return;
+  float u[4][4];
+  sh_rows<NL, SH, CL, BF>(sW, S.dx, S.dy, S.dz, lane, u);
+  float Tseg = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
+  march_tiles<NL, SH, CL, TabT, BF, SHADOW>(S, S.k0, S.k1, F, table, sW, P, B, sstack, use_occ, lane, u, Tseg, acc0,
+                                            acc1, acc2, nsamp);
+  acc0 = sum16(acc0);
+  acc1 = sum16(acc1);
+  acc2 = sum16(acc2);
+  if (lane == 0) ray_update(q, r, Tseg, acc0, acc1, acc2);
+}
+
+// Short queues: one ray per block of four waves, each wave marching a
+// contiguous quarter of the ray's tiles from transmittance 1; the quarters are
+// chained in order at the end (L = L0 + T0 L1 + T0 T1 L2 + ..., T = T0 T1 T2
+// T3).  Then the longest ray no longer sets the launch's duration alone.  The
+// same samples and arithmetic up to the association of the transmittance
+// products (a few ulp).
+template <int NL, int SH, int CL, typename TabT, bool BF>
+__device__ __forceinline__ void march_ray_split(const RayQueue& q, int r, const FieldView& F,
+                                                const TabT* __restrict__ table, const uint32_t* __restrict__ sW,
+                                                const MarchParams& P, const BvhView& B, bool use_occ, int lane,
+                                                int wave, float (*part)[4], unsigned long long& nsamp) {
+  RaySeg S;
+  const bool live = ray_seg(q, r, F, P, S);   // the same for the whole block
+  float Tseg = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
+  if (live) {
+    float u[4][4];
+    sh_rows<NL, SH, CL, BF>(sW, S.dx, S.dy, S.dz, lane, u);
+    const int ntiles = (S.k1 - S.k0 + 15) / 16, per = (ntiles + 3) / 4;
+    const int kb0 = S.k0 + 16 * per * wave, kb1 = min(S.k1, S.k0 + 16 * per * (wave + 1));
+    march_tiles<NL, SH, CL, TabT, BF, false>(S, kb0, kb1, F, table, sW, P, B, nullptr, use_occ, lane, u, Tseg, acc0,
+                                             acc1, acc2, nsamp);
+  }
   acc0 = sum16(acc0);
   acc1 = sum16(acc1);
   acc2 = sum16(acc2);
   if (lane == 0) {
-    const float tr = q.tr[r], tg = q.tg[r], tb = q.tb[r];
-    q.lr[r] += tr * acc0;
-    q.lg[r] += tg * acc1;
-    q.lb[r] += tb * acc2;
-    q.tr[r] = tr * Tseg;
-    q.tg[r] = tg * Tseg;
-    q.tb[r] = tb * Tseg;
+    part[wave][0] = Tseg;
+    part[wave][1] = acc0;
+    part[wave][2] = acc1;
+    part[wave][3] = acc2;
   }
+  __syncthreads();
+  if (live && threadIdx.x == 0) {
+    float T = 1.0f, l0 = 0.0f, l1 = 0.0f, l2 = 0.0f;
+    for (int w = 0; w < 4; ++w) {
+      l0 += T * part[w][1];
+      l1 += T * part[w][2];
+      l2 += T * part[w][3];
+      T *= part[w][0];
+    }
+    ray_update(q, r, T, l0, l1, l2);
+  }
+  __syncthreads();
 }
 
 // Column j's ray of a 16-ray packet (every lane group holds the same 16).
@@ -187,6 +260,10 @@ __device__ __forceinline__ void march_packet(const RayQueue& q, const PacketRay&
 // PK: 16-ray packets (march_packet), else one ray per wave (march_ray).
 // SHADOW: the shadow mask per field sample (instances without it carry none
 // of its code or registers).
+// At most this many rays per block: the per-ray march splits each ray over
+// the four waves of a block instead of taking one ray per wave.
+constexpr int kSplitRaysPerBlock = 8;
+
 template <int NL, int SH, int CL, typename TabT, bool BF, bool PK, bool SHADOW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_march_mfma(
     RayQueue q, const int* __restrict__ count, int* __restrict__ work, FieldView F, const TabT* __restrict__ table,
@@ -201,14 +278,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const bool use_occ = P.use_occupancy && F.occ;
   int* stack = sstack + (threadIdx.x >> 6) * 16 * kStack + j;
   unsigned long long nsamp = 0;
+  bool cnt_done = false;   // the short-queue path marched every ray
+  if constexpr (!PK && !SHADOW) {
+    if (cnt <= kSplitRaysPerBlock * (int)gridDim.x) {
+      __shared__ float part[4][4];
+      for (int r = blockIdx.x; r < cnt; r += gridDim.x)
+        march_ray_split<NL, SH, CL, TabT, BF>(q, r, F, table, sW, P, B, use_occ, lane, threadIdx.x >> 6, part, nsamp);
+      cnt_done = true;
+    }
+  }
   if constexpr (!PK) {
-    WorkQueue wq(work, cnt, P.chunk, P.batch);
-    for (int base = wq.next(lane); base >= 0; base = wq.next(lane))
-      for (int bi = 0; bi < wq.batch; ++bi) {
-        const int r = wq.map(base + bi);
-        if (r >= cnt) break;
-        march_ray<NL, SH, CL, TabT, BF, SHADOW>(q, r, F, table, sW, P, B, stack, use_occ, lane, nsamp);
-      }
+    if (!cnt_done) {
+      WorkQueue wq(work, cnt, P.chunk, P.batch);
+      for (int base = wq.next(lane); base >= 0; base = wq.next(lane))
+        for (int bi = 0; bi < wq.batch; ++bi) {
+          const int r = wq.map(base + bi);
+          if (r >= cnt) break;
+          march_ray<NL, SH, CL, TabT, BF, SHADOW>(q, r, F, table, sW, P, B, stack, use_occ, lane, nsamp);
+        }
+    }
   } else {
     WorkQueue wq(work, cnt, P.chunk, 16);
     for (int base = wq.next(lane); base >= 0; base = wq.next(lane)) {
