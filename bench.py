@@ -872,12 +872,38 @@ def main():
                                args.train_steps)
         print(json.dumps({"proposal_fp16": out}))
         return
+    # launch shape (march and stage blocks per CU, stage tile, queue chunk and
+    # batch, packet segments) from the library's autotuner, cached per
+    # architecture and workload; the search runs outside every timed region
+    opts_default = opts
+    key = M.autotune_key("mid", sc.field.resolutions.tobytes(), len(sc.mesh.indices), sc.n_samples, n,
+                         sc.max_bounces, cams.tobytes(), sc.occupancy_res)
+    cache = os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")), "meshrf_autotune.json")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    search = {}
+
+    def tune():
+        t_s = time.perf_counter()
+        M.mr_rays_from_cameras(cams, o, d, None, n)
+        shape, ms, ms0, nt = M.mr_autotune_search(F.handle, G.handle, n, o, d, sc.max_bounces, None, sc.lights,
+                                                  opts_default, R.out, R.workspace, R.ws_bytes, reps=2, passes=2)
+        search.update({"shapes_timed": nt, "search_s": round(time.perf_counter() - t_s, 2),
+                       "default_ms_in_search": round(ms0, 3), "tuned_ms_in_search": round(ms, 3)})
+        return shape, ms
+    shape, _, hit = M.autotune_cached(cache, key, tune)
+    opts = M.apply_launch(M.make_opts(sc, use_occupancy=True), shape)
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    # the library's default shape, for comparison (before the timed and
+    # profiled passes of the tuned shape)
+    def step_default():
+        M.mr_rays_from_cameras(cams, o, d, None, n)
+        R.render(F, G, o, d, sc.lights, opts_default)
+    ms_default = timed(step_default, args.steps, args.warmup)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -920,6 +946,11 @@ def main():
     # random single-entry loads from this table (every load a line lookup, eight
     # independent ones per lane): the rate at which the memory side serves
     # incoherent 128-byte lines, the ceiling of a march whose gathers share no line
+    names = ("march_blocks_per_cu", "stage_blocks_per_cu", "stage_tile", "march_chunk", "march_batch",
+             "march_packets")
+    launch = {"shape": dict(zip(names, shape)), "autotuned": True, "cache_hit": hit, "key": key, **search,
+              "default_shape": {"value": round(n / (ms_default / 1e3), 1), "unit": "rays/s",
+                                "ms_per_step": round(ms_default, 3)}}
     probe = gather_probe(M, sg, F)
     line_ceiling = probe["mid_fp32_64MiB"]["Gloads_per_s"]
 
@@ -955,6 +986,7 @@ def main():
                    "precision": "fp32 (MLP products on FP32 values split into three exact BF16 pieces, FP32 "
                                 "accumulation; error against the FP64 oracle in error_vs_fp64_oracle)"},
         "segments_per_s": round(segments / (ms_step / 1e3), 1),
+        "launch_shape": launch,
         "stage_ms_per_step": {"closest_hit": round(stage_ms[0] / args.steps, 3),
                               "march": round(march_ms_per_step, 3),
                               "shade": round(stage_ms[2] / args.steps, 3),
