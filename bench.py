@@ -169,13 +169,40 @@ def proposal_variant(M, sg, sc, F_plain, G, cams, n, plain_img, steps, warmup, t
     o = torch.empty(n, 3, device="cuda")
     d = torch.empty(n, 3, device="cuda")
     R = M.Renderer(n, sc.max_bounces, with_hits=False)
-    opts = M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P, use_occupancy=True)
+    opts_default = M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P, use_occupancy=True)
+    # launch shape from the library's autotuner, as for the plain frame
+    key = M.autotune_key("mid-proposal", sc.field.resolutions.tobytes(), len(sc.mesh.indices), n, sc.max_bounces,
+                         cams.tobytes(), sc.occupancy_res)
+    cache = os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")), "meshrf_autotune.json")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    search = {}
+
+    def tune():
+        t_s = time.perf_counter()
+        M.mr_rays_from_cameras(cams, o, d, None, n)
+        shape, tms, ms0, nt = M.mr_autotune_search(F16.handle, G.handle, n, o, d, sc.max_bounces, None, sc.lights,
+                                                   opts_default, R.out, R.workspace, R.ws_bytes, reps=2, passes=2)
+        search.update({"shapes_timed": nt, "search_s": round(time.perf_counter() - t_s, 2),
+                       "default_ms_in_search": round(ms0, 3), "tuned_ms_in_search": round(tms, 3)})
+        return shape, tms
+    shape, _, hit = M.autotune_cached(cache, key, tune)
+    opts = M.apply_launch(M.make_opts(sc, sampler=M.MR_SAMPLER_PROPOSAL, proposal=P, use_occupancy=True), shape)
+
+    def step_default():
+        M.mr_rays_from_cameras(cams, o, d, None, n)
+        R.render(F16, G, o, d, sc.lights, opts_default)
+    ms_default = timed(step_default, steps, warmup)
 
     def step():
         M.mr_rays_from_cameras(cams, o, d, None, n)
         R.render(F16, G, o, d, sc.lights, opts)
     ms = timed(step, steps, warmup)
     img = R.radiance.cpu().numpy()
+    names = ("march_blocks_per_cu", "stage_blocks_per_cu", "stage_tile", "march_chunk", "march_batch",
+             "march_packets")
+    launch = {"shape": dict(zip(names, shape)), "autotuned": True, "cache_hit": hit, **search,
+              "default_shape": {"value": round(n / (ms_default / 1e3), 1), "unit": "rays/s",
+                                "ms_per_step": round(ms_default, 3)}}
     stage_ms, stage_n, counters = profiled(M, step, steps, R)
     fine = int(counters[0])
     prop = fine                             # 32 proposal intervals and 32 fine samples per marched segment
@@ -215,6 +242,7 @@ def proposal_variant(M, sg, sc, F_plain, G, cams, n, plain_img, steps, warmup, t
         R.render(F16, G, o, d, sc.lights, opts_sh)
     ms_sh = timed(step_sh, steps, 1)
     return {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms, 3),
+            "launch_shape": launch,
             "with_sample_shadows": {"value": round(n / (ms_sh / 1e3), 1), "unit": "rays/s",
                                     "ms_per_step": round(ms_sh, 3), "mask": 0.2},
             "psnr_db_vs_plain_fp32": round(psnr_tonemapped(img, plain_img), 2),
