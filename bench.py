@@ -390,7 +390,12 @@ def precision_report(M, sg):
     return out
 
 
-def moving_field(M, sg, sc, F, G, cams, n, steps):
+def tuned(M, opts, shape):
+    """The plain mid frame's autotuned launch shape on a variant of that frame."""
+    return M.apply_launch(opts, shape) if shape is not None else opts
+
+
+def moving_field(M, sg, sc, F, G, cams, n, steps, shape=None):
     """The mid workload with the field as a moving object: a different rigid
     placement (turning about y, drifting along x) on every step, set with
     mr_field_set_pose between renders."""
@@ -398,7 +403,7 @@ def moving_field(M, sg, sc, F, G, cams, n, steps):
     o = torch.empty(n, 3, device="cuda")
     d = torch.empty(n, 3, device="cuda")
     R = M.Renderer(n, sc.max_bounces, with_hits=False)
-    opts = M.make_opts(sc, use_occupancy=True)
+    opts = tuned(M, M.make_opts(sc, use_occupancy=True), shape)
     poses = [sg.pose_matrix(sg.rotation((0.0, 1.0, 0.0), 0.05 * k), (0.02 * k, 0.0, 0.0)) for k in range(16)]
     state = {"k": 0}
 
@@ -412,17 +417,18 @@ def moving_field(M, sg, sc, F, G, cams, n, steps):
     finally:
         F.set_pose(None)
     return {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms, 3),
-            "motion": "turn 0.05 rad about y and move 0.02 along x per step"}
+            "motion": "turn 0.05 rad about y and move 0.02 along x per step",
+            "launch_shape": "the plain mid frame's autotuned shape" if shape is not None else "default"}
 
 
-def sample_shadows(M, sg, sc, F, G, cams, n, steps, mask=0.2):
+def sample_shadows(M, sg, sc, F, G, cams, n, steps, mask=0.2, shape=None):
     """The mid workload with the paper's per-sample shadow mask: every field
     sample sends a ray to the light (one any-hit traversal per sample)."""
     import torch
     o = torch.empty(n, 3, device="cuda")
     d = torch.empty(n, 3, device="cuda")
     R = M.Renderer(n, sc.max_bounces, with_hits=False)
-    opts = M.make_opts(sc, use_occupancy=True, shadow_mask=mask)
+    opts = tuned(M, M.make_opts(sc, use_occupancy=True, shadow_mask=mask), shape)
 
     def step():
         M.mr_rays_from_cameras(cams, o, d, None, n)
@@ -430,7 +436,8 @@ def sample_shadows(M, sg, sc, F, G, cams, n, steps, mask=0.2):
     ms = timed(step, steps, 1)
     c = R.counters.cpu().numpy()
     return {"value": round(n / (ms / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms, 3),
-            "shadow_rays_per_s": round(int(c[0]) * len(sc.lights) / (ms / 1e3), 1), "mask": mask}
+            "shadow_rays_per_s": round(int(c[0]) * len(sc.lights) / (ms / 1e3), 1), "mask": mask,
+            "launch_shape": "the plain mid frame's autotuned shape" if shape is not None else "default"}
 
 
 def scaling(M, sg, steps):
@@ -473,7 +480,7 @@ def scaling(M, sg, steps):
     return out
 
 
-def emitters(M, sg, steps):
+def emitters(M, sg, steps, shape=None):
     """The mid workload with an emitting ceiling panel (Eq. 12 L_e) next to the
     point light: 800x800, 8 bounces, plain FP32."""
     import torch
@@ -485,7 +492,7 @@ def emitters(M, sg, steps):
     o = torch.empty(n, 3, device="cuda")
     d = torch.empty(n, 3, device="cuda")
     R = M.Renderer(n, sc.max_bounces, with_hits=False)
-    opts = M.make_opts(sc, use_occupancy=True)
+    opts = tuned(M, M.make_opts(sc, use_occupancy=True), shape)
 
     def step():
         M.mr_rays_from_cameras(cams, o, d, None, n)
@@ -493,7 +500,7 @@ def emitters(M, sg, steps):
     ms = timed(step, steps, 1)
     mean = [round(float(x), 5) for x in R.radiance.mean(0).cpu().numpy()]
     # light sampling toward the panel's triangles at every diffuse hit
-    opts_ls = M.make_opts(sc, use_occupancy=True, sample_emitters=True)
+    opts_ls = tuned(M, M.make_opts(sc, use_occupancy=True, sample_emitters=True), shape)
 
     def step_ls():
         M.mr_rays_from_cameras(cams, o, d, None, n)
@@ -501,7 +508,7 @@ def emitters(M, sg, steps):
     ms_ls = timed(step_ls, steps, 1)
     mean_ls = [round(float(x), 5) for x in R.radiance.mean(0).cpu().numpy()]
     # the same with the light samples' optical depth on a coarse grid (32 intervals per segment length)
-    opts_c = M.make_opts(sc, use_occupancy=True, sample_emitters=True, light_depth_samples=32)
+    opts_c = tuned(M, M.make_opts(sc, use_occupancy=True, sample_emitters=True, light_depth_samples=32), shape)
 
     def step_c():
         M.mr_rays_from_cameras(cams, o, d, None, n)
@@ -514,7 +521,8 @@ def emitters(M, sg, steps):
             "with_light_sampling_coarse_depth": {
                 "value": round(n / (ms_c / 1e3), 1), "unit": "rays/s", "ms_per_step": round(ms_c, 3),
                 "mean_radiance": [round(float(x), 5) for x in R.radiance.mean(0).cpu().numpy()],
-                "light_depth_grid": "32 intervals per segment length"}}
+                "light_depth_grid": "32 intervals per segment length"},
+            "launch_shape": "the plain mid frame's autotuned shape" if shape is not None else "default"}
 
 
 def several_fields(M, sg, steps, n_fields=3, train_steps=0):
@@ -1055,9 +1063,9 @@ def main():
         line["proposal_fp16"] = proposal_variant(M, sg, sc, F, G, cams, n, plain_img, args.steps, 1,
                                                  args.train_steps)
         line["shell_field_proposal_vs_uniform"] = shell_proposal(M, sg, args.steps, args.train_steps)
-        line["moving_field"] = moving_field(M, sg, sc, F, G, cams, n, args.steps)
-        line["sample_shadows"] = sample_shadows(M, sg, sc, F, G, cams, n, args.steps)
-        line["emitters"] = emitters(M, sg, args.steps)
+        line["moving_field"] = moving_field(M, sg, sc, F, G, cams, n, args.steps, shape=shape)
+        line["sample_shadows"] = sample_shadows(M, sg, sc, F, G, cams, n, args.steps, shape=shape)
+        line["emitters"] = emitters(M, sg, args.steps, shape=shape)
         line["several_fields"] = several_fields(M, sg, args.steps, train_steps=args.train_steps)
         line["multicam_16_cameras"] = multicam(M, sg, 2)
         line["scaling_spheres"] = scaling(M, sg, 3)
