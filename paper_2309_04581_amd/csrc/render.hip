@@ -1455,6 +1455,7 @@ void tune_axes(int64_t n, int cus, TuneAxis ax[kAxes]) {
   // (a chunk a few times a die's share of one grab round)
   add_value(ax[3], 0);
   add_value(ax[3], 1024);
+  add_value(ax[3], 4096);
   add_value(ax[3], 8192);
   // rays per march queue grab
   for (int v : {1, 2, 4, 8}) add_value(ax[4], v);
